@@ -1,0 +1,184 @@
+/*
+ * tjm.h - tensor jump method (TJM) on one MI355X GPU: C ABI.
+ *
+ * The library runs the per-trajectory TJM of arXiv:2501.17913 (Sec. "Tensor
+ * jump method"): a sampling MPS Phi evolved by the step functions
+ * F_0 = J D[dt/2], F_j = J D[dt] U[dt], and sampled through
+ * F_n = J D[dt/2] U[dt] (Eqs. TimeEvolutionFunctions, SimulationStep), with
+ *   U  dynamic TDVP (Sec. "Dynamic TDVP"),
+ *   D  the exact dissipative contraction (Eq. DissipativeMPO),
+ *   J  the stochastic jump process (Sec. "Stochastic jump process"),
+ * averaged over N trajectories (Eq. TJMExpVal).  Inputs follow the
+ * paper's list in Sec. "Algorithm / Initialization": the initial state, the
+ * Hamiltonian as an MPO, single-site jump operators with rates, dt, T,
+ * chi_max and N.
+ *
+ * Conventions
+ *  - Complex arrays are interleaved (re, im) doubles.
+ *  - An MPO site tensor is W_l[s_out][s_in][w_{l-1}][w_l] (Methods, MPO
+ *    section: O = sum W^{s,s'} |s><s'|); an operator matrix is op[s_out][s_in].
+ *  - The basis is (|0>, |1>); sites and jump/observable indices are 0-based.
+ *  - Every pointer argument is a HOST pointer.  The library copies all
+ *    inputs before returning; outputs are written into caller-allocated host
+ *    buffers.  A model handle owns its device memory until tjm_destroy.
+ *  - Functions return a tjm_status and never throw; tjm_last_error gives a
+ *    message for the last failing call on that handle.
+ *  - A model handle is not thread-safe.
+ *  - Only local dimension d = 2 is supported (TJM_E_UNSUPPORTED otherwise).
+ *
+ * Random numbers: each jump process draws two uniforms in [0,1) from
+ * Philox4x32-10 (Salmon et al., SC'11) with key (seed lo, seed hi) and
+ * counter (traj_base + trajectory, step, branch, 0); branch 0 is the jump
+ * process of the sampling MPS (step 0 = F_0), branch 1 the sampling layer.
+ * Results therefore do not depend on how trajectories are scheduled.
+ */
+#ifndef TJM_H
+#define TJM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tjm_model tjm_model;
+
+typedef enum {
+  TJM_OK = 0,
+  TJM_E_INVAL = 1,        /* invalid argument (message says which)            */
+  TJM_E_NOMEM = 2,        /* device or host allocation failed                 */
+  TJM_E_DEVICE = 3,       /* HIP runtime error / no usable GPU                */
+  TJM_E_NUMERIC = 4,      /* non-finite norm in some trajectory               */
+  TJM_E_UNSUPPORTED = 5,  /* valid request outside what is implemented        */
+  TJM_E_BUSY = 6          /* call out of order (e.g. advance without begin)   */
+} tjm_status;
+
+typedef enum {
+  TJM_PREC_FP64 = 0,      /* complex128 everywhere                            */
+  TJM_PREC_MIXED = 1      /* complex64 contractions on FP32 matrix cores with
+                             FP32 accumulation; MPS, Krylov basis,
+                             re-orthogonalisation, small exponentials,
+                             QR/SVD, jump probabilities and observables FP64 */
+} tjm_precision;
+
+typedef struct {
+  int precision;          /* tjm_precision, default TJM_PREC_FP64             */
+  int chi_cap;            /* hard bond cap of SVD truncation; <= 0 means
+                             chi_max; at most 64                              */
+  double svd_discard;     /* keep the smallest k with discarded weight
+                             sum_{i>=k} s_i^2 <= svd_discard * sum s_i^2;
+                             default 1e-12                                    */
+  int krylov_max;         /* Lanczos iterations per exponential, 1..32;
+                             default 30                                       */
+  double krylov_tol;      /* stop when beta_j |[exp(-itT)]_{j,0}| <= tol;
+                             <= 0 selects 1e-12 (FP64) or 1e-10 (mixed)       */
+  double deg_tol;         /* multiplet tolerance at the cap, default 1e-12    */
+  int workers;            /* resident workgroups; <= 0: automatic             */
+  int record_bonds;       /* 1: keep bond dimensions after every U[dt]        */
+  uint32_t traj_base;     /* global id of trajectory 0 of this run            */
+  int device;             /* HIP device ordinal                               */
+} tjm_options;
+
+typedef struct {
+  int n_traj, n_steps, steps_done, workers;
+  double init_kernel_ms;          /* duration of the F_0 launch               */
+  double step_kernel_ms_total;    /* sum of all step-kernel durations         */
+  double step_kernel_ms_last;     /* duration of the most recent step launch  */
+  int step_launches;              /* launches counted in the total            */
+  unsigned long long cmac_mfma;   /* complex MACs issued to matrix cores      */
+  unsigned long long cmac_mix;    /* complex MACs of the MPO mixing stage     */
+  unsigned long long krylov_iters, expm_calls;
+  unsigned long long one_site, two_site, factorizations, jumps;
+  size_t device_bytes;            /* device memory held by the run            */
+} tjm_stats;
+
+/* Fills *opt with the defaults listed above. */
+void tjm_default_options(tjm_options *opt);
+
+/*
+ * Creates a model: chain length L >= 1, local dimension d (must be 2), the
+ * Hamiltonian H0 as an MPO and the jump operators (Eq. Lindblad).
+ *   mpo_bond  L+1 MPO bond dimensions, mpo_bond[0] = mpo_bond[L] = 1, each
+ *             in 1..8
+ *   mpo       concatenation over l of W_l[d][d][mpo_bond[l]][mpo_bond[l+1]]
+ *             (complex); H0 must be Hermitian (not checked)
+ *   n_jump    number of jump operators (>= 0)
+ *   jump_site site of each jump operator (0..L-1)
+ *   jump_op   n_jump complex d x d matrices L_m^{[l]}[s_out][s_in]
+ *   rate      gamma_m, finite and >= 0
+ * The initial state defaults to |0...0>.
+ * Errors: TJM_E_INVAL (sizes, boundary bonds, sites, non-finite values,
+ * negative rates), TJM_E_UNSUPPORTED (d != 2).  On error *out is NULL.
+ */
+tjm_status tjm_create(tjm_model **out, int L, int d, const int *mpo_bond, const double *mpo,
+                      int n_jump, const int *jump_site, const double *jump_op, const double *rate);
+
+/*
+ * Sets the initial state Psi(0) to the product state with site vectors
+ * site_vec[l][s] (L x d complex); each must be nonzero and finite.  The state
+ * is normalised by the library.
+ */
+tjm_status tjm_set_initial_product(tjm_model *m, const double *site_vec);
+
+/*
+ * One whole run (Sec. "Algorithm"): N = n_traj trajectories from t = 0 to
+ * T = n dt (n = T/dt must be an integer within 1e-9), chi_max the bond
+ * dimension at which dynamic TDVP switches to 1TDVP, and single-site
+ * observables (obs_site[i], obs_op[i] complex d x d).  Outputs:
+ *   mean  [(n+1)][n_obs]  trajectory average of <Psi_i(t_k)|O|Psi_i(t_k)>
+ *                         (real part), t_k = k dt, k = 0..n (Eq. TJMExpVal)
+ *   sem   [(n+1)][n_obs]  standard error of that mean, or NULL
+ * opt may be NULL (defaults).  Errors: TJM_E_INVAL for bad arguments,
+ * TJM_E_NUMERIC if a trajectory's norm became non-finite, TJM_E_NOMEM /
+ * TJM_E_DEVICE from the GPU.
+ */
+tjm_status tjm_run(tjm_model *m, int n_traj, double dt, double T, int chi_max,
+                   int n_obs, const int *obs_site, const double *obs_op,
+                   uint64_t seed, const tjm_options *opt, double *mean, double *sem);
+
+/*
+ * As tjm_run, additionally returning per-trajectory records (each pointer may
+ * be NULL):
+ *   per_traj_obs [n_traj][n+1][n_obs]
+ *   jump_log     [n_traj][2n]: index m of the applied jump operator or -1,
+ *                in the order F_0, then (sampling layer k, main step k) for
+ *                k = 1..n (no main step at k = n)
+ *   bond_log     [n_traj][n][L+1]: bond dimensions after U[dt] of step k
+ *                (requires opt->record_bonds = 1)
+ */
+tjm_status tjm_run_traces(tjm_model *m, int n_traj, double dt, double T, int chi_max,
+                          int n_obs, const int *obs_site, const double *obs_op,
+                          uint64_t seed, const tjm_options *opt, double *mean, double *sem,
+                          double *per_traj_obs, int32_t *jump_log, int32_t *bond_log);
+
+/*
+ * The same run in three calls, so that a caller can time steps with all
+ * inputs resident on the GPU.  tjm_run_begin validates, uploads and applies
+ * F_0 to every trajectory (and measures t = 0); tjm_run_advance applies the
+ * next `steps` step functions to every trajectory (one kernel launch per
+ * step) and waits for them; tjm_run_end reduces and copies the outputs (any
+ * pointer may be NULL) and releases the run.  TJM_E_BUSY if called out of
+ * order or past step n.
+ */
+tjm_status tjm_run_begin(tjm_model *m, int n_traj, double dt, double T, int chi_max,
+                         int n_obs, const int *obs_site, const double *obs_op,
+                         uint64_t seed, const tjm_options *opt);
+tjm_status tjm_run_advance(tjm_model *m, int steps);
+tjm_status tjm_run_end(tjm_model *m, double *mean, double *sem, double *per_traj_obs,
+                       int32_t *jump_log, int32_t *bond_log);
+
+/* Kernel timings and algorithmic counters of the current or last run. */
+tjm_status tjm_get_stats(const tjm_model *m, tjm_stats *out);
+
+/* Message of the last failing call on m (m may be NULL: last create error). */
+const char *tjm_last_error(const tjm_model *m);
+
+/* Releases the model and any run it holds; NULL is ignored. */
+void tjm_destroy(tjm_model *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TJM_H */

@@ -1,0 +1,112 @@
+// Complex arithmetic, deterministic workgroup reductions and the
+// counter-based random stream used by the jump process.
+#pragma once
+#include <dev_platform.hpp>
+
+template <typename T> struct cplx { T re, im; };
+
+template <typename T> TJM_DEV cplx<T> cmk(T r, T i) { cplx<T> z; z.re = r; z.im = i; return z; }
+template <typename T> TJM_DEV cplx<T> operator+(cplx<T> a, cplx<T> b) { return cmk(a.re + b.re, a.im + b.im); }
+template <typename T> TJM_DEV cplx<T> operator-(cplx<T> a, cplx<T> b) { return cmk(a.re - b.re, a.im - b.im); }
+template <typename T> TJM_DEV cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T> TJM_DEV cplx<T> operator*(T s, cplx<T> a) { return cmk(s * a.re, s * a.im); }
+template <typename T> TJM_DEV cplx<T> conjg(cplx<T> a) { return cmk(a.re, -a.im); }
+template <typename T> TJM_DEV T abs2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+// conj(a) * b
+template <typename T> TJM_DEV cplx<T> cdotc(cplx<T> a, cplx<T> b) {
+  return cmk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T, typename S> TJM_DEV cplx<T> ccast(cplx<S> a) { return cmk((T)a.re, (T)a.im); }
+
+typedef cplx<double> zd;
+typedef cplx<float> zf;
+
+// LDS scratch every workgroup routine may use for reductions and broadcasts.
+struct BlkScratch {
+  double red[TJM_NWAVE * 4];
+  double bcast[8];
+  int ibcast[8];
+};
+
+// Sum of one double over the workgroup; every thread receives it.  The order
+// of additions is fixed (butterfly in each wavefront, then waves in order),
+// so the result does not depend on scheduling.
+TJM_DEV double blk_sum(double v, BlkScratch& S) {
+  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) v += tjm_shfl_xor(v, m);
+  if (tjm_lane() == 0) S.red[tjm_wave()] = v;
+  tjm_sync();
+  double s = 0.0;
+  for (int w = 0; w < TJM_NWAVE; ++w) s += S.red[w];
+  tjm_sync();
+  return s;
+}
+
+// Two (or up to four) simultaneous sums.
+TJM_DEV void blk_sum2(double& a, double& b, BlkScratch& S) {
+  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) { a += tjm_shfl_xor(a, m); b += tjm_shfl_xor(b, m); }
+  if (tjm_lane() == 0) { S.red[2 * tjm_wave()] = a; S.red[2 * tjm_wave() + 1] = b; }
+  tjm_sync();
+  double sa = 0.0, sb = 0.0;
+  for (int w = 0; w < TJM_NWAVE; ++w) { sa += S.red[2 * w]; sb += S.red[2 * w + 1]; }
+  tjm_sync();
+  a = sa; b = sb;
+}
+
+TJM_DEV void blk_sum4(double& a, double& b, double& c, double& d, BlkScratch& S) {
+  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) {
+    a += tjm_shfl_xor(a, m); b += tjm_shfl_xor(b, m);
+    c += tjm_shfl_xor(c, m); d += tjm_shfl_xor(d, m);
+  }
+  if (tjm_lane() == 0) {
+    S.red[4 * tjm_wave()] = a; S.red[4 * tjm_wave() + 1] = b;
+    S.red[4 * tjm_wave() + 2] = c; S.red[4 * tjm_wave() + 3] = d;
+  }
+  tjm_sync();
+  double sa = 0, sb = 0, sc = 0, sd = 0;
+  for (int w = 0; w < TJM_NWAVE; ++w) {
+    sa += S.red[4 * w]; sb += S.red[4 * w + 1]; sc += S.red[4 * w + 2]; sd += S.red[4 * w + 3];
+  }
+  tjm_sync();
+  a = sa; b = sb; c = sc; d = sd;
+}
+
+// Sum of v over groups of g consecutive lanes (g a power of two <= 64); all
+// lanes of the group receive the group's sum.
+TJM_DEV double grp_sum(double v, int g) {
+  for (int m = g / 2; m > 0; m >>= 1) v += tjm_shfl_xor(v, m);
+  return v;
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (c0,c1,c2,c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),
+// key bumped by the golden-ratio Weyl constants between rounds.
+// Stream layout of the jump process: key = (seed lo, seed hi), counter =
+// (trajectory, step, branch, 0); branch 0 = jump process of the sampling
+// MPS (step 0 is F_0), branch 1 = the sampling layer applied at that step.
+// --------------------------------------------------------------------------
+TJM_DEV void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint32_t hi0 = tjm_mulhi(M0, c[0]), lo0 = M0 * c[0];
+    uint32_t hi1 = tjm_mulhi(M1, c[2]), lo1 = M1 * c[2];
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+TJM_DEV double u53(uint32_t a, uint32_t b) {
+  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+TJM_DEV void tjm_draws(uint64_t seed, uint32_t traj, uint32_t step, uint32_t branch,
+                       double& eps, double& r) {
+  uint32_t c[4] = {traj, step, branch, 0u};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  eps = u53(c[0], c[1]);
+  r = u53(c[2], c[3]);
+}

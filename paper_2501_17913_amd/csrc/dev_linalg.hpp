@@ -1,0 +1,433 @@
+// FP64 workgroup factorisations and the Lanczos matrix exponential.
+//
+//   blk_qr        Householder QR of an m x n complex matrix, explicit thin Q,
+//                 R with a real non-negative diagonal.
+//   blk_svd       one-sided (Hestenes) Jacobi SVD with the truncation rule of
+//                 the sweep code; singular values to high relative accuracy.
+//   blk_expm      exp(-i t H) v by Lanczos with full re-orthogonalisation;
+//                 the small tridiagonal exponential by scaled Taylor series.
+// All matrices are row-major complex<double> in global scratch memory.
+#pragma once
+#include <dev_common.hpp>
+
+#define TJM_KMAX 32                 // largest Krylov dimension supported
+
+// --------------------------------------------------------------------------
+// Householder QR.  X (m x n, ld n) is destroyed.  On return Q (m x k, ld k)
+// and R (k x n, ld n) hold the thin factors, k = min(m, n), with
+// diag(R) real >= 0.  hv (>= k doubles of LDS-or-global scratch) is used for
+// the reflector scales.
+// --------------------------------------------------------------------------
+struct QrLds {
+  double vnorm2[128];
+  double bre[128], bim[128];      // diagonal of R before the gauge fix
+};
+
+TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) {
+  const int k = m < n ? m : n;
+  const int tid = tjm_tid();
+  const int TPC = TJM_NT >= 16 ? 16 : 1;        // threads per column
+  const int ngrp = TJM_NT / TPC;
+  const int g = tid / TPC, gl = tid % TPC;
+  for (int j = 0; j < k; ++j) {
+    double a2 = 0.0;
+    for (int i = j + tid; i < m; i += TJM_NT) a2 += abs2(X[(long)i * n + j]);
+    a2 = blk_sum(a2, S);
+    if (tid == 0) {
+      zd x0 = X[(long)j * n + j];
+      double ax0 = sqrt(abs2(x0));
+      double al = sqrt(a2);
+      if (al == 0.0) {
+        H.vnorm2[j] = 0.0; H.bre[j] = 0.0; H.bim[j] = 0.0;
+      } else {
+        zd ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+        zd beta = cmk(-ph.re * al, -ph.im * al);
+        X[(long)j * n + j] = x0 - beta;           // v0 = x0 + ph * alpha
+        H.vnorm2[j] = 2.0 * al * (al + ax0);
+        H.bre[j] = beta.re; H.bim[j] = beta.im;
+      }
+    }
+    tjm_sync();
+    const double vn = H.vnorm2[j];
+    if (vn > 0.0) {
+      const double f = 2.0 / vn;
+      for (int c = j + 1 + g; c < n; c += ngrp) {
+        double sr = 0.0, si = 0.0;
+        for (int i = j + gl; i < m; i += TPC) {
+          zd v = X[(long)i * n + j], x = X[(long)i * n + c];
+          zd p = cdotc(v, x);
+          sr += p.re; si += p.im;
+        }
+        sr = grp_sum(sr, TPC); si = grp_sum(si, TPC);
+        zd s = cmk(f * sr, f * si);
+        for (int i = j + gl; i < m; i += TPC) {
+          zd v = X[(long)i * n + j];
+          X[(long)i * n + c] = X[(long)i * n + c] - s * v;
+        }
+      }
+    }
+    tjm_sync();
+  }
+  // R (upper triangle of X, diagonal beta), then the gauge fix
+  for (int e = tid; e < k * n; e += TJM_NT) {
+    int i = e / n, c = e % n;
+    zd v = cmk(0.0, 0.0);
+    if (c > i) v = X[(long)i * n + c];
+    else if (c == i) v = cmk(H.bre[i], H.bim[i]);
+    R[(long)i * n + c] = v;
+  }
+  // Q = H_0 ... H_{k-1} [I; 0]
+  for (int e = tid; e < m * k; e += TJM_NT) {
+    int i = e / k, c = e % k;
+    Q[(long)i * k + c] = cmk(i == c ? 1.0 : 0.0, 0.0);
+  }
+  tjm_sync();
+  for (int j = k - 1; j >= 0; --j) {
+    const double vn = H.vnorm2[j];
+    if (vn > 0.0) {
+      const double f = 2.0 / vn;
+      for (int c = j + g; c < k; c += ngrp) {
+        double sr = 0.0, si = 0.0;
+        for (int i = j + gl; i < m; i += TPC) {
+          zd p = cdotc(X[(long)i * n + j], Q[(long)i * k + c]);
+          sr += p.re; si += p.im;
+        }
+        sr = grp_sum(sr, TPC); si = grp_sum(si, TPC);
+        zd s = cmk(f * sr, f * si);
+        for (int i = j + gl; i < m; i += TPC)
+          Q[(long)i * k + c] = Q[(long)i * k + c] - s * X[(long)i * n + j];
+      }
+    }
+    tjm_sync();
+  }
+  // diag(R) real >= 0: row j of R times conj(ph_j), column j of Q times ph_j
+  for (int e = tid; e < k * n; e += TJM_NT) {
+    int i = e / n;
+    double br = H.bre[i], bi = H.bim[i], ab = sqrt(br * br + bi * bi);
+    if (ab > 0.0) R[e] = cmk(br / ab, -bi / ab) * R[e];
+  }
+  for (int e = tid; e < m * k; e += TJM_NT) {
+    int c = e % k;
+    double br = H.bre[c], bi = H.bim[c], ab = sqrt(br * br + bi * bi);
+    if (ab > 0.0) Q[e] = cmk(br / ab, bi / ab) * Q[e];
+  }
+  tjm_sync();
+}
+
+// --------------------------------------------------------------------------
+// Truncation rank of a non-increasing spectrum s_0 >= s_1 >= ... (n values,
+// read through s(i)); run by one thread.  Smallest k >= 1 with
+// sum_{i>=k} s_i^2 <= discard * sum s_i^2 (the tail accumulated from the
+// end), capped at cap; a cap that cuts a multiplet (s_{k-1} - s_k <=
+// deg_tol s_0) is lowered until it does not.
+// --------------------------------------------------------------------------
+template <class F>
+TJM_DEV int trunc_rank(F s, int n, double discard, int cap, double deg_tol) {
+  double total = 0.0;
+  for (int i = 0; i < n; ++i) total += s(i) * s(i);
+  const double thr = discard * total;
+  int k = n;
+  double tail = 0.0;                      // tail(n) = 0 <= thr unless discard < 0
+  if (!(0.0 <= thr)) k = n;
+  else {
+    for (int kk = n - 1; kk >= 1; --kk) {
+      tail += s(kk) * s(kk);              // = sum_{i >= kk} s_i^2
+      if (tail <= thr) k = kk; else break;
+    }
+  }
+  if (k > cap) {
+    k = cap;
+    while (k > 1 && s(k - 1) - s(k) <= deg_tol * s(0)) --k;
+  }
+  return k < 1 ? 1 : k;
+}
+
+// --------------------------------------------------------------------------
+// One-sided Jacobi SVD of G (m x n, row-major ld n), truncated.
+//   left  (m x k, ld k)  = U        or U S   (absorb_left)
+//   right (k x n, ld n)  = S V^H    or V^H
+// Returns k.  Wc/Vc are (p x nc) and (nc x nc) column-major work arrays,
+// p = max(m, n), nc = min(m, n) <= 128.
+// --------------------------------------------------------------------------
+struct SvdLds {
+  double s[128];
+  int order[128];
+  int rotated;
+  int k;
+};
+
+TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
+                    double discard, int cap, double deg_tol,
+                    zd* Wc, zd* Vc, SvdLds& SL, BlkScratch& S) {
+  const int tid = tjm_tid();
+  const bool tr = m < n;                 // work on G^H so that columns <= rows
+  const int p = tr ? n : m;              // rows of the working matrix
+  const int nc = tr ? m : n;             // columns of the working matrix
+  for (int e = tid; e < p * nc; e += TJM_NT) {
+    int c = e / p, r = e % p;            // Wc[c][r] = Gw[r][c]
+    Wc[e] = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
+  }
+  for (int e = tid; e < nc * nc; e += TJM_NT) {
+    int c = e / nc, r = e % nc;
+    Vc[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
+  }
+  tjm_sync();
+  const int np = (nc + 1) & ~1;          // players, a dummy if nc is odd
+  const int npair = np / 2;
+  int tpp = 64;
+  while (tpp > 1 && tpp * npair > TJM_NT) tpp >>= 1;
+  const int ngrp = TJM_NT / tpp;
+  const int g = tid / tpp, gl = tid % tpp;
+  const double tol = 2.220446049250313e-16 * sqrt((double)p);
+  // columns whose norm is below 1e-18 of ||G||_F are exact zeros: rotating
+  // them only stirs rounding noise (and can never converge)
+  double f2 = 0.0;
+  for (int e = tid; e < p * nc; e += TJM_NT) f2 += abs2(Wc[e]);
+  const double zero2 = 1e-36 * blk_sum(f2, S);
+  for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
+    if (tid == 0) SL.rotated = 0;
+    tjm_sync();
+    for (int rnd = 0; rnd < np - 1; ++rnd) {
+      for (int pr = g; pr < npair; pr += ngrp) {
+        int a, b;
+        if (pr == 0) { a = rnd; b = np - 1; }
+        else { a = (rnd + pr) % (np - 1); b = (rnd - pr + (np - 1)) % (np - 1); }
+        if (a > b) { int t = a; a = b; b = t; }
+        if (b >= nc) continue;
+        zd* wa = Wc + (long)a * p;
+        zd* wb = Wc + (long)b * p;
+        double aa = 0.0, bb = 0.0, cr = 0.0, ci = 0.0;
+        for (int r = gl; r < p; r += tpp) {
+          zd x = wa[r], y = wb[r];
+          aa += abs2(x); bb += abs2(y);
+          zd c = cdotc(x, y);
+          cr += c.re; ci += c.im;
+        }
+        aa = grp_sum(aa, tpp); bb = grp_sum(bb, tpp);
+        cr = grp_sum(cr, tpp); ci = grp_sum(ci, tpp);
+        const double ac = hypot(cr, ci);
+        if (aa > zero2 && bb > zero2 && ac > tol * sqrt(aa) * sqrt(bb)) {
+          const double zeta = (bb - aa) / (2.0 * ac);
+          const double az = fabs(zeta);
+          double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
+          if (zeta < 0.0) t = -t;
+          double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          zd eph = cmk(cr / ac, -ci / ac);      // conj(c)/|c|
+          for (int r = gl; r < p; r += tpp) {
+            zd x = wa[r], y = eph * wb[r];
+            wa[r] = cs * x - sn * y;
+            wb[r] = sn * x + cs * y;
+          }
+          zd* va = Vc + (long)a * nc;
+          zd* vb = Vc + (long)b * nc;
+          for (int r = gl; r < nc; r += tpp) {
+            zd x = va[r], y = eph * vb[r];
+            va[r] = cs * x - sn * y;
+            vb[r] = sn * x + cs * y;
+          }
+          if (gl == 0) SL.rotated = 1;
+        }
+      }
+      tjm_sync();
+    }
+    if (SL.rotated == 0) break;
+    tjm_sync();
+  }
+  // singular values, descending order (stable in the column index)
+  for (int c = tjm_wave(); c < nc; c += TJM_NWAVE) {
+    double a = 0.0;
+    for (int r = tjm_lane(); r < p; r += TJM_WAVE) a += abs2(Wc[(long)c * p + r]);
+    a = grp_sum(a, TJM_WAVE);
+    if (tjm_lane() == 0) SL.s[c] = sqrt(a);
+  }
+  tjm_sync();
+  for (int c = tid; c < nc; c += TJM_NT) {
+    const double sc = SL.s[c];
+    int rank = 0;
+    for (int i = 0; i < nc; ++i) {
+      double si = SL.s[i];
+      if (si > sc || (si == sc && i < c)) ++rank;
+    }
+    SL.order[rank] = c;
+  }
+  tjm_sync();
+  if (tid == 0) {
+    auto sv = [&](int i) { return SL.s[SL.order[i]]; };
+    int k = trunc_rank(sv, nc, discard, cap, deg_tol);
+    while (k > 1 && sv(k - 1) <= 0.0) --k;   // never keep an exact zero
+    SL.k = k;
+  }
+  tjm_sync();
+  const int k = SL.k;
+  // U_j = w_{o_j} / s_{o_j} (p x k), V_j = v_{o_j} (nc x k)
+  // not transposed: G = U S V^H -> left rows m = p, right columns n = nc
+  // transposed:     G = V S U^H -> left rows m = nc, right columns n = p
+  if (!tr) {
+    for (int e = tid; e < m * k; e += TJM_NT) {
+      int r = e / k, j = e % k;
+      int o = SL.order[j];
+      double s = SL.s[o];
+      zd u = Wc[(long)o * p + r];
+      left[e] = absorb_left ? u : (1.0 / s) * u;
+    }
+    for (int e = tid; e < k * n; e += TJM_NT) {
+      int j = e / n, c = e % n;
+      int o = SL.order[j];
+      zd v = conjg(Vc[(long)o * nc + c]);
+      right[e] = absorb_left ? v : SL.s[o] * v;
+    }
+  } else {
+    for (int e = tid; e < m * k; e += TJM_NT) {
+      int r = e / k, j = e % k;
+      int o = SL.order[j];
+      zd v = Vc[(long)o * nc + r];
+      left[e] = absorb_left ? SL.s[o] * v : v;
+    }
+    for (int e = tid; e < k * n; e += TJM_NT) {
+      int j = e / n, c = e % n;
+      int o = SL.order[j];
+      double s = SL.s[o];
+      zd u = conjg(Wc[(long)o * p + c]);
+      right[e] = absorb_left ? (1.0 / s) * u : u;
+    }
+  }
+  tjm_sync();
+  return k;
+}
+
+// --------------------------------------------------------------------------
+// Lanczos exponential.  v (n complex doubles) is replaced by exp(-i t H) v.
+// Op must provide  void apply(const zd* q, zd* w)  (a collective call that
+// leaves w complete for all threads).  Q holds up to m_max basis vectors of
+// length n, w is an n-vector of scratch.  Returns the Krylov dimension used.
+// --------------------------------------------------------------------------
+struct LanczosLds {
+  double alpha[TJM_KMAX], beta[TJM_KMAX];
+  double cre[TJM_KMAX], cim[TJM_KMAX];
+  double hre[TJM_KMAX], him[TJM_KMAX];
+  double red[TJM_NWAVE][2 * TJM_KMAX];
+  double ur[TJM_KMAX], ui[TJM_KMAX], tr[TJM_KMAX], ti[TJM_KMAX];
+  int done;
+};
+
+// exp(-i t T) e_0 for the symmetric tridiagonal T = tridiag(beta, alpha, beta)
+// of size m <= 32, by thread 0: shift by alpha_0, split t into s pieces with
+// |t/s| * ||T - alpha_0||_inf <= 1/2 (Gershgorin) and sum 18 Taylor terms per
+// piece (remainder below 1e-21 of the norm).
+TJM_DEV void tridiag_exp_e0(int m, double t, LanczosLds& Lz) {
+  if (tjm_tid() != 0) return;
+  const double mu = Lz.alpha[0];
+  double gers = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double g = fabs(Lz.alpha[i] - mu) + (i > 0 ? Lz.beta[i - 1] : 0.0) + (i + 1 < m ? Lz.beta[i] : 0.0);
+    gers = fmax(gers, g);
+  }
+  int pieces = (int)ceil(fabs(t) * gers / 0.5);
+  if (pieces < 1) pieces = 1;
+  const double h = t / pieces;
+  double* ur = Lz.ur;
+  double* ui = Lz.ui;
+  double* tr = Lz.tr;
+  double* ti = Lz.ti;
+  for (int i = 0; i < m; ++i) { ur[i] = (i == 0) ? 1.0 : 0.0; ui[i] = 0.0; }
+  for (int pc = 0; pc < pieces; ++pc) {
+    for (int i = 0; i < m; ++i) { tr[i] = ur[i]; ti[i] = ui[i]; }
+    for (int kk = 1; kk <= 18; ++kk) {
+      // term <- (-i h / kk) (T - mu) term, in place with a one-element lag
+      const double f = h / kk;
+      double prev_r = 0.0, prev_i = 0.0;
+      for (int i = 0; i < m; ++i) {
+        double yr = (Lz.alpha[i] - mu) * tr[i], yi = (Lz.alpha[i] - mu) * ti[i];
+        if (i > 0) { yr += Lz.beta[i - 1] * prev_r; yi += Lz.beta[i - 1] * prev_i; }
+        if (i + 1 < m) { yr += Lz.beta[i] * tr[i + 1]; yi += Lz.beta[i] * ti[i + 1]; }
+        prev_r = tr[i]; prev_i = ti[i];
+        tr[i] = f * yi;                   // (-i f)(yr + i yi)
+        ti[i] = -f * yr;
+        ur[i] += tr[i]; ui[i] += ti[i];
+      }
+    }
+  }
+  const double cr = cos(t * mu), ci = -sin(t * mu);
+  for (int i = 0; i < m; ++i) {
+    Lz.cre[i] = cr * ur[i] - ci * ui[i];
+    Lz.cim[i] = cr * ui[i] + ci * ur[i];
+  }
+}
+
+template <class Op>
+TJM_DEV int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol,
+                     zd* Q, zd* w, LanczosLds& Lz, BlkScratch& S) {
+  const int tid = tjm_tid();
+  double b0 = 0.0;
+  for (int e = tid; e < n; e += TJM_NT) b0 += abs2(v[e]);
+  b0 = sqrt(blk_sum(b0, S));
+  if (b0 == 0.0) return 0;
+  if (m_max > TJM_KMAX) m_max = TJM_KMAX;
+  if (m_max > n) m_max = n;
+  for (int e = tid; e < n; e += TJM_NT) Q[e] = (1.0 / b0) * v[e];
+  tjm_sync();
+  int used = 0;
+  for (int j = 0; j < m_max; ++j) {
+    const zd* qj = Q + (long)j * n;
+    op.apply(qj, w);                                   // w = H q_j
+    double al = 0.0;
+    for (int e = tid; e < n; e += TJM_NT) al += cdotc(qj[e], w[e]).re;
+    al = blk_sum(al, S);
+    const double bprev = j > 0 ? Lz.beta[j - 1] : 0.0;
+    const zd* qp = j > 0 ? Q + (long)(j - 1) * n : Q;
+    for (int e = tid; e < n; e += TJM_NT) {
+      zd x = w[e] - al * qj[e];
+      if (j > 0) x = x - bprev * qp[e];
+      w[e] = x;
+    }
+    // full re-orthogonalisation: w -= Q (Q^H w) against q_0..q_j
+    const int nq = j + 1;
+    for (int i = 0; i < nq; ++i) {
+      const zd* qi = Q + (long)i * n;
+      double hr = 0.0, hi = 0.0;
+      for (int e = tid; e < n; e += TJM_NT) {
+        zd p = cdotc(qi[e], w[e]);
+        hr += p.re; hi += p.im;
+      }
+      for (int s = TJM_WAVE / 2; s > 0; s >>= 1) { hr += tjm_shfl_xor(hr, s); hi += tjm_shfl_xor(hi, s); }
+      if (tjm_lane() == 0) { Lz.red[tjm_wave()][2 * i] = hr; Lz.red[tjm_wave()][2 * i + 1] = hi; }
+    }
+    tjm_sync();
+    for (int i = tid; i < nq; i += TJM_NT) {
+      double hr = 0.0, hi = 0.0;
+      for (int wv = 0; wv < TJM_NWAVE; ++wv) { hr += Lz.red[wv][2 * i]; hi += Lz.red[wv][2 * i + 1]; }
+      Lz.hre[i] = hr; Lz.him[i] = hi;
+    }
+    if (tid == 0) Lz.alpha[j] = al;
+    tjm_sync();
+    double bn = 0.0;
+    for (int e = tid; e < n; e += TJM_NT) {
+      zd x = w[e];
+      for (int i = 0; i < nq; ++i) x = x - cmk(Lz.hre[i], Lz.him[i]) * Q[(long)i * n + e];
+      w[e] = x;
+      bn += abs2(x);
+    }
+    bn = sqrt(blk_sum(bn, S));
+    tridiag_exp_e0(j + 1, t, Lz);
+    tjm_sync();
+    if (tid == 0) {
+      double cj = sqrt(Lz.cre[j] * Lz.cre[j] + Lz.cim[j] * Lz.cim[j]);
+      Lz.done = (bn * cj <= tol || j == m_max - 1) ? 1 : 0;
+      Lz.beta[j] = bn;
+    }
+    tjm_sync();
+    used = j + 1;
+    if (Lz.done) break;
+    zd* qn = Q + (long)(j + 1) * n;
+    for (int e = tid; e < n; e += TJM_NT) qn[e] = (1.0 / bn) * w[e];
+    tjm_sync();
+  }
+  // v = b0 * sum_i c_i q_i
+  for (int e = tid; e < n; e += TJM_NT) {
+    zd x = cmk(0.0, 0.0);
+    for (int i = 0; i < used; ++i) x = x + cmk(Lz.cre[i], Lz.cim[i]) * Q[(long)i * n + e];
+    v[e] = b0 * x;
+  }
+  tjm_sync();
+  return used;
+}

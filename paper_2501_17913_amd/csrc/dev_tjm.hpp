@@ -1,0 +1,649 @@
+// One trajectory of the tensor jump method, executed by one workgroup.
+//
+// Paper map (Sec. "Tensor jump method"):
+//   traj_init / traj_step        schedule of the sampling MPS, Eqs.
+//                                TimeEvolutionFunctions and SimulationStep
+//   tdvp                         dynamic TDVP U[dt] (Sec. "Dynamic TDVP"):
+//                                1TDVP/2TDVP forward/backward updates,
+//                                Lanczos exponentials of effective
+//                                Hamiltonians built from cached environments
+//   dissipate                    D[tau] = prod_l D_l[tau] (Eq. DissipativeMPO)
+//   jump_process                 J_eps (Sec. "Stochastic jump process")
+// Decisions that must match any other implementation (switch rule,
+// truncation rank, jump / no jump, which jump) are functions of
+// gauge-invariant quantities only.
+//
+// Storage: a site tensor is M[a][s][b] (row-major, current bond dims); a left
+// environment at bond b is L[w][a_bra][a_ket]; a right environment at bond b
+// is R[w][b_ket][b_bra].  Environments live in numbered slots so that a new
+// one can be built while the old one at the same bond is still in use.
+#pragma once
+#include <dev_gemm.hpp>
+#include <dev_linalg.hpp>
+#include "tjm_params.h"
+
+struct Lds {
+  BlkScratch S;
+  QrLds qr;
+  SvdLds sv;
+  LanczosLds lz;
+  unsigned long long st[8];
+  int item;
+  int pick;
+  double rho[4];
+};
+
+template <typename Tc> struct Tjm {
+  typedef cplx<Tc> zc;
+  const TjmParams& P;
+  Lds& sh;
+  int* slot;          // LDS [L+2]: env slot of each bond; slot[L+1] is the spare
+  int* bA;            // LDS [L+1]: bonds of the sampling MPS
+  int* bB;            // LDS [L+1]: bonds of the sampling-layer copy
+  // worker scratch
+  zc* env; zd* smps; zd* Q; zd* w; zd* v; zc* T1; zc* T2; zd* X; zd* Y; zd* Z; zd* Cb; double* wts;
+  int d, L;
+
+  TJM_DEV Tjm(const TjmParams& p, Lds& s, int* dyn, int worker) : P(p), sh(s) {
+    L = P.L; d = P.d;
+    slot = dyn;
+    bA = dyn + (L + 2);
+    bB = bA + (L + 1);
+    char* base = P.scratch + (long)worker * P.scratch_stride;
+    env = (zc*)(base + P.off_env);
+    smps = (zd*)(base + P.off_smps);
+    Q = (zd*)(base + P.off_Q);
+    w = (zd*)(base + P.off_w);
+    v = (zd*)(base + P.off_v);
+    T1 = (zc*)(base + P.off_T1);
+    T2 = (zc*)(base + P.off_T2);
+    X = (zd*)(base + P.off_X);
+    Y = (zd*)(base + P.off_Y);
+    Z = (zd*)(base + P.off_Z);
+    Cb = (zd*)(base + P.off_C);
+    wts = (double*)(base + P.off_wts);
+  }
+
+  TJM_DEV zc* envp(int bond) { return env + (long)slot[bond] * P.env_cap; }
+  TJM_DEV zc* spare() { return env + (long)slot[L + 1] * P.env_cap; }
+  TJM_DEV void count(int i, unsigned long long n) { if (tjm_tid() == 0) sh.st[i] += n; }
+  TJM_DEV static zd* site(zd* mps, const TjmParams& P, int s) { return mps + P.site_off[s]; }
+
+  // ------------------------------------------------------------------
+  // MPO mixing stage: dst[wo][a][so][b] = sum_{(wi,si,val) in row (wo,so)}
+  //                                       val * src[wi][a][si][b]
+  // (src has dph physical values per channel, dst the same)
+  // ------------------------------------------------------------------
+  TJM_DEV void mix(int Dout, int A, int dph, int B, const int* rp, const MixEnt* ent,
+                   const zc* src, zc* dst) {
+    const long per = (long)A * dph * B;
+    const long tot = (long)Dout * per;
+    for (long e = tjm_tid(); e < tot; e += TJM_NT) {
+      int wo = (int)(e / per);
+      long r = e - wo * per;
+      int a = (int)(r / ((long)dph * B));
+      int r2 = (int)(r - (long)a * dph * B);
+      int so = r2 / B, b = r2 % B;
+      int row = wo * dph + so;
+      Tc xr = 0, xi = 0;
+      for (int q = rp[row]; q < rp[row + 1]; ++q) {
+        MixEnt m = ent[q];
+        zc x = src[(long)m.w * per + ((long)a * dph + m.s) * B + b];
+        xr += (Tc)m.re * x.re - (Tc)m.im * x.im;
+        xi += (Tc)m.re * x.im + (Tc)m.im * x.re;
+      }
+      dst[e] = cmk(xr, xi);
+    }
+  }
+  TJM_DEV unsigned long long mix_nnz(int Dout, int dph, const int* rp) {
+    return (unsigned long long)(rp[Dout * dph] - rp[0]);
+  }
+
+  // ------------------------------------------------------------------
+  // Environments (Fig. TDVP; Sec. "Hybrid strategy")
+  // ------------------------------------------------------------------
+  TJM_DEV void env_one(zc* e) {
+    if (tjm_tid() == 0) e[0] = cmk((Tc)1, (Tc)0);
+  }
+
+  // L_{s+1}[w'][b'][b] = sum L_s[w][a'][a] conj(A[a'][s'][b']) W[w][w'][s'][s] A[a][s][b]
+  TJM_DEV void lupdate(int s, const zd* A, int chl, int chr, const zc* Lold, zc* Lnew) {
+    const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
+    const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
+    blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
+                  T1, d * chr, (long)chl * d * chr, false);
+    tjm_sync();
+    mix(Dr, chl, d, chr, rp, P.mixL, T1, T2);
+    tjm_sync();
+    blk_cgemm<Tc>(chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
+                  cmat((const zc*)T2, chr, (long)chl * d * chr), Lnew, chr, (long)chr * chr, false);
+    tjm_sync();
+    count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chr * chr * chl * d);
+    count(TJM_ST_CMAC_MIX, mix_nnz(Dr, d, rp) * chl * chr);
+  }
+
+  // R_{s-1}[w][a][a'] = sum B[a][s][b] R_s[w'][b][b'] W[w][w'][s'][s] conj(B[a'][s'][b'])
+  TJM_DEV void rupdate(int s, const zd* B, int chl, int chr, const zc* Rold, zc* Rnew) {
+    const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
+    const int* rp = P.mixR_ptr + (long)s * (P.Dmax * d + 1);
+    blk_cgemm<Tc>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
+                  T1, chr, (long)chl * d * chr, false);
+    tjm_sync();
+    mix(Dl, chl, d, chr, rp, P.mixR, T1, T2);
+    tjm_sync();
+    blk_cgemm<Tc>(chl, chl, d * chr, Dl, false, cmat((const zc*)T2, d * chr, (long)chl * d * chr),
+                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false);
+    tjm_sync();
+    count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
+    count(TJM_ST_CMAC_MIX, mix_nnz(Dl, d, rp) * chl * chr);
+  }
+
+  // ------------------------------------------------------------------
+  // Effective Hamiltonians as matrix-free products (Fig. TDVP)
+  // ------------------------------------------------------------------
+  struct H1 {            // site s: degree-6 network
+    Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
+    TJM_DEV void apply(const zd* q, zd* y) {
+      const TjmParams& P = t->P;
+      const int d = t->d, Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
+      const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
+      blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
+                    t->T1, d * chr, (long)chl * d * chr, false);
+      tjm_sync();
+      t->mix(Dr, chl, d, chr, rp, P.mixL, t->T1, t->T2);
+      tjm_sync();
+      blk_cgemm<Tc>(chl * d, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d * chr),
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false);
+      tjm_sync();
+      t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chl * d * chr * chr);
+      t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d, rp) * chl * chr);
+    }
+  };
+
+  struct H2 {            // sites s, s+1: degree-8 network
+    Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
+    TJM_DEV void apply(const zd* q, zd* y) {
+      const TjmParams& P = t->P;
+      const int d = t->d, d2 = d * d, Dl = P.mpoD[s], Dr = P.mpoD[s + 2];
+      const int* rp = P.mix2_ptr + (long)s * (P.Dmax * d2 + 1);
+      blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
+                    t->T1, d2 * chr, (long)chl * d2 * chr, false);
+      tjm_sync();
+      t->mix(Dr, chl, d2, chr, rp, P.mix2, t->T1, t->T2);
+      tjm_sync();
+      blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d2 * chr),
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false);
+      tjm_sync();
+      t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d2 * chr + (unsigned long long)Dr * chl * d2 * chr * chr);
+      t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d2, rp) * chl * chr);
+    }
+  };
+
+  struct H0 {            // bond b: degree-4 network, C is kl x kr
+    Tjm* t; int D, kl, kr; const zc* Le; const zc* Re;
+    TJM_DEV void apply(const zd* q, zd* y) {
+      blk_cgemm<Tc>(kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
+                    t->T1, kr, (long)kl * kr, false);
+      tjm_sync();
+      blk_cgemm<Tc>(kl, kr, kr, D, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
+                    cmat(Re, kr, (long)kr * kr), y, kr, 0, false);
+      tjm_sync();
+      t->count(TJM_ST_CMAC_MFMA, (unsigned long long)D * kl * kl * kr + (unsigned long long)D * kl * kr * kr);
+    }
+  };
+
+  template <class Op> TJM_DEV void expm(Op& op, zd* vec, int n, double t) {
+    int it = blk_expm(op, vec, n, t, P.krylov_max, P.krylov_tol, Q, w, sh.lz, sh.S);
+    count(TJM_ST_KRYLOV, (unsigned long long)it);
+    count(TJM_ST_EXPM, 1ull);
+  }
+
+  // ------------------------------------------------------------------
+  // Site moves (FP64 factorisations)
+  // ------------------------------------------------------------------
+  TJM_DEV void copy(zd* dst, const zd* src, long n) {
+    for (long e = tjm_tid(); e < n; e += TJM_NT) dst[e] = src[e];
+  }
+
+  // next (k x d x c) = C (k x m) . next (m x d x c), via v
+  TJM_DEV void absorb_right(zd* next, int k, int m, int c) {
+    blk_cgemm<double>(k, d * c, m, 1, true, cmat((const zd*)Cb, m), cmat((const zd*)next, d * c), v, d * c, 0, false);
+    tjm_sync();
+    copy(next, v, (long)k * d * c);
+    tjm_sync();
+  }
+  // prev (p x d x k) = prev (p x d x m) . C (m x k), via v
+  TJM_DEV void absorb_left(zd* prev, int p, int m, int k) {
+    blk_cgemm<double>(p * d, k, m, 1, true, cmat((const zd*)prev, m), cmat((const zd*)Cb, k), v, k, 0, false);
+    tjm_sync();
+    copy(prev, v, (long)p * d * k);
+    tjm_sync();
+  }
+
+  // QR of M_s as (chl d) x chr: M_s <- Q, Cb <- R (k x chr); returns k
+  TJM_DEV int qr_site(zd* Ms, int chl, int chr) {
+    const int m = chl * d;
+    copy(X, Ms, (long)m * chr);
+    tjm_sync();
+    blk_qr(m, chr, X, Ms, Cb, sh.qr, sh.S);
+    count(TJM_ST_FACT, 1ull);
+    return m < chr ? m : chr;
+  }
+
+  // LQ of M_s as chl x (d chr): M_s <- B (k x d chr, orthonormal rows),
+  // Cb <- C (chl x k); returns k
+  TJM_DEV int lq_site(zd* Ms, int chl, int chr) {
+    const int n = d * chr;
+    for (long e = tjm_tid(); e < (long)n * chl; e += TJM_NT) {      // X = M^H (n x chl)
+      int i = (int)(e / chl), j = (int)(e % chl);
+      X[e] = conjg(Ms[(long)j * n + i]);
+    }
+    tjm_sync();
+    blk_qr(n, chl, X, Y, Z, sh.qr, sh.S);                           // Y: n x k, Z: k x chl
+    const int k = n < chl ? n : chl;
+    for (long e = tjm_tid(); e < (long)k * n; e += TJM_NT) {        // M = Y^H
+      int i = (int)(e / n), j = (int)(e % n);
+      Ms[e] = conjg(Y[(long)j * k + i]);
+    }
+    for (long e = tjm_tid(); e < (long)chl * k; e += TJM_NT) {      // C = Z^H
+      int i = (int)(e / k), j = (int)(e % k);
+      Cb[e] = conjg(Z[(long)j * chl + i]);
+    }
+    tjm_sync();
+    count(TJM_ST_FACT, 1ull);
+    return k;
+  }
+
+  TJM_DEV void qr_move_right(zd* mps, int* bd, int s) {
+    zd* Ms = site(mps, P, s);
+    const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
+    const int k = qr_site(Ms, chl, chr);
+    absorb_right(site(mps, P, s + 1), k, chr, cn);
+    if (tjm_tid() == 0) bd[s + 1] = k;
+    tjm_sync();
+  }
+
+  TJM_DEV void lq_move_left(zd* mps, int* bd, int s) {
+    zd* Ms = site(mps, P, s);
+    const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
+    const int k = lq_site(Ms, chl, chr);
+    absorb_left(site(mps, P, s - 1), cp, chl, k);
+    if (tjm_tid() == 0) bd[s] = k;
+    tjm_sync();
+  }
+
+  TJM_DEV void svd_move_right(zd* mps, int* bd, int s) {
+    zd* Ms = site(mps, P, s);
+    const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
+    const int k = blk_svd(chl * d, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+    count(TJM_ST_FACT, 1ull);
+    absorb_right(site(mps, P, s + 1), k, chr, cn);
+    if (tjm_tid() == 0) bd[s + 1] = k;
+    tjm_sync();
+  }
+
+  TJM_DEV void svd_move_left(zd* mps, int* bd, int s) {
+    zd* Ms = site(mps, P, s);
+    const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
+    const int k = blk_svd(chl, d * chr, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+    count(TJM_ST_FACT, 1ull);
+    absorb_left(site(mps, P, s - 1), cp, chl, k);
+    if (tjm_tid() == 0) bd[s] = k;
+    tjm_sync();
+  }
+
+  // ------------------------------------------------------------------
+  // Dynamic TDVP U[dt] (Sec. "Dynamic TDVP"): an L->R and an R->L
+  // half-sweep of tau = dt/2; 2TDVP at bond l iff chi_l < chi_max when the
+  // sweep reaches it, else 1TDVP; the turning unit is evolved again.
+  // Precondition: centre at site 0, other sites right-canonical.
+  // ------------------------------------------------------------------
+  TJM_DEV void tdvp(zd* mps, int* bd) {
+    const double tau = 0.5 * P.dt;
+    if (tjm_tid() == 0)
+      for (int b = 0; b < L + 2; ++b) slot[b] = b;
+    tjm_sync();
+    env_one(envp(0));
+    env_one(envp(L));
+    tjm_sync();
+    for (int s = L - 1; s >= 1; --s) {
+      rupdate(s, site(mps, P, s), bd[s], bd[s + 1], envp(s + 1), envp(s));
+    }
+    // left to right
+    bool last_two = false;
+    for (int s = 0; s < L - 1; ++s) {
+      zd* Ms = site(mps, P, s);
+      zd* Mn = site(mps, P, s + 1);
+      const int chl = bd[s], chm = bd[s + 1], chr = bd[s + 2];
+      if (chm < P.chi_max) {
+        count(TJM_ST_TWO_SITE, 1ull);
+        blk_cgemm<double>(chl * d, d * chr, chm, 1, true, cmat((const zd*)Ms, chm), cmat((const zd*)Mn, d * chr),
+                          v, d * chr, 0, false);
+        tjm_sync();
+        H2 op{this, s, chl, chr, envp(s), envp(s + 2)};
+        expm(op, v, chl * d * d * chr, tau);
+        const int k = blk_svd(chl * d, d * chr, v, Ms, Mn, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+        count(TJM_ST_FACT, 1ull);
+        if (tjm_tid() == 0) bd[s + 1] = k;
+        tjm_sync();
+        lupdate(s, Ms, chl, k, envp(s), envp(s + 1));
+        if (s + 1 < L - 1) {
+          H1 op1{this, s + 1, k, chr, envp(s + 1), envp(s + 2)};
+          expm(op1, Mn, k * d * chr, -tau);
+        }
+        last_two = true;
+      } else {
+        count(TJM_ST_ONE_SITE, 1ull);
+        H1 op{this, s, chl, chm, envp(s), envp(s + 1)};
+        expm(op, Ms, chl * d * chm, tau);
+        const int k = qr_site(Ms, chl, chm);
+        lupdate(s, Ms, chl, k, envp(s), spare());
+        H0 op0{this, P.mpoD[s + 1], k, chm, spare(), envp(s + 1)};
+        expm(op0, Cb, k * chm, -tau);
+        if (tjm_tid() == 0) {
+          int t = slot[s + 1]; slot[s + 1] = slot[L + 1]; slot[L + 1] = t;
+          bd[s + 1] = k;
+        }
+        tjm_sync();
+        absorb_right(Mn, k, chm, chr);
+        last_two = false;
+      }
+    }
+    if (L == 1 || !last_two) {
+      H1 op{this, L - 1, bd[L - 1], bd[L], envp(L - 1), envp(L)};
+      expm(op, site(mps, P, L - 1), bd[L - 1] * d * bd[L], tau);
+    }
+    // right to left
+    last_two = false;
+    for (int s = L - 1; s >= 1; --s) {
+      zd* Ms = site(mps, P, s);
+      zd* Mp = site(mps, P, s - 1);
+      const int chp = bd[s - 1], chl = bd[s], chr = bd[s + 1];
+      if (chl < P.chi_max) {
+        count(TJM_ST_TWO_SITE, 1ull);
+        blk_cgemm<double>(chp * d, d * chr, chl, 1, true, cmat((const zd*)Mp, chl), cmat((const zd*)Ms, d * chr),
+                          v, d * chr, 0, false);
+        tjm_sync();
+        H2 op{this, s - 1, chp, chr, envp(s - 1), envp(s + 1)};
+        expm(op, v, chp * d * d * chr, tau);
+        const int k = blk_svd(chp * d, d * chr, v, Mp, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+        count(TJM_ST_FACT, 1ull);
+        if (tjm_tid() == 0) bd[s] = k;
+        tjm_sync();
+        rupdate(s, Ms, k, chr, envp(s + 1), envp(s));
+        if (s - 1 > 0) {
+          H1 op1{this, s - 1, chp, k, envp(s - 1), envp(s)};
+          expm(op1, Mp, chp * d * k, -tau);
+        }
+        last_two = true;
+      } else {
+        count(TJM_ST_ONE_SITE, 1ull);
+        H1 op{this, s, chl, chr, envp(s), envp(s + 1)};
+        expm(op, Ms, chl * d * chr, tau);
+        const int k = lq_site(Ms, chl, chr);
+        rupdate(s, Ms, k, chr, envp(s + 1), spare());
+        H0 op0{this, P.mpoD[s], chl, k, envp(s), spare()};
+        expm(op0, Cb, chl * k, -tau);
+        if (tjm_tid() == 0) {
+          int t = slot[s]; slot[s] = slot[L + 1]; slot[L + 1] = t;
+          bd[s] = k;
+        }
+        tjm_sync();
+        absorb_left(Mp, chp, chl, k);
+        last_two = false;
+      }
+    }
+    if (L == 1 || !last_two) {
+      H1 op{this, 0, bd[0], bd[1], envp(0), envp(1)};
+      expm(op, site(mps, P, 0), bd[0] * d * bd[1], tau);
+    }
+  }
+
+  // ------------------------------------------------------------------
+  // Dissipative contraction (Eq. DissipativeMPO): M_l <- D_l M_l on the
+  // physical index of every site; bond dimensions unchanged.
+  // ------------------------------------------------------------------
+  TJM_DEV void dissipate(zd* mps, const int* bd, const double* Dtab) {
+    for (int s = 0; s < L; ++s) {
+      zd* M = site(mps, P, s);
+      const zd* D = (const zd*)Dtab + (long)s * d * d;
+      const int chl = bd[s], chr = bd[s + 1];
+      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
+        int a = (int)(e / chr), b = (int)(e % chr);
+        zd in0 = M[((long)a * d + 0) * chr + b], in1 = M[((long)a * d + 1) * chr + b];
+        M[((long)a * d + 0) * chr + b] = D[0] * in0 + D[1] * in1;
+        M[((long)a * d + 1) * chr + b] = D[2] * in0 + D[3] * in1;
+      }
+    }
+    tjm_sync();
+  }
+
+  // rho[s][s'] = sum_{a,b} M[a][s][b] conj(M[a][s'][b]) at the centre
+  // (d = 2): sh.rho = (rho00, rho11, Re rho01, Im rho01)
+  TJM_DEV void site_rho(const zd* M, int chl, int chr) {
+    double r00 = 0, r11 = 0, rr = 0, ri = 0;
+    for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
+      int a = (int)(e / chr), b = (int)(e % chr);
+      zd x0 = M[((long)a * 2 + 0) * chr + b], x1 = M[((long)a * 2 + 1) * chr + b];
+      r00 += abs2(x0); r11 += abs2(x1);
+      zd c = cdotc(x1, x0);      // x0 conj(x1)
+      rr += c.re; ri += c.im;
+    }
+    blk_sum4(r00, r11, rr, ri, sh.S);
+    if (tjm_tid() == 0) { sh.rho[0] = r00; sh.rho[1] = r11; sh.rho[2] = rr; sh.rho[3] = ri; }
+    tjm_sync();
+  }
+
+  // sum_{s,s'} O[s'][s] rho[s][s'] (real part), for a 2x2 operator O
+  TJM_DEV double tr_op_rho(const zd* O) {
+    zd r01 = cmk(sh.rho[2], sh.rho[3]);
+    zd v = O[0] * cmk(sh.rho[0], 0.0) + O[3] * cmk(sh.rho[1], 0.0) + O[2] * r01 + O[1] * conjg(r01);
+    return v.re;
+  }
+
+  // Tr(L rho L^dag) for a 2x2 L
+  TJM_DEV double tr_l_rho_ld(const zd* Lop) {
+    zd rho[4] = {cmk(sh.rho[0], 0.0), cmk(sh.rho[2], sh.rho[3]), cmk(sh.rho[2], -sh.rho[3]), cmk(sh.rho[1], 0.0)};
+    double acc = 0.0;
+    for (int a = 0; a < 2; ++a) {
+      zd x = cmk(0.0, 0.0);
+      for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) x = x + Lop[a * 2 + b] * rho[b * 2 + c] * conjg(Lop[a * 2 + c]);
+      acc += x.re;
+    }
+    return acc;
+  }
+
+  // measure every observable of site s with the centre at s (rho in sh.rho)
+  TJM_DEV void measure(int s, double* out) {
+    if (tjm_tid() == 0) {
+      const double tr = sh.rho[0] + sh.rho[1];
+      for (int q = P.optr[s]; q < P.optr[s + 1]; ++q) {
+        int o = P.oidx[q];
+        out[o] = tr_op_rho((const zd*)P.obs_op + (long)o * 4) / tr;
+      }
+    }
+  }
+
+  TJM_DEV double norm2_site(const zd* M, long n) {
+    double a = 0.0;
+    for (long e = tjm_tid(); e < n; e += TJM_NT) a += abs2(M[e]);
+    return blk_sum(a, sh.S);
+  }
+
+  TJM_DEV void scale_site(zd* M, long n, double f) {
+    for (long e = tjm_tid(); e < n; e += TJM_NT) M[e] = f * M[e];
+    tjm_sync();
+  }
+
+  // ------------------------------------------------------------------
+  // Jump process J_eps (Sec. "Stochastic jump process").  Entry: centre at
+  // site 0.  Exit: normalised, centre at site 0.  If obs_out is non-null,
+  // the site observables of the final state are written there.
+  // Returns the applied jump index, -1 for none, -2 on a non-finite norm.
+  // ------------------------------------------------------------------
+  TJM_DEV int jump_process(zd* mps, int* bd, const double* Dtab, uint32_t step, uint32_t branch,
+                           double* obs_out) {
+    dissipate(mps, bd, Dtab);
+    for (int s = 0; s < L - 1; ++s) qr_move_right(mps, bd, s);
+    const long nlast = (long)bd[L - 1] * d * bd[L];
+    const double nrm2 = norm2_site(site(mps, P, L - 1), nlast);
+    if (!(nrm2 == nrm2) || nrm2 > 1e300) return -2;
+    const double dp = nrm2 < 1.0 ? 1.0 - nrm2 : 0.0;
+    double eps, r;
+    tjm_draws(P.seed, P.traj_base + (uint32_t)traj_id, step, branch, eps, r);
+    if (eps >= dp) {                                  // no jump: normalise
+      for (int s = L - 1; s >= 1; --s) {
+        if (obs_out) { site_rho(site(mps, P, s), bd[s], bd[s + 1]); measure(s, obs_out); }
+        lq_move_left(mps, bd, s);
+      }
+      finish(mps, bd, obs_out);
+      return -1;
+    }
+    // jump probabilities: sweep the centre right to left
+    for (int s = L - 1; s >= 0; --s) {
+      site_rho(site(mps, P, s), bd[s], bd[s + 1]);
+      if (tjm_tid() == 0) {
+        for (int q = P.jptr[s]; q < P.jptr[s + 1]; ++q) {
+          int j = P.jidx[q];
+          wts[j] = P.jump_rate[j] * tr_l_rho_ld((const zd*)P.jump_op + (long)j * 4);
+        }
+      }
+      if (obs_out) measure(s, obs_out);
+      if (s > 0) lq_move_left(mps, bd, s);
+    }
+    if (tjm_tid() == 0) {
+      double tot = 0.0;
+      for (int j = 0; j < P.n_jump; ++j) tot += wts[j];
+      int m = -1;
+      if (tot > 1e-300) {
+        const double thr = r * tot;
+        double cum = 0.0;
+        for (int j = 0; j < P.n_jump; ++j) {
+          cum += wts[j];
+          if (cum > thr) { m = j; break; }
+        }
+        if (m < 0)
+          for (int j = P.n_jump - 1; j >= 0; --j)
+            if (wts[j] > 0.0) { m = j; break; }
+      }
+      sh.pick = m;
+    }
+    tjm_sync();
+    const int m = sh.pick;
+    if (m < 0) {
+      finish(mps, bd, nullptr);
+      return -1;
+    }
+    const int sj = P.jump_site[m];
+    for (int s = 0; s < sj; ++s) qr_move_right(mps, bd, s);
+    {
+      zd* M = site(mps, P, sj);
+      const zd* Op = (const zd*)P.jump_op + (long)m * 4;
+      const int chl = bd[sj], chr = bd[sj + 1];
+      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
+        int a = (int)(e / chr), b = (int)(e % chr);
+        zd in0 = M[((long)a * 2 + 0) * chr + b], in1 = M[((long)a * 2 + 1) * chr + b];
+        M[((long)a * 2 + 0) * chr + b] = Op[0] * in0 + Op[1] * in1;
+        M[((long)a * 2 + 1) * chr + b] = Op[2] * in0 + Op[3] * in1;
+      }
+      tjm_sync();
+      const long n = (long)chl * d * chr;
+      const double nn = norm2_site(M, n);
+      scale_site(M, n, 1.0 / sqrt(nn));
+    }
+    count(TJM_ST_JUMPS, 1ull);
+    // normalisation through successive SVDs: jump site -> right end -> site 0
+    for (int s = sj; s < L - 1; ++s) svd_move_right(mps, bd, s);
+    for (int s = L - 1; s >= 1; --s) {
+      if (obs_out) { site_rho(site(mps, P, s), bd[s], bd[s + 1]); measure(s, obs_out); }
+      svd_move_left(mps, bd, s);
+    }
+    finish(mps, bd, obs_out);
+    return m;
+  }
+
+  // centre at site 0: measure it and normalise
+  TJM_DEV void finish(zd* mps, int* bd, double* obs_out) {
+    zd* M0 = site(mps, P, 0);
+    const long n = (long)bd[0] * d * bd[1];
+    if (obs_out) { site_rho(M0, bd[0], bd[1]); measure(0, obs_out); }
+    const double nn = norm2_site(M0, n);
+    scale_site(M0, n, 1.0 / sqrt(nn));
+  }
+
+  int traj_id;
+
+  // ------------------------------------------------------------------
+  // Schedule (Eqs. TimeEvolutionFunctions, SimulationStep)
+  // ------------------------------------------------------------------
+  TJM_DEV void load_bonds(int* bd, const int* src) {
+    for (int b = tjm_tid(); b <= L; b += TJM_NT) bd[b] = src[b];
+    tjm_sync();
+  }
+  TJM_DEV void store_bonds(int* dst, const int* bd) {
+    for (int b = tjm_tid(); b <= L; b += TJM_NT) dst[b] = bd[b];
+    tjm_sync();
+  }
+  TJM_DEV void stats_begin() {
+    for (int i = tjm_tid(); i < 8; i += TJM_NT) sh.st[i] = 0ull;
+    tjm_sync();
+  }
+  TJM_DEV void stats_end(int traj) {
+    tjm_sync();
+    for (int i = tjm_tid(); i < 8; i += TJM_NT) P.tstats[(long)traj * 8 + i] += sh.st[i];
+  }
+
+  // Psi(0): product state, canonicalised; t = 0 observables; Phi = F_0 Psi(0)
+  TJM_DEV void traj_init(int traj) {
+    traj_id = traj;
+    stats_begin();
+    zd* mps = (zd*)P.mps + (long)traj * P.mps_cap;
+    for (int b = tjm_tid(); b <= L; b += TJM_NT) bA[b] = 1;
+    for (long e = tjm_tid(); e < (long)L * d; e += TJM_NT) {
+      int s = (int)(e / d), q = (int)(e % d);
+      site(mps, P, s)[q] = ((const zd*)P.init_sites)[e];
+    }
+    tjm_sync();
+    double* o0 = P.obs + (long)traj * (P.n_steps + 1) * P.n_obs;
+    for (int s = L - 1; s >= 1; --s) {
+      site_rho(site(mps, P, s), bA[s], bA[s + 1]);
+      measure(s, o0);
+      lq_move_left(mps, bA, s);
+    }
+    finish(mps, bA, o0);
+    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
+    if (tjm_tid() == 0) {
+      P.jlog[(long)traj * 2 * P.n_steps] = m;
+      if (m == -2) P.tflags[traj] = 1;
+    }
+    store_bonds(P.bonds + (long)traj * (L + 1), bA);
+    stats_end(traj);
+  }
+
+  // F_k for k = 1..n: X = U Phi; Psi_k = J D[dt/2] X (measured);
+  // Phi = J D[dt] X for k < n
+  TJM_DEV void traj_step(int traj, int k) {
+    traj_id = traj;
+    stats_begin();
+    zd* mps = (zd*)P.mps + (long)traj * P.mps_cap;
+    load_bonds(bA, P.bonds + (long)traj * (L + 1));
+    tdvp(mps, bA);
+    if (P.record_bonds) store_bonds(P.blog + ((long)traj * P.n_steps + (k - 1)) * (L + 1), bA);
+    for (int s = 0; s < L; ++s) copy(site(smps, P, s), site(mps, P, s), (long)bA[s] * d * bA[s + 1]);
+    for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
+    tjm_sync();
+    double* ok = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
+    int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok);
+    int mm = -1;
+    if (k < P.n_steps) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr);
+    if (tjm_tid() == 0) {
+      int* jl = P.jlog + (long)traj * 2 * P.n_steps;
+      jl[2 * k - 1] = ms;
+      if (k < P.n_steps) jl[2 * k] = mm;
+      if (ms == -2 || mm == -2) P.tflags[traj] = 1;
+    }
+    store_bonds(P.bonds + (long)traj * (L + 1), bA);
+    stats_end(traj);
+  }
+};

@@ -1,0 +1,740 @@
+// C ABI of the TJM library: validation, host-side tables, device memory and
+// launches.  See include/tjm.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tjm.h"
+#include "tjm_internal.h"
+#include "tjm_selftest.h"
+
+typedef std::complex<double> cd;
+
+namespace {
+
+struct Run {
+  int n_traj = 0, n_steps = 0, n_obs = 0, steps_done = 0, workers = 0;
+  TjmParams P;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  double init_ms = 0, step_ms_total = 0, step_ms_last = 0;
+  int step_launches = 0;
+  // device pointers needed at the end
+  double* d_obs = nullptr;
+  int* d_jlog = nullptr;
+  int* d_blog = nullptr;
+  unsigned long long* d_stats = nullptr;
+  int* d_flags = nullptr;
+  int record_bonds = 0;
+};
+
+std::string g_create_err;
+
+}  // namespace
+
+struct tjm_model {
+  int L = 0, d = 0;
+  std::vector<int> mpoD;
+  std::vector<std::vector<cd>> W;     // per site [wl][wr][so][si]
+  int n_jump = 0;
+  std::vector<int> jsite;
+  std::vector<cd> jop;                // [n_jump][d][d]
+  std::vector<double> jrate;
+  std::vector<cd> init;               // [L][d]
+  std::string err;
+  Run* run = nullptr;
+  tjm_stats last{};
+};
+
+static tjm_status fail(tjm_model* m, tjm_status st, const std::string& msg) {
+  if (m) m->err = msg; else g_create_err = msg;
+  return st;
+}
+
+static bool finite_arr(const double* p, long n) {
+  for (long i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+#define HIPCHK(m, expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(m, e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+extern "C" void tjm_default_options(tjm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = TJM_PREC_FP64;
+  o->chi_cap = 0;
+  o->svd_discard = 1e-12;
+  o->krylov_max = 30;
+  o->krylov_tol = 0.0;
+  o->deg_tol = 1e-12;
+  o->workers = 0;
+  o->record_bonds = 0;
+  o->traj_base = 0;
+  o->device = 0;
+}
+
+extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
+                                 int n_jump, const int* jump_site, const double* jump_op,
+                                 const double* rate) {
+  if (!out) return fail(nullptr, TJM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 1) return fail(nullptr, TJM_E_INVAL, "L must be >= 1");
+  if (d != 2) return fail(nullptr, TJM_E_UNSUPPORTED, "only local dimension d = 2 is supported");
+  if (!mpo_bond || !mpo) return fail(nullptr, TJM_E_INVAL, "mpo_bond / mpo is NULL");
+  if (mpo_bond[0] != 1 || mpo_bond[L] != 1)
+    return fail(nullptr, TJM_E_INVAL, "MPO boundary bonds must be 1");
+  for (int b = 0; b <= L; ++b)
+    if (mpo_bond[b] < 1 || mpo_bond[b] > 8)
+      return fail(nullptr, TJM_E_INVAL, "MPO bond dimensions must be in 1..8");
+  if (n_jump < 0) return fail(nullptr, TJM_E_INVAL, "n_jump must be >= 0");
+  if (n_jump > 0 && (!jump_site || !jump_op || !rate))
+    return fail(nullptr, TJM_E_INVAL, "jump arrays are NULL");
+  tjm_model* m = new tjm_model();
+  m->L = L; m->d = d;
+  m->mpoD.assign(mpo_bond, mpo_bond + L + 1);
+  long off = 0;
+  m->W.resize(L);
+  for (int s = 0; s < L; ++s) {
+    const int Dl = mpo_bond[s], Dr = mpo_bond[s + 1];
+    const long n = (long)d * d * Dl * Dr;
+    if (!finite_arr(mpo + 2 * off, 2 * n)) {
+      delete m;
+      return fail(nullptr, TJM_E_INVAL, "MPO has non-finite entries");
+    }
+    m->W[s].assign((size_t)n, cd(0, 0));
+    for (int so = 0; so < d; ++so)
+      for (int si = 0; si < d; ++si)
+        for (int wl = 0; wl < Dl; ++wl)
+          for (int wr = 0; wr < Dr; ++wr) {
+            long src = off + (((long)so * d + si) * Dl + wl) * Dr + wr;
+            m->W[s][(((long)wl * Dr + wr) * d + so) * d + si] = cd(mpo[2 * src], mpo[2 * src + 1]);
+          }
+    off += n;
+  }
+  m->n_jump = n_jump;
+  for (int j = 0; j < n_jump; ++j) {
+    if (jump_site[j] < 0 || jump_site[j] >= L) {
+      delete m;
+      return fail(nullptr, TJM_E_INVAL, "jump site out of range");
+    }
+    if (!std::isfinite(rate[j]) || rate[j] < 0.0) {
+      delete m;
+      return fail(nullptr, TJM_E_INVAL, "jump rates must be finite and >= 0");
+    }
+    if (!finite_arr(jump_op + 8L * j, 8)) {
+      delete m;
+      return fail(nullptr, TJM_E_INVAL, "jump operator has non-finite entries");
+    }
+    m->jsite.push_back(jump_site[j]);
+    m->jrate.push_back(rate[j]);
+    for (int e = 0; e < 4; ++e) m->jop.push_back(cd(jump_op[8L * j + 2 * e], jump_op[8L * j + 2 * e + 1]));
+  }
+  m->init.assign((size_t)L * d, cd(0, 0));
+  for (int s = 0; s < L; ++s) m->init[(size_t)s * d] = 1.0;
+  *out = m;
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_set_initial_product(tjm_model* m, const double* v) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (!v) return fail(m, TJM_E_INVAL, "site_vec is NULL");
+  if (!finite_arr(v, 2L * m->L * m->d)) return fail(m, TJM_E_INVAL, "site vectors must be finite");
+  for (int s = 0; s < m->L; ++s) {
+    double n2 = 0;
+    for (int q = 0; q < m->d; ++q) n2 += v[2 * (s * m->d + q)] * v[2 * (s * m->d + q)] + v[2 * (s * m->d + q) + 1] * v[2 * (s * m->d + q) + 1];
+    if (!(n2 > 0.0)) return fail(m, TJM_E_INVAL, "a site vector is zero");
+    const double f = 1.0 / std::sqrt(n2);
+    for (int q = 0; q < m->d; ++q)
+      m->init[(size_t)s * m->d + q] = f * cd(v[2 * (s * m->d + q)], v[2 * (s * m->d + q) + 1]);
+  }
+  return TJM_OK;
+}
+
+// exp(-tau/2 G) for a 2x2 Hermitian G = [[a, b], [conj b, c]]:
+// -tau/2 G = mu I + N with N traceless, N^2 = rho^2 I, so
+// exp = e^mu (cosh(rho) I + sinh(rho)/rho N).
+static void dissipator2(const cd G[4], double tau, cd out[4]) {
+  const double a = G[0].real(), c = G[3].real();
+  const double f = -0.5 * tau;
+  const double mu = f * 0.5 * (a + c);
+  const cd n00 = f * 0.5 * (a - c), n01 = f * G[1], n10 = f * G[2];
+  const double rho = std::sqrt(std::norm(n00) + std::norm(n01));
+  const double ch = std::cosh(rho);
+  const double sr = rho > 1e-8 ? std::sinh(rho) / rho : 1.0 + rho * rho / 6.0;
+  const double e = std::exp(mu);
+  out[0] = e * (ch + sr * n00);
+  out[1] = e * (sr * n01);
+  out[2] = e * (sr * n10);
+  out[3] = e * (ch - sr * n00);
+}
+
+static void free_run(Run* r) {
+  if (!r) return;
+  for (void* p : r->allocs) (void)hipFree(p);
+  if (r->ev0) (void)hipEventDestroy(r->ev0);
+  if (r->ev1) (void)hipEventDestroy(r->ev1);
+  if (r->stream) (void)hipStreamDestroy(r->stream);
+  delete r;
+}
+
+template <typename T>
+static hipError_t upload(Run* r, const std::vector<T>& h, T** dptr) {
+  size_t n = std::max<size_t>(h.size(), 1) * sizeof(T);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) return e;
+  r->allocs.push_back(p);
+  r->bytes += n;
+  if (!h.empty()) e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  *dptr = (T*)p;
+  return e;
+}
+
+static hipError_t dalloc(Run* r, size_t n, void** dptr) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(n, 16));
+  if (e != hipSuccess) return e;
+  r->allocs.push_back(p);
+  r->bytes += n;
+  e = hipMemset(p, 0, std::max<size_t>(n, 16));
+  *dptr = p;
+  return e;
+}
+
+static long align256(long x) { return (x + 255) & ~255L; }
+
+extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double T, int chi_max,
+                                    int n_obs, const int* obs_site, const double* obs_op,
+                                    uint64_t seed, const tjm_options* opt_in) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (m->run) return fail(m, TJM_E_BUSY, "a run is already in progress on this model");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  const int L = m->L, d = m->d;
+  if (n_traj < 1) return fail(m, TJM_E_INVAL, "n_traj must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m, TJM_E_INVAL, "dt must be > 0");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(m, TJM_E_INVAL, "T must be > 0");
+  const double ratio = T / dt;
+  const long n = std::lround(ratio);
+  if (n < 1 || std::fabs(ratio - (double)n) > 1e-9 * std::max(1.0, ratio))
+    return fail(m, TJM_E_INVAL, "T / dt must be a positive integer");
+  if (n > 1000000) return fail(m, TJM_E_INVAL, "too many steps");
+  if (chi_max < 1) return fail(m, TJM_E_INVAL, "chi_max must be >= 1");
+  if (opt.precision != TJM_PREC_FP64 && opt.precision != TJM_PREC_MIXED)
+    return fail(m, TJM_E_INVAL, "unknown precision");
+  const int chi_cap = opt.chi_cap > 0 ? opt.chi_cap : chi_max;
+  if (chi_cap > 64) return fail(m, TJM_E_UNSUPPORTED, "chi_cap above 64 is not supported");
+  if (opt.krylov_max < 1 || opt.krylov_max > 32) return fail(m, TJM_E_INVAL, "krylov_max must be in 1..32");
+  if (!std::isfinite(opt.svd_discard) || !std::isfinite(opt.deg_tol) || opt.deg_tol < 0)
+    return fail(m, TJM_E_INVAL, "svd_discard / deg_tol must be finite");
+  if (n_obs < 0 || (n_obs > 0 && (!obs_site || !obs_op))) return fail(m, TJM_E_INVAL, "bad observables");
+  for (int i = 0; i < n_obs; ++i)
+    if (obs_site[i] < 0 || obs_site[i] >= L) return fail(m, TJM_E_INVAL, "observable site out of range");
+  if (n_obs > 0 && !finite_arr(obs_op, 2L * n_obs * d * d)) return fail(m, TJM_E_INVAL, "observable not finite");
+  if ((double)n_traj * (double)(n + 1) * std::max(n_obs, 1) > 4e9)
+    return fail(m, TJM_E_INVAL, "output too large");
+  double tol = opt.krylov_tol;
+  if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-10 : 1e-12;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(m, TJM_E_DEVICE, "no HIP device");
+  if (opt.device < 0 || opt.device >= ndev) return fail(m, TJM_E_INVAL, "device ordinal out of range");
+  HIPCHK(m, hipSetDevice(opt.device));
+
+  Run* r = new Run();
+  r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = n_obs; r->record_bonds = opt.record_bonds ? 1 : 0;
+  TjmParams& P = r->P;
+  std::memset(&P, 0, sizeof(P));
+  P.L = L; P.d = d;
+  P.Dmax = *std::max_element(m->mpoD.begin(), m->mpoD.end());
+  P.n_traj = n_traj; P.n_steps = (int)n;
+  P.chi_max = chi_max; P.chi_cap = chi_cap; P.krylov_max = opt.krylov_max;
+  P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = r->record_bonds;
+  P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
+  P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
+  P.seed = seed; P.traj_base = opt.traj_base;
+
+  auto bail = [&](tjm_status st, const std::string& msg) {
+    free_run(r);
+    return fail(m, st, msg);
+  };
+#define RCHK(expr)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return bail(e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,                      \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+  // ---- MPO mixing tables -------------------------------------------------
+  const int Dm = P.Dmax;
+  std::vector<MixEnt> ents;
+  std::vector<int> mixL_ptr((size_t)L * (Dm * d + 1)), mixR_ptr((size_t)L * (Dm * d + 1));
+  std::vector<int> mix2_ptr((size_t)std::max(L - 1, 1) * (Dm * d * d + 1), 0);
+  auto push = [&](int w, int s, cd v) {
+    MixEnt e; e.w = w; e.s = s; e.re = v.real(); e.im = v.imag();
+    ents.push_back(e);
+  };
+  for (int s = 0; s < L; ++s) {
+    const int Dl = m->mpoD[s], Dr = m->mpoD[s + 1];
+    const auto& W = m->W[s];
+    auto at = [&](int wl, int wr, int so, int si) { return W[(((long)wl * Dr + wr) * d + so) * d + si]; };
+    int* rp = &mixL_ptr[(size_t)s * (Dm * d + 1)];
+    for (int row = 0; row <= Dm * d; ++row) {
+      rp[row] = (int)ents.size();
+      if (row == Dm * d || row >= Dr * d) continue;
+      const int wr = row / d, so = row % d;
+      for (int wl = 0; wl < Dl; ++wl)
+        for (int si = 0; si < d; ++si)
+          if (at(wl, wr, so, si) != cd(0, 0)) push(wl, si, at(wl, wr, so, si));
+    }
+    rp = &mixR_ptr[(size_t)s * (Dm * d + 1)];
+    for (int row = 0; row <= Dm * d; ++row) {
+      rp[row] = (int)ents.size();
+      if (row == Dm * d || row >= Dl * d) continue;
+      const int wl = row / d, so = row % d;
+      for (int wr = 0; wr < Dr; ++wr)
+        for (int si = 0; si < d; ++si)
+          if (at(wl, wr, so, si) != cd(0, 0)) push(wr, si, at(wl, wr, so, si));
+    }
+  }
+  for (int s = 0; s + 1 < L; ++s) {
+    const int Dl = m->mpoD[s], Du = m->mpoD[s + 1], Dr = m->mpoD[s + 2];
+    const auto& W1 = m->W[s];
+    const auto& W2 = m->W[s + 1];
+    int* rp = &mix2_ptr[(size_t)s * (Dm * d * d + 1)];
+    for (int row = 0; row <= Dm * d * d; ++row) {
+      rp[row] = (int)ents.size();
+      if (row == Dm * d * d || row >= Dr * d * d) continue;
+      const int wr = row / (d * d), s1o = (row / d) % d, s2o = row % d;
+      for (int wl = 0; wl < Dl; ++wl)
+        for (int s1 = 0; s1 < d; ++s1)
+          for (int s2 = 0; s2 < d; ++s2) {
+            cd v = 0;
+            for (int u = 0; u < Du; ++u)
+              v += W1[(((long)wl * Du + u) * d + s1o) * d + s1] * W2[(((long)u * Dr + wr) * d + s2o) * d + s2];
+            if (v != cd(0, 0)) push(wl, s1 * d + s2, v);
+          }
+    }
+  }
+
+  // ---- dissipators, jumps, observables ------------------------------------
+  std::vector<double> Dh((size_t)L * 8), Df((size_t)L * 8);
+  for (int s = 0; s < L; ++s) {
+    cd G[4] = {0, 0, 0, 0};
+    for (int j = 0; j < m->n_jump; ++j) {
+      if (m->jsite[j] != s) continue;
+      const cd* Lj = &m->jop[(size_t)j * 4];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          for (int c = 0; c < 2; ++c) G[a * 2 + b] += m->jrate[j] * std::conj(Lj[c * 2 + a]) * Lj[c * 2 + b];
+    }
+    cd h[4], f[4];
+    dissipator2(G, 0.5 * dt, h);
+    dissipator2(G, dt, f);
+    for (int e = 0; e < 4; ++e) {
+      Dh[(size_t)s * 8 + 2 * e] = h[e].real(); Dh[(size_t)s * 8 + 2 * e + 1] = h[e].imag();
+      Df[(size_t)s * 8 + 2 * e] = f[e].real(); Df[(size_t)s * 8 + 2 * e + 1] = f[e].imag();
+    }
+  }
+  std::vector<int> jptr(L + 1, 0), jidx;
+  for (int s = 0; s < L; ++s) {
+    jptr[s] = (int)jidx.size();
+    for (int j = 0; j < m->n_jump; ++j)
+      if (m->jsite[j] == s) jidx.push_back(j);
+  }
+  jptr[L] = (int)jidx.size();
+  std::vector<int> optr(L + 1, 0), oidx;
+  for (int s = 0; s < L; ++s) {
+    optr[s] = (int)oidx.size();
+    for (int o = 0; o < n_obs; ++o)
+      if (obs_site[o] == s) oidx.push_back(o);
+  }
+  optr[L] = (int)oidx.size();
+  std::vector<double> jopd(m->jop.size() * 2), initd(m->init.size() * 2);
+  for (size_t i = 0; i < m->jop.size(); ++i) { jopd[2 * i] = m->jop[i].real(); jopd[2 * i + 1] = m->jop[i].imag(); }
+  for (size_t i = 0; i < m->init.size(); ++i) { initd[2 * i] = m->init[i].real(); initd[2 * i + 1] = m->init[i].imag(); }
+  std::vector<double> obsd(obs_op ? obs_op : (const double*)nullptr,
+                           obs_op ? obs_op + 2L * n_obs * d * d : (const double*)nullptr);
+
+  // ---- MPS layout: bond b holds at most min(chi_cap, d^b, d^(L-b)) ----------
+  std::vector<int> bcap(L + 1);
+  for (int b = 0; b <= L; ++b) {
+    long c1 = 1, c2 = 1;
+    for (int i = 0; i < b && c1 < chi_cap; ++i) c1 *= d;
+    for (int i = 0; i < L - b && c2 < chi_cap; ++i) c2 *= d;
+    bcap[b] = (int)std::min<long>(chi_cap, std::min(c1, c2));
+  }
+  std::vector<long> soff(L + 1, 0);
+  for (int s = 0; s < L; ++s) soff[s + 1] = soff[s] + (long)bcap[s] * d * bcap[s + 1];
+  P.mps_cap = std::max<long>(soff[L], 1);
+  const int chic = *std::max_element(bcap.begin(), bcap.end());
+
+  // ---- worker scratch layout ---------------------------------------------
+  const long csz = P.mixed ? 8 : 16;
+  P.vec_cap = (long)chic * chic * d * d;
+  P.env_cap = (long)Dm * chic * chic;
+  P.t_cap = (long)Dm * P.vec_cap;
+  P.mat_cap = (long)d * chic * d * chic;
+  long o = 0;
+  P.off_env = o; o = align256(o + (long)(L + 2) * P.env_cap * csz);
+  P.off_smps = o; o = align256(o + P.mps_cap * 16);
+  P.off_Q = o; o = align256(o + (long)opt.krylov_max * P.vec_cap * 16);
+  P.off_w = o; o = align256(o + P.vec_cap * 16);
+  P.off_v = o; o = align256(o + P.vec_cap * 16);
+  P.off_T1 = o; o = align256(o + P.t_cap * csz);
+  P.off_T2 = o; o = align256(o + P.t_cap * csz);
+  P.off_X = o; o = align256(o + P.mat_cap * 16);
+  P.off_Y = o; o = align256(o + P.mat_cap * 16);
+  P.off_Z = o; o = align256(o + P.mat_cap * 16);
+  P.off_C = o; o = align256(o + P.mat_cap * 16);
+  P.off_wts = o; o = align256(o + (long)std::max(m->n_jump, 1) * 8);
+  P.scratch_stride = o;
+
+  // ---- worker count --------------------------------------------------------
+  hipDeviceProp_t prop;
+  RCHK(hipGetDeviceProperties(&prop, opt.device));
+  int bpc = 1;
+  RCHK(tjm_blocks_per_cu(P.mixed, L, &bpc));
+  if (bpc < 1) return bail(TJM_E_UNSUPPORTED, "kernel does not fit on a compute unit");
+  long workers = (long)bpc * prop.multiProcessorCount;
+  if (opt.workers > 0) workers = std::min<long>(workers, opt.workers);
+  workers = std::min<long>(workers, n_traj);
+  size_t freeb = 0, totalb = 0;
+  RCHK(hipMemGetInfo(&freeb, &totalb));
+  const double per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_obs * 8.0 + 2.0 * n * 4 +
+                          (r->record_bonds ? (double)n * (L + 1) * 4 : 0.0) + 8 * 8 + 4;
+  const double avail = 0.85 * (double)freeb - per_traj * n_traj;
+  if (avail < (double)P.scratch_stride) return bail(TJM_E_NOMEM, "not enough device memory for the run");
+  workers = std::min<long>(workers, (long)(avail / (double)P.scratch_stride));
+  r->workers = (int)std::max<long>(workers, 1);
+
+  // ---- uploads ---------------------------------------------------------------
+  RCHK(upload(r, m->mpoD, (int**)&P.mpoD));
+  MixEnt* dents = nullptr;
+  RCHK(upload(r, ents, &dents));
+  P.mixL = dents; P.mixR = dents; P.mix2 = dents;
+  RCHK(upload(r, mixL_ptr, (int**)&P.mixL_ptr));
+  RCHK(upload(r, mixR_ptr, (int**)&P.mixR_ptr));
+  RCHK(upload(r, mix2_ptr, (int**)&P.mix2_ptr));
+  RCHK(upload(r, Dh, (double**)&P.Dhalf));
+  RCHK(upload(r, Df, (double**)&P.Dfull));
+  RCHK(upload(r, jopd, (double**)&P.jump_op));
+  RCHK(upload(r, m->jrate, (double**)&P.jump_rate));
+  RCHK(upload(r, m->jsite, (int**)&P.jump_site));
+  RCHK(upload(r, jptr, (int**)&P.jptr));
+  RCHK(upload(r, jidx, (int**)&P.jidx));
+  RCHK(upload(r, optr, (int**)&P.optr));
+  RCHK(upload(r, oidx, (int**)&P.oidx));
+  RCHK(upload(r, obsd, (double**)&P.obs_op));
+  RCHK(upload(r, initd, (double**)&P.init_sites));
+  RCHK(upload(r, soff, (long**)&P.site_off));
+  RCHK(upload(r, bcap, (int**)&P.bond_cap));
+  void* p = nullptr;
+  RCHK(dalloc(r, (size_t)n_traj * P.mps_cap * 16, &p)); P.mps = (double*)p;
+  RCHK(dalloc(r, (size_t)n_traj * (L + 1) * 4, &p)); P.bonds = (int*)p;
+  RCHK(dalloc(r, (size_t)n_traj * (n + 1) * std::max(n_obs, 1) * 8, &p)); P.obs = (double*)p; r->d_obs = P.obs;
+  RCHK(dalloc(r, (size_t)n_traj * 2 * n * 4, &p)); P.jlog = (int*)p; r->d_jlog = P.jlog;
+  if (r->record_bonds) {
+    RCHK(dalloc(r, (size_t)n_traj * n * (L + 1) * 4, &p)); P.blog = (int*)p; r->d_blog = P.blog;
+  }
+  RCHK(dalloc(r, (size_t)n_traj * 8 * 8, &p)); P.tstats = (unsigned long long*)p; r->d_stats = P.tstats;
+  RCHK(dalloc(r, (size_t)n_traj * 4, &p)); P.tflags = (int*)p; r->d_flags = P.tflags;
+  RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
+  RCHK(dalloc(r, 256, &p)); P.counter = (int*)p;
+
+  RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+  RCHK(hipEventCreate(&r->ev0));
+  RCHK(hipEventCreate(&r->ev1));
+
+  // ---- F_0 ------------------------------------------------------------------
+  RCHK(tjm_launch_reset(P.counter, r->stream));
+  RCHK(hipEventRecord(r->ev0, r->stream));
+  RCHK(tjm_launch_step(P, 0, r->workers, r->stream));
+  RCHK(hipEventRecord(r->ev1, r->stream));
+  RCHK(hipStreamSynchronize(r->stream));
+  float ms = 0;
+  RCHK(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+  r->init_ms = ms;
+  m->run = r;
+#undef RCHK
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_run_advance(tjm_model* m, int steps) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  Run* r = m->run;
+  if (!r) return fail(m, TJM_E_BUSY, "no run in progress");
+  if (steps < 0 || r->steps_done + steps > r->n_steps) return fail(m, TJM_E_BUSY, "advance past the last step");
+  for (int i = 0; i < steps; ++i) {
+    const int k = r->steps_done + 1;
+    HIPCHK(m, tjm_launch_reset(r->P.counter, r->stream));
+    HIPCHK(m, hipEventRecord(r->ev0, r->stream));
+    HIPCHK(m, tjm_launch_step(r->P, k, r->workers, r->stream));
+    HIPCHK(m, hipEventRecord(r->ev1, r->stream));
+    HIPCHK(m, hipStreamSynchronize(r->stream));
+    float ms = 0;
+    HIPCHK(m, hipEventElapsedTime(&ms, r->ev0, r->ev1));
+    r->step_ms_last = ms;
+    r->step_ms_total += ms;
+    r->step_launches++;
+    r->steps_done = k;
+  }
+  return TJM_OK;
+}
+
+static void collect_stats(tjm_model* m, Run* r) {
+  tjm_stats& s = m->last;
+  std::memset(&s, 0, sizeof(s));
+  s.n_traj = r->n_traj; s.n_steps = r->n_steps; s.steps_done = r->steps_done; s.workers = r->workers;
+  s.init_kernel_ms = r->init_ms;
+  s.step_kernel_ms_total = r->step_ms_total;
+  s.step_kernel_ms_last = r->step_ms_last;
+  s.step_launches = r->step_launches;
+  s.device_bytes = r->bytes;
+  std::vector<unsigned long long> st((size_t)r->n_traj * 8);
+  if (hipMemcpy(st.data(), r->d_stats, st.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return;
+  for (int t = 0; t < r->n_traj; ++t) {
+    const unsigned long long* q = &st[(size_t)t * 8];
+    s.cmac_mfma += q[TJM_ST_CMAC_MFMA]; s.cmac_mix += q[TJM_ST_CMAC_MIX];
+    s.krylov_iters += q[TJM_ST_KRYLOV]; s.expm_calls += q[TJM_ST_EXPM];
+    s.one_site += q[TJM_ST_ONE_SITE]; s.two_site += q[TJM_ST_TWO_SITE];
+    s.factorizations += q[TJM_ST_FACT]; s.jumps += q[TJM_ST_JUMPS];
+  }
+}
+
+extern "C" tjm_status tjm_get_stats(const tjm_model* m, tjm_stats* out) {
+  if (!m || !out) return fail(nullptr, TJM_E_INVAL, "NULL argument");
+  if (m->run) collect_stats(const_cast<tjm_model*>(m), m->run);
+  *out = m->last;
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_run_end(tjm_model* m, double* mean, double* sem, double* per_traj_obs,
+                                  int32_t* jump_log, int32_t* bond_log) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  Run* r = m->run;
+  if (!r) return fail(m, TJM_E_BUSY, "no run in progress");
+  tjm_status st = TJM_OK;
+  std::string msg;
+  const int entries = (r->n_steps + 1) * r->n_obs;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == TJM_OK) {
+      st = TJM_E_DEVICE;
+      msg = std::string(what) + ": " + hipGetErrorString(e);
+    }
+  };
+  if (r->steps_done != r->n_steps) { st = TJM_E_BUSY; msg = "run ended before its last step"; }
+  if (st == TJM_OK && entries > 0 && (mean || sem)) {
+    double *dm = nullptr, *ds = nullptr;
+    chk(hipMalloc((void**)&dm, entries * 8), "hipMalloc");
+    chk(hipMalloc((void**)&ds, entries * 8), "hipMalloc");
+    if (st == TJM_OK) {
+      chk(tjm_launch_reduce(r->d_obs, r->n_traj, entries, dm, ds, r->stream), "reduce");
+      chk(hipStreamSynchronize(r->stream), "sync");
+      if (mean) chk(hipMemcpy(mean, dm, entries * 8, hipMemcpyDeviceToHost), "copy mean");
+      if (sem) chk(hipMemcpy(sem, ds, entries * 8, hipMemcpyDeviceToHost), "copy sem");
+    }
+    if (dm) (void)hipFree(dm);
+    if (ds) (void)hipFree(ds);
+  }
+  if (st == TJM_OK && per_traj_obs && entries > 0)
+    chk(hipMemcpy(per_traj_obs, r->d_obs, (size_t)r->n_traj * entries * 8, hipMemcpyDeviceToHost), "copy obs");
+  if (st == TJM_OK && jump_log)
+    chk(hipMemcpy(jump_log, r->d_jlog, (size_t)r->n_traj * 2 * r->n_steps * 4, hipMemcpyDeviceToHost), "copy jlog");
+  if (st == TJM_OK && bond_log) {
+    if (!r->d_blog) { st = TJM_E_INVAL; msg = "bond_log requested without record_bonds"; }
+    else chk(hipMemcpy(bond_log, r->d_blog, (size_t)r->n_traj * r->n_steps * (m->L + 1) * 4, hipMemcpyDeviceToHost), "copy blog");
+  }
+  if (st == TJM_OK) {
+    std::vector<int> fl(r->n_traj);
+    chk(hipMemcpy(fl.data(), r->d_flags, (size_t)r->n_traj * 4, hipMemcpyDeviceToHost), "copy flags");
+    for (int t = 0; t < r->n_traj && st == TJM_OK; ++t)
+      if (fl[t]) { st = TJM_E_NUMERIC; msg = "non-finite norm in trajectory " + std::to_string(t); }
+  }
+  collect_stats(m, r);
+  free_run(r);
+  m->run = nullptr;
+  if (st != TJM_OK) return fail(m, st, msg);
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_run_traces(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                                     const int* obs_site, const double* obs_op, uint64_t seed,
+                                     const tjm_options* opt, double* mean, double* sem, double* per_traj_obs,
+                                     int32_t* jump_log, int32_t* bond_log) {
+  tjm_status st = tjm_run_begin(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt);
+  if (st != TJM_OK) return st;
+  st = tjm_run_advance(m, m->run->n_steps);
+  if (st != TJM_OK) {
+    std::string keep = m->err;
+    tjm_run_end(m, nullptr, nullptr, nullptr, nullptr, nullptr);
+    m->err = keep;
+    return st;
+  }
+  return tjm_run_end(m, mean, sem, per_traj_obs, jump_log, bond_log);
+}
+
+extern "C" tjm_status tjm_run(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                              const int* obs_site, const double* obs_op, uint64_t seed,
+                              const tjm_options* opt, double* mean, double* sem) {
+  return tjm_run_traces(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt, mean, sem,
+                        nullptr, nullptr, nullptr);
+}
+
+extern "C" const char* tjm_last_error(const tjm_model* m) {
+  return m ? m->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" void tjm_destroy(tjm_model* m) {
+  if (!m) return;
+  free_run(m->run);
+  delete m;
+}
+
+// --------------------------------------------------------------------------
+// self-test entry points
+// --------------------------------------------------------------------------
+namespace {
+struct DevScope {
+  std::vector<void*> ps;
+  ~DevScope() { for (void* p : ps) (void)hipFree(p); }
+  template <typename T> hipError_t put(const T* h, long n, T** d) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<long>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    ps.push_back(p);
+    *d = (T*)p;
+    if (h && n > 0) return hipMemcpy(p, h, n * sizeof(T), hipMemcpyHostToDevice);
+    return hipMemset(p, 0, std::max<long>(n, 1) * sizeof(T));
+  }
+};
+}  // namespace
+
+#define STCHK(expr)                                                         \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) return fail(nullptr, TJM_E_DEVICE, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" tjm_status tjm_selftest_cgemm(int precision, int M, int N, int K, int nb, int sum_batches,
+                                         const double* A, int lda, long bsA, int transA, int conjA,
+                                         const double* B, int ldb, long bsB, int transB, int conjB,
+                                         double* C, int ldc, long csC, int accumulate,
+                                         long a_elems, long b_elems, long c_elems) {
+  if (M < 1 || N < 1 || K < 1 || M > 512 || N > 512 || K > 512 || nb < 1 || nb > 16)
+    return fail(nullptr, TJM_E_INVAL, "gemm sizes out of range");
+  if (!A || !B || !C || a_elems < 1 || b_elems < 1 || c_elems < 1) return fail(nullptr, TJM_E_INVAL, "NULL buffer");
+  // every addressed element must be inside the buffers
+  long amax = (long)(nb - 1) * bsA + (transA ? (long)(K - 1) * lda + (M - 1) : (long)(M - 1) * lda + (K - 1));
+  long bmax = (long)(nb - 1) * bsB + (transB ? (long)(N - 1) * ldb + (K - 1) : (long)(K - 1) * ldb + (N - 1));
+  long cmax = (long)(sum_batches ? 0 : nb - 1) * csC + (long)(M - 1) * ldc + (N - 1);
+  if (amax >= a_elems || bmax >= b_elems || cmax >= c_elems || bsA < 0 || bsB < 0 || csC < 0)
+    return fail(nullptr, TJM_E_INVAL, "gemm operand out of buffer bounds");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  DevScope ds;
+  double *dA, *dB, *dC;
+  STCHK(ds.put(A, 2 * a_elems, &dA));
+  STCHK(ds.put(B, 2 * b_elems, &dB));
+  STCHK(ds.put(C, 2 * c_elems, &dC));
+  STCHK(tjm_launch_st_cgemm(precision == TJM_PREC_MIXED, M, N, K, nb, sum_batches, dA, lda, bsA, transA, conjA,
+                            dB, ldb, bsB, transB, conjB, dC, ldc, csC, accumulate));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipMemcpy(C, dC, 2 * c_elems * 8, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_selftest_qr(int m, int n, const double* X, double* Q, double* R) {
+  if (m < 1 || n < 1 || m > 128 || n > 128 || !X || !Q || !R) return fail(nullptr, TJM_E_INVAL, "qr sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  const int k = std::min(m, n);
+  DevScope ds;
+  double *dX, *dQ, *dR;
+  STCHK(ds.put(X, 2L * m * n, &dX));
+  STCHK(ds.put((const double*)nullptr, 2L * m * k, &dQ));
+  STCHK(ds.put((const double*)nullptr, 2L * k * n, &dR));
+  STCHK(tjm_launch_st_qr(m, n, dX, dQ, dR));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipMemcpy(Q, dQ, 2L * m * k * 8, hipMemcpyDeviceToHost));
+  STCHK(hipMemcpy(R, dR, 2L * k * n * 8, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_selftest_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
+                                       int absorb_left, double* left, double* right, double* S, int* k) {
+  if (m < 1 || n < 1 || std::min(m, n) > 128 || std::max(m, n) > 256 || cap < 1 || !G || !left || !right || !S || !k)
+    return fail(nullptr, TJM_E_INVAL, "svd sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  const int nc = std::min(m, n), p = std::max(m, n);
+  DevScope ds;
+  double *dG, *dl, *dr, *dS, *dW, *dV;
+  int* dk;
+  STCHK(ds.put(G, 2L * m * n, &dG));
+  STCHK(ds.put((const double*)nullptr, 2L * m * nc, &dl));
+  STCHK(ds.put((const double*)nullptr, 2L * nc * n, &dr));
+  STCHK(ds.put((const double*)nullptr, nc, &dS));
+  STCHK(ds.put((const double*)nullptr, 2L * p * nc, &dW));
+  STCHK(ds.put((const double*)nullptr, 2L * nc * nc, &dV));
+  STCHK(ds.put((const int*)nullptr, 1, &dk));
+  STCHK(tjm_launch_st_svd(m, n, dG, discard, cap, deg_tol, absorb_left, dl, dr, dS, dk, dW, dV));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipMemcpy(k, dk, 4, hipMemcpyDeviceToHost));
+  const int kk = *k;
+  STCHK(hipMemcpy(left, dl, 2L * m * kk * 8, hipMemcpyDeviceToHost));
+  STCHK(hipMemcpy(right, dr, 2L * kk * n * 8, hipMemcpyDeviceToHost));
+  STCHK(hipMemcpy(S, dS, (long)kk * 8, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_selftest_expm(int n, const double* H, const double* v, double t, int krylov_max,
+                                        double tol, double* out, int* iters) {
+  if (n < 1 || n > 512 || krylov_max < 1 || krylov_max > 32 || !H || !v || !out || !iters)
+    return fail(nullptr, TJM_E_INVAL, "expm sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  DevScope ds;
+  double *dH, *dv, *dQ, *dw;
+  int* dit;
+  STCHK(ds.put(H, 2L * n * n, &dH));
+  STCHK(ds.put(v, 2L * n, &dv));
+  STCHK(ds.put((const double*)nullptr, 2L * n * krylov_max, &dQ));
+  STCHK(ds.put((const double*)nullptr, 2L * n, &dw));
+  STCHK(ds.put((const int*)nullptr, 1, &dit));
+  STCHK(tjm_launch_st_expm(n, dH, dv, t, krylov_max, tol, dQ, dw, dit));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipMemcpy(out, dv, 2L * n * 8, hipMemcpyDeviceToHost));
+  STCHK(hipMemcpy(iters, dit, 4, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_selftest_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out) {
+  if (count < 1 || count > (1 << 20) || !ctr || !out) return fail(nullptr, TJM_E_INVAL, "philox sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  DevScope ds;
+  uint32_t *dc, *dout;
+  STCHK(ds.put(ctr, 4L * count, &dc));
+  STCHK(ds.put((const uint32_t*)nullptr, 4L * count, &dout));
+  STCHK(tjm_launch_st_philox(count, dc, k0, k1, dout));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipMemcpy(out, dout, 16L * count, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}

@@ -1,0 +1,27 @@
+// Host-side interface between the C ABI (tjm_api.cpp) and the kernels
+// (tjm_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "tjm_params.h"
+
+size_t tjm_dyn_lds_bytes(int L);
+hipError_t tjm_blocks_per_cu(int mixed, int L, int* blocks);
+hipError_t tjm_launch_reset(int* counter, hipStream_t s);
+// k = 0: F_0 and t = 0 observables; k >= 1: step function k
+hipError_t tjm_launch_step(const TjmParams& P, int k, int workers, hipStream_t s);
+// mean / standard error over trajectories of obs[n_traj][entries], fixed order
+hipError_t tjm_launch_reduce(const double* obs, int n_traj, int entries, double* mean,
+                             double* sem, hipStream_t s);
+
+hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_batches,
+                               const double* A, int lda, long bsA, int transA, int conjA,
+                               const double* B, int ldb, long bsB, int transB, int conjB,
+                               double* C, int ldc, long csC, int accumulate);
+hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R);
+hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
+                             int absorb_left, double* left, double* right, double* S, int* k,
+                             double* Wc, double* Vc);
+hipError_t tjm_launch_st_expm(int n, const double* H, double* v, double t, int kmax, double tol,
+                              double* Q, double* w, int* iters);
+hipError_t tjm_launch_st_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
+                                uint32_t* out);

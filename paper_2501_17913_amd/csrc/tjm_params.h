@@ -1,0 +1,86 @@
+// Run description shared by the host runtime and the device kernels.
+// All pointers are device pointers; all complex arrays are interleaved
+// (re, im) doubles unless a field says otherwise.
+#pragma once
+#include <stdint.h>
+
+// One nonzero of a local MPO block, seen from an output row: the source
+// virtual channel w, the source physical index s (s1*d+s2 for two sites)
+// and the value.
+struct MixEnt {
+  int w;
+  int s;
+  double re, im;
+};
+
+struct TjmParams {
+  // sizes and options
+  int L, d, Dmax;
+  int n_traj, n_steps;
+  int chi_max, chi_cap, krylov_max;
+  int n_jump, n_obs;
+  int record_bonds;
+  int mixed;                         // 1: complex-FP32 contractions
+  double dt, krylov_tol, svd_discard, deg_tol;
+  uint64_t seed;
+  uint32_t traj_base;                // global id of trajectory 0 of this run
+
+  // model tables
+  const int* mpoD;                   // [L+1] MPO bond dimensions
+  const int* mixL_ptr;               // [L][Dmax*d+1]      rows w'*d+s'  -> (w, s)
+  const MixEnt* mixL;
+  const int* mixR_ptr;               // [L][Dmax*d+1]      rows w*d+s'   -> (w', s)
+  const MixEnt* mixR;
+  const int* mix2_ptr;               // [L-1][Dmax*d*d+1]  rows w''*d*d+s1'*d+s2' -> (w, s1*d+s2)
+  const MixEnt* mix2;
+  const double* Dhalf;               // [L][d][d] complex: D_l[dt/2]
+  const double* Dfull;               // [L][d][d] complex: D_l[dt]
+  const double* jump_op;             // [n_jump][d][d] complex
+  const double* jump_rate;           // [n_jump]
+  const int* jump_site;              // [n_jump]
+  const int* jptr;                   // [L+1] CSR: jumps of site s are jidx[jptr[s]..jptr[s+1])
+  const int* jidx;
+  const int* optr;                   // [L+1] CSR of observables per site
+  const int* oidx;
+  const double* obs_op;              // [n_obs][d][d] complex
+  const double* init_sites;          // [L][d] complex product state
+
+  // layout of one trajectory MPS (complex doubles)
+  const long* site_off;              // [L+1]
+  long mps_cap;
+  const int* bond_cap;               // [L+1]
+
+  // per-trajectory state
+  double* mps;                       // [n_traj][mps_cap] complex
+  int* bonds;                        // [n_traj][L+1]
+  double* obs;                       // [n_traj][n_steps+1][n_obs]
+  int* jlog;                         // [n_traj][2*n_steps]
+  int* blog;                         // [n_traj][n_steps][L+1] (if record_bonds)
+  unsigned long long* tstats;        // [n_traj][8]
+  int* tflags;                       // [n_traj] nonzero: numerical failure
+
+  // per-worker scratch (byte offsets inside one worker's block)
+  char* scratch;
+  long scratch_stride;
+  long off_env, env_cap;             // (L+2) slots of env_cap complex (T_c)
+  long off_smps;                     // mps_cap complex doubles
+  long off_Q, vec_cap;               // krylov_max vectors of vec_cap complex doubles
+  long off_w, off_v;                 // vec_cap complex doubles each
+  long off_T1, off_T2, t_cap;        // t_cap complex (T_c) each
+  long off_X, off_Y, off_Z, off_C, mat_cap;   // mat_cap complex doubles each
+  long off_wts;                      // n_jump doubles
+
+  int* counter;                      // work queue head
+};
+
+// indices of the per-trajectory statistics
+enum {
+  TJM_ST_CMAC_MFMA = 0,   // complex multiply-adds issued to the matrix cores
+  TJM_ST_CMAC_MIX = 1,    // complex multiply-adds of the MPO mixing stage
+  TJM_ST_KRYLOV = 2,      // Lanczos iterations
+  TJM_ST_EXPM = 3,        // Lanczos exponentials
+  TJM_ST_ONE_SITE = 4,    // 1TDVP bond updates
+  TJM_ST_TWO_SITE = 5,    // 2TDVP bond updates
+  TJM_ST_FACT = 6,        // QR + SVD factorisations
+  TJM_ST_JUMPS = 7        // jumps applied
+};

@@ -1,0 +1,290 @@
+"""ctypes binding of libtjm.so (include/tjm.h, include/tjm_selftest.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Importing this module fails loudly if libtjm.so has not been
+built (python -m paper_2501_17913_amd.build).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtjm.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError("libtjm.so is not built: run python -m paper_2501_17913_amd.build")
+lib = C.CDLL(_LIB_PATH)
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_BUSY = range(7)
+PREC_FP64, PREC_MIXED = 0, 1
+STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NUMERIC",
+                5: "E_UNSUPPORTED", 6: "E_BUSY"}
+
+EXPORTED = [
+    "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_run", "tjm_run_traces",
+    "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_get_stats", "tjm_last_error",
+    "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
+    "tjm_selftest_expm", "tjm_selftest_philox",
+]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("chi_cap", C.c_int), ("svd_discard", C.c_double),
+                ("krylov_max", C.c_int), ("krylov_tol", C.c_double), ("deg_tol", C.c_double),
+                ("workers", C.c_int), ("record_bonds", C.c_int), ("traj_base", C.c_uint32),
+                ("device", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_traj", C.c_int), ("n_steps", C.c_int), ("steps_done", C.c_int), ("workers", C.c_int),
+                ("init_kernel_ms", C.c_double), ("step_kernel_ms_total", C.c_double),
+                ("step_kernel_ms_last", C.c_double), ("step_launches", C.c_int),
+                ("cmac_mfma", C.c_ulonglong), ("cmac_mix", C.c_ulonglong),
+                ("krylov_iters", C.c_ulonglong), ("expm_calls", C.c_ulonglong),
+                ("one_site", C.c_ulonglong), ("two_site", C.c_ulonglong),
+                ("factorizations", C.c_ulonglong), ("jumps", C.c_ulonglong),
+                ("device_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_up = C.POINTER(C.c_uint32)
+_vp = C.c_void_p
+
+lib.tjm_default_options.argtypes = [C.POINTER(Options)]
+lib.tjm_default_options.restype = None
+lib.tjm_create.argtypes = [C.POINTER(_vp), C.c_int, C.c_int, _ip, _dp, C.c_int, _ip, _dp, _dp]
+lib.tjm_create.restype = C.c_int
+lib.tjm_set_initial_product.argtypes = [_vp, _dp]
+lib.tjm_set_initial_product.restype = C.c_int
+lib.tjm_run.argtypes = [_vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_uint64,
+                        C.POINTER(Options), _dp, _dp]
+lib.tjm_run.restype = C.c_int
+lib.tjm_run_traces.argtypes = lib.tjm_run.argtypes + [_dp, _ip, _ip]
+lib.tjm_run_traces.restype = C.c_int
+lib.tjm_run_begin.argtypes = [_vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_uint64,
+                              C.POINTER(Options)]
+lib.tjm_run_begin.restype = C.c_int
+lib.tjm_run_advance.argtypes = [_vp, C.c_int]
+lib.tjm_run_advance.restype = C.c_int
+lib.tjm_run_end.argtypes = [_vp, _dp, _dp, _dp, _ip, _ip]
+lib.tjm_run_end.restype = C.c_int
+lib.tjm_get_stats.argtypes = [_vp, C.POINTER(Stats)]
+lib.tjm_get_stats.restype = C.c_int
+lib.tjm_last_error.argtypes = [_vp]
+lib.tjm_last_error.restype = C.c_char_p
+lib.tjm_destroy.argtypes = [_vp]
+lib.tjm_destroy.restype = None
+lib.tjm_selftest_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   _dp, C.c_int, C.c_long, C.c_int, C.c_int,
+                                   _dp, C.c_int, C.c_long, C.c_int, C.c_int,
+                                   _dp, C.c_int, C.c_long, C.c_int, C.c_long, C.c_long, C.c_long]
+lib.tjm_selftest_cgemm.restype = C.c_int
+lib.tjm_selftest_qr.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+lib.tjm_selftest_qr.restype = C.c_int
+lib.tjm_selftest_svd.argtypes = [C.c_int, C.c_int, _dp, C.c_double, C.c_int, C.c_double, C.c_int,
+                                 _dp, _dp, _dp, _ip]
+lib.tjm_selftest_svd.restype = C.c_int
+lib.tjm_selftest_expm.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, C.c_double, _dp, _ip]
+lib.tjm_selftest_expm.restype = C.c_int
+lib.tjm_selftest_philox.argtypes = [C.c_int, _up, C.c_uint32, C.c_uint32, _up]
+lib.tjm_selftest_philox.restype = C.c_int
+
+
+class TjmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _iptr(a):
+    return None if a is None else a.ctypes.data_as(_ip)
+
+
+def default_options(**kw):
+    o = Options()
+    lib.tjm_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Model:
+    """A TJM model: chain length, Hamiltonian MPO, jump operators (tjm_create)."""
+
+    def __init__(self, L, mpo, jump_sites, jump_ops, rates, d=2):
+        mpo = [_c128(W) for W in mpo]
+        bonds = np.array([1] + [W.shape[3] for W in mpo], dtype=np.int32)
+        if len(mpo) != L:
+            raise ValueError("need one MPO tensor per site")
+        flat = np.concatenate([W.reshape(-1) for W in mpo]) if mpo else np.zeros(1, np.complex128)
+        self._flat = flat
+        js = np.ascontiguousarray(jump_sites, dtype=np.int32)
+        jo = _c128(np.asarray(jump_ops).reshape(-1)) if len(js) else np.zeros(1, np.complex128)
+        rt = np.ascontiguousarray(rates, dtype=np.float64) if len(js) else np.zeros(1)
+        h = _vp()
+        st = lib.tjm_create(C.byref(h), int(L), int(d), _iptr(bonds), flat.view(np.float64).ctypes.data_as(_dp),
+                            int(len(js)), _iptr(js), jo.view(np.float64).ctypes.data_as(_dp), _dptr(rt))
+        if st != OK:
+            raise TjmError(st, lib.tjm_last_error(None).decode())
+        self.h = h
+        self.L = L
+        self.d = d
+
+    def _check(self, st):
+        if st != OK:
+            raise TjmError(st, lib.tjm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tjm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_initial_product(self, site_vecs):
+        v = _c128(site_vecs).reshape(-1)
+        self._check(lib.tjm_set_initial_product(self.h, v.view(np.float64).ctypes.data_as(_dp)))
+
+    @staticmethod
+    def _obs(observables):
+        sites = np.ascontiguousarray([s for s, _ in observables], dtype=np.int32)
+        ops = _c128(np.array([o for _, o in observables]).reshape(-1)) if observables else np.zeros(1, np.complex128)
+        return sites, ops
+
+    def run(self, n_traj, dt, T, chi_max, observables, seed, options=None, traces=False):
+        """Whole run; returns dict with mean, sem (and per_traj, jumps, bonds)."""
+        opt = options or default_options()
+        n = int(round(T / dt))
+        sites, ops = self._obs(observables)
+        no = len(observables)
+        mean = np.zeros((n + 1, no))
+        sem = np.zeros((n + 1, no))
+        out = {"mean": mean, "sem": sem}
+        if traces:
+            per = np.zeros((n_traj, n + 1, no))
+            jl = np.zeros((n_traj, 2 * n), dtype=np.int32)
+            bl = np.zeros((n_traj, n, self.L + 1), dtype=np.int32) if opt.record_bonds else None
+            st = lib.tjm_run_traces(self.h, n_traj, dt, T, chi_max, no, _iptr(sites),
+                                    ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt),
+                                    _dptr(mean), _dptr(sem), _dptr(per), _iptr(jl), _iptr(bl))
+            out.update(per_traj=per, jumps=jl, bonds=bl)
+        else:
+            st = lib.tjm_run(self.h, n_traj, dt, T, chi_max, no, _iptr(sites),
+                             ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt),
+                             _dptr(mean), _dptr(sem))
+        self._check(st)
+        out["stats"] = self.stats()
+        return out
+
+    def begin(self, n_traj, dt, T, chi_max, observables, seed, options=None):
+        opt = options or default_options()
+        sites, ops = self._obs(observables)
+        self._n = int(round(T / dt))
+        self._no = len(observables)
+        self._nt = n_traj
+        self._rec = bool(opt.record_bonds)
+        self._check(lib.tjm_run_begin(self.h, n_traj, dt, T, chi_max, self._no, _iptr(sites),
+                                      ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt)))
+
+    def advance(self, steps):
+        self._check(lib.tjm_run_advance(self.h, int(steps)))
+
+    def end(self, traces=False):
+        n, no, nt = self._n, self._no, self._nt
+        mean = np.zeros((n + 1, no))
+        sem = np.zeros((n + 1, no))
+        per = np.zeros((nt, n + 1, no)) if traces else None
+        jl = np.zeros((nt, 2 * n), dtype=np.int32) if traces else None
+        bl = np.zeros((nt, n, self.L + 1), dtype=np.int32) if (traces and self._rec) else None
+        self._check(lib.tjm_run_end(self.h, _dptr(mean), _dptr(sem), _dptr(per), _iptr(jl), _iptr(bl)))
+        return {"mean": mean, "sem": sem, "per_traj": per, "jumps": jl, "bonds": bl}
+
+    def stats(self):
+        s = Stats()
+        self._check(lib.tjm_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# self-test wrappers (one workgroup of the device building blocks)
+# ---------------------------------------------------------------------------
+
+def _st(status):
+    if status != OK:
+        raise TjmError(status, lib.tjm_last_error(None).decode())
+
+
+def selftest_cgemm(precision, M, N, K, A, B, C0=None, nb=1, sum_batches=True, lda=None, ldb=None, ldc=None,
+                   bsA=0, bsB=0, csC=0, transA=False, conjA=False, transB=False, conjB=False, accumulate=False):
+    A = _c128(A).reshape(-1)
+    B = _c128(B).reshape(-1)
+    if C0 is None:
+        C0 = np.zeros(max(1, (M * N) if sum_batches else nb * M * N), np.complex128)
+    Cb = _c128(C0).reshape(-1).copy()
+    lda = lda if lda is not None else (M if transA else K)
+    ldb = ldb if ldb is not None else (K if transB else N)
+    ldc = ldc if ldc is not None else N
+    _st(lib.tjm_selftest_cgemm(precision, M, N, K, nb, int(sum_batches),
+                               A.view(np.float64).ctypes.data_as(_dp), lda, bsA, int(transA), int(conjA),
+                               B.view(np.float64).ctypes.data_as(_dp), ldb, bsB, int(transB), int(conjB),
+                               Cb.view(np.float64).ctypes.data_as(_dp), ldc, csC, int(accumulate),
+                               A.size, B.size, Cb.size))
+    return Cb
+
+
+def selftest_qr(X):
+    X = _c128(X)
+    m, n = X.shape
+    k = min(m, n)
+    Q = np.zeros((m, k), np.complex128)
+    R = np.zeros((k, n), np.complex128)
+    _st(lib.tjm_selftest_qr(m, n, X.view(np.float64).ctypes.data_as(_dp),
+                            Q.view(np.float64).ctypes.data_as(_dp), R.view(np.float64).ctypes.data_as(_dp)))
+    return Q, R
+
+
+def selftest_svd(G, discard=1e-12, cap=1 << 30, deg_tol=1e-12, absorb_left=False):
+    G = _c128(G)
+    m, n = G.shape
+    nc = min(m, n)
+    left = np.zeros(m * nc, np.complex128)
+    right = np.zeros(nc * n, np.complex128)
+    S = np.zeros(nc)
+    k = C.c_int(0)
+    _st(lib.tjm_selftest_svd(m, n, G.view(np.float64).ctypes.data_as(_dp), discard, min(cap, 1 << 30), deg_tol,
+                             int(absorb_left), left.view(np.float64).ctypes.data_as(_dp),
+                             right.view(np.float64).ctypes.data_as(_dp), _dptr(S), C.byref(k)))
+    kk = k.value
+    return left[:m * kk].reshape(m, kk), S[:kk], right[:kk * n].reshape(kk, n)
+
+
+def selftest_expm(H, v, t, krylov_max=30, tol=1e-12):
+    H = _c128(H)
+    v = _c128(v)
+    n = v.size
+    out = np.zeros(n, np.complex128)
+    it = C.c_int(0)
+    _st(lib.tjm_selftest_expm(n, H.view(np.float64).ctypes.data_as(_dp), v.view(np.float64).ctypes.data_as(_dp),
+                              t, krylov_max, tol, out.view(np.float64).ctypes.data_as(_dp), C.byref(it)))
+    return out, it.value
+
+
+def selftest_philox(counters, k0, k1):
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    _st(lib.tjm_selftest_philox(c.shape[0], c.ctypes.data_as(_up), k0, k1, out.ctypes.data_as(_up)))
+    return out
