@@ -1,0 +1,141 @@
+"""The HIP TJM against the CPU oracle, through the C ABI.
+
+Per trajectory (same Philox streams on both sides): identical jump logs and
+bond dimensions, site observables within 1e-10 on the FP64 path; within
+2e-4 on the mixed path for trajectories whose jump logs agree.  Ensembles:
+the C1 workload against exact Lindblad dynamics.  Large launch shapes: the
+full trajectory counts and chain lengths of the measured workloads, a few
+steps, with sampled trajectories recomputed by the oracle one by one, plus
+properties that hold at any size."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2501_17913_amd import models, tjm  # noqa: E402
+from oracle import lindblad, model as om, mps_tjm  # noqa: E402
+from tests import inputs  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(L, chi, init, n, N, g, gamma, seed, prec=tjm.PREC_FP64, J=1.0, traces=True, **kw):
+    mpo, s, o, r = models.xxx_model(L, J, g, gamma)
+    m = tjm.Model(L, mpo, s, o, r)
+    m.set_initial_product(models.product_state(inputs.init_bits(L, init)))
+    opt = tjm.default_options(precision=prec, record_bonds=1 if traces else 0, **kw)
+    out = m.run(N, 0.1, n * 0.1, chi, models.zx_observables(L), seed, opt, traces=traces)
+    m.close()
+    return out
+
+
+def oracle_traj(L, chi, init, n, g, gamma, seed, traj, J=1.0):
+    Ws = om.xxx_mpo(L, J, g)
+    jumps = om.relax_dephase_jumps(L, gamma, gamma)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    sv = om.product_site_vectors(L, inputs.init_bits(L, init))
+    rec = {}
+    out = mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, n, obs, seed, traj,
+                                 mps_tjm.Options(chi_max=chi), rec)
+    return out, [m for (_, _, m) in rec['jumps']], np.array(rec['bonds'])
+
+
+@pytest.mark.parametrize("case", inputs.small_cases(), ids=lambda c: "L%d_chi%d_%s" % (c[0], c[1], c[2]))
+def test_fp64_per_trajectory_parity(case):
+    L, chi, init, n, N, g, gamma = case
+    seed = inputs.SEED + L
+    log("fp64 parity", case)
+    res = gpu_run(L, chi, init, n, N, g, gamma, seed)
+    worst = 0.0
+    for t in range(N):
+        ref, jl, bl = oracle_traj(L, chi, init, n, g, gamma, seed, t)
+        assert list(res['jumps'][t]) == jl, (t, list(res['jumps'][t]), jl)
+        assert np.array_equal(res['bonds'][t], bl), t
+        worst = max(worst, np.abs(res['per_traj'][t] - ref).max())
+    log("  max |gpu - oracle| =", worst)
+    assert worst < 1e-10
+    # trajectory average and its standard error are those of the records
+    per = res['per_traj']
+    assert np.abs(res['mean'] - per.mean(0)).max() < 1e-13
+    if N > 1:
+        assert np.abs(res['sem'] - per.std(0, ddof=1) / np.sqrt(N)).max() < 1e-13
+
+
+@pytest.mark.parametrize("case", [inputs.small_cases()[3], inputs.small_cases()[5]],
+                         ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
+def test_mixed_precision_per_trajectory_parity(case):
+    L, chi, init, n, N, g, gamma = case
+    seed = inputs.SEED + L
+    log("mixed parity", case)
+    res = gpu_run(L, chi, init, n, N, g, gamma, seed, prec=tjm.PREC_MIXED)
+    worst, flips = 0.0, 0
+    for t in range(N):
+        ref, jl, bl = oracle_traj(L, chi, init, n, g, gamma, seed, t)
+        if list(res['jumps'][t]) != jl:
+            flips += 1
+            continue
+        worst = max(worst, np.abs(res['per_traj'][t] - ref).max())
+    log("  max |mixed - oracle| =", worst, "flipped trajectories", flips)
+    assert flips <= max(1, N // 8)
+    assert worst < 2e-4
+
+
+def test_c1_ensemble_matches_exact_lindblad_and_oracle():
+    w = inputs.workload("C1")
+    L, n = w["L"], int(round(w["T"] / w["dt"]))
+    log("C1 ensemble", w)
+    res = gpu_run(L, w["chi_max"], w["init"], n, w["n_traj"], w["g"], w["gamma"], w["seed"])
+    H = om.xxx_dense(L, w["J"], w["g"])
+    jumps = om.relax_dephase_jumps(L, w["gamma"], w["gamma"])
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    psi0 = om.product_dense(om.product_site_vectors(L, inputs.init_bits(L, w["init"])))
+    t0 = time.time()
+    exact = lindblad.evolve_observables(H, jumps, psi0, w["dt"], n, obs)
+    log("  exact Lindblad (4096-entry density matrix) in %.1fs" % (time.time() - t0))
+    dev = np.abs(res['mean'] - exact)
+    se = res['sem']
+    assert np.mean(dev <= 3 * se + 2e-3) >= 0.99
+    assert np.all(dev <= 5 * se + 2e-3)
+    for t in (0, 57, 199):
+        ref, jl, _ = oracle_traj(L, w["chi_max"], w["init"], n, w["g"], w["gamma"], w["seed"], t)
+        assert list(res['jumps'][t]) == jl
+        assert np.abs(res['per_traj'][t] - ref).max() < 1e-10
+
+
+def _large(name, steps, prec, sample):
+    w = inputs.workload(name)
+    L = w["L"]
+    log("large launch", name, "steps", steps, "precision", prec, "sampled", sample)
+    t0 = time.time()
+    res = gpu_run(L, w["chi_max"], w["init"], steps, w["n_traj"], w["g"], w["gamma"], w["seed"], prec=prec)
+    log("  gpu %.1fs" % (time.time() - t0), {k: res['stats'][k] for k in ('jumps', 'krylov_iters', 'two_site', 'one_site')})
+    per = res['per_traj']
+    # properties that hold at any size
+    assert np.all(np.isfinite(per)) and np.all(np.abs(per) <= 1 + 1e-9)
+    assert np.all(res['bonds'] <= w["chi_max"]) and np.all(res['bonds'][:, :, 0] == 1)
+    assert np.all(res['bonds'][:, :, -1] == 1)
+    assert np.all((res['jumps'] >= -1) & (res['jumps'] < 2 * L))
+    tol = 1e-10 if prec == tjm.PREC_FP64 else 2e-4
+    for t in sample:
+        t1 = time.time()
+        ref, jl, bl = oracle_traj(L, w["chi_max"], w["init"], steps, w["g"], w["gamma"], w["seed"], t)
+        log("  oracle trajectory %d in %.1fs" % (t, time.time() - t1))
+        if prec == tjm.PREC_FP64:
+            assert list(res['jumps'][t]) == jl
+            assert np.array_equal(res['bonds'][t], bl)
+        if list(res['jumps'][t]) == jl:
+            assert np.abs(per[t] - ref).max() < tol
+
+
+def test_c2_launch_fp64_sampled_trajectories():
+    _large("C2", 3, tjm.PREC_FP64, (0, 511, 1023))
+
+
+def test_c3_launch_mixed_sampled_trajectories():
+    _large("C3", 2, tjm.PREC_MIXED, (0, 4095))
