@@ -1,0 +1,163 @@
+"""Throughput of the TJM step on one MI355X.
+
+One *step* is one step function F_k of the sampling MPS applied to every
+trajectory of the batch (dynamic TDVP, both dissipation/jump branches,
+observables): one launch of the persistent TJM kernel.  The workload is the
+XXX chain L=100, chi_max=64, 4096 trajectories, dt=0.1, T=5 (50 steps),
+Neel initial state, relaxation + dephasing at gamma=0.1 on every site,
+mixed precision (complex-FP32 matrix-core contractions, FP64 factorisations).
+
+Timed region: the K steps that follow W untimed warmup steps of the same run
+(F_0 and uploads happen before; inputs are resident in HBM).  With the
+defaults (W=0, K=50) the timed region is the whole job.  value = trajectories
+x K / wall seconds.
+
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "C2": dict(L=40, chi_max=32, n_traj=1024, T=5.0),
+    "C3": dict(L=100, chi_max=64, n_traj=4096, T=5.0),
+    "C4": dict(L=1000, chi_max=16, n_traj=512, T=2.0),
+}
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
+SEED = 0x250117913
+
+
+def _oracle_worker(args):
+    L, chi, steps, traj, budget = args
+    from oracle import model as om, mps_tjm
+    Ws = om.xxx_mpo(L, 1.0, 0.5)
+    jumps = om.relax_dephase_jumps(L, 0.1, 0.1)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    sv = om.product_site_vectors(L, [l % 2 for l in range(L)])
+    start = time.time()
+    best = (0, 1.0)
+    n = 1
+    while n <= steps:                    # runs of 1, 2, 4, ... steps until the budget is used
+        t0 = time.time()
+        mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, n, obs, SEED, traj,
+                               mps_tjm.Options(chi_max=chi))
+        el = time.time() - t0
+        best = (n, el)
+        if time.time() - start + 2.5 * el > budget:
+            break
+        n *= 2
+    return best
+
+
+def cpu_baseline(L, chi, max_steps, budget=20.0):
+    """The oracle as it stands on the host cores, one trajectory per process
+    (different trajectory ids).  Each process runs its trajectory for 1, 2,
+    4, ... steps while the time budget lasts; its rate is the longest
+    completed run's steps over that run's time."""
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"                     # one core per trajectory, as in the paper's runs
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(L, chi, max_steps, t, budget) for t in range(cores)])
+    rate = sum(n / el for n, el in res)
+    steps = min(n for n, _ in res)
+    return {"value": rate, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 NumPy MPS-TJM of the same chain, %d trajectories (one per core), "
+                      "steps 1..%d from the Neel state (the cheaper early steps), ~%.0fs budget"
+                      % (cores, steps, budget)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole job)")
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--n-traj", type=int, default=None)
+    ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2501_17913_amd import models, tjm
+
+    w = dict(WORKLOADS[args.workload])
+    if args.n_traj:
+        w["n_traj"] = args.n_traj
+    L, chi, N, T = w["L"], w["chi_max"], w["n_traj"], w["T"]
+    dt = 0.1
+    n = int(round(T / dt))
+    K = n - args.warmup if args.steps is None else args.steps
+    if args.warmup + K > n or K < 1:
+        print("warmup + steps must be within the %d steps of the job" % n, file=sys.stderr)
+        sys.exit(2)
+    prec = tjm.PREC_MIXED if args.precision == "mixed" else tjm.PREC_FP64
+
+    mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
+    m = tjm.Model(L, mpo, s, o, r)
+    m.set_initial_product(models.neel(L))
+    opt = tjm.default_options(precision=prec, workers=args.workers)
+    m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
+    if args.warmup:
+        m.advance(args.warmup)
+    s0 = m.stats()
+    t0 = time.perf_counter()
+    m.advance(K)                      # synchronous: returns after the last kernel
+    wall = time.perf_counter() - t0
+    s1 = m.stats()
+    m.advance(n - args.warmup - K)
+    res = m.end()
+    m.close()
+
+    kern_ms = s1["step_kernel_ms_total"] - s0["step_kernel_ms_total"]
+    launches = s1["step_launches"] - s0["step_launches"]
+    cmac = s1["cmac_mfma"] - s0["cmac_mfma"]
+    flops_per_launch = 8.0 * cmac / launches
+    avg_ms = kern_ms / launches
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    value = N * K / wall
+    out = {
+        "metric": "trajectory-steps/s at L=100 chi=64 (mixed vs FP64 path)",
+        "value": value,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64-mfma/f64" if prec == tjm.PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": "XXX chain L=%d J=1 g=0.5 (X field), sigma- and Z jumps gamma=0.1, Neel, "
+                               "chi_max=%d, dt=0.1, T=%g, %d trajectories, %s" %
+                               (L, chi, T, N, args.precision),
+                   "L": L, "chi_max": chi, "n_traj": N, "dt": dt, "T": T, "precision": args.precision,
+                   "timed_steps": "%d..%d" % (args.warmup + 1, args.warmup + K)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "tjm_step_kernel<%s>" % ("float" if prec == tjm.PREC_MIXED else "double"),
+                     "avg_launch_ms": avg_ms, "algorithmic_flop_per_launch": flops_per_launch},
+        "stats": {k: s1[k] - s0[k] for k in ("krylov_iters", "expm_calls", "one_site", "two_site",
+                                              "factorizations", "jumps", "cmac_mix")},
+        "workers": s1["workers"],
+        "mean_Z0_final": float(res["mean"][-1][0]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, chi, n, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,6 +91,12 @@ typedef struct {
   unsigned long long krylov_iters, expm_calls;
   unsigned long long one_site, two_site, factorizations, jumps;
   size_t device_bytes;            /* device memory held by the run            */
+  /* workgroup-seconds summed over trajectories, by phase: [0] whole step
+   * functions, [1] contractions (effective Hamiltonians, environments),
+   * [2] of which the MPO mixing stage, [3] SVDs, [4] QR/LQ, [5] Lanczos
+   * exponentials including their contractions, [6] bond-matrix absorption
+   * and two-site products, [7] unused                                       */
+  double phase_s[8];
 } tjm_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -37,9 +37,11 @@ tjm_status tjm_selftest_cgemm(int precision, int M, int N, int K, int nb, int su
  * diag(R) real >= 0. */
 tjm_status tjm_selftest_qr(int m, int n, const double *X, double *Q, double *R);
 
-/* Truncated one-sided Jacobi SVD of G (m x n), min(m, n) <= 128,
- * max(m, n) <= 256: left (m x k) = U or U S (absorb_left), right (k x n) =
- * S V^H or V^H, S the kept singular values (k doubles, descending), *k out. */
+/* Truncated one-sided Jacobi SVD of G (m x n), max(m, n) <= 256, and n <= 128
+ * (absorb_left = 0) or m <= 128 (absorb_left = 1): left (m x k) = U or U S,
+ * right (k x n) = S V^H or V^H; the factor without S is orthonormal to
+ * rounding.  S receives the kept singular values (k doubles, descending),
+ * *k the kept rank. */
 tjm_status tjm_selftest_svd(int m, int n, const double *G, double discard, int cap,
                             double deg_tol, int absorb_left, double *left, double *right,
                             double *S, int *k);

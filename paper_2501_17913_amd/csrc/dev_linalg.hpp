@@ -8,7 +8,7 @@
 //                 the small tridiagonal exponential by scaled Taylor series.
 // All matrices are row-major complex<double> in global scratch memory.
 #pragma once
-#include <dev_common.hpp>
+#include <dev_gemm.hpp>
 
 #define TJM_KMAX 32                 // largest Krylov dimension supported
 
@@ -146,8 +146,14 @@ TJM_DEV int trunc_rank(F s, int n, double discard, int cap, double deg_tol) {
 // One-sided Jacobi SVD of G (m x n, row-major ld n), truncated.
 //   left  (m x k, ld k)  = U        or U S   (absorb_left)
 //   right (k x n, ld n)  = S V^H    or V^H
-// Returns k.  Wc/Vc are (p x nc) and (nc x nc) column-major work arrays,
-// p = max(m, n), nc = min(m, n) <= 128.
+// Returns k.  The factor without S must come out orthonormal to rounding (it
+// becomes a left- or right-canonical site tensor), so the Jacobi rotations
+// act on the columns of G (absorb_left = false: U) or of G^H (absorb_left =
+// true: V); the factor carrying S is then one FP64 matrix-core product with
+// G (U^H G = S V^H, or G V = U S), read before any output is written, so
+// `left` or `right` may alias G.  Work arrays: Wc and Uc (p x nc each), Tg
+// (m x n), with p, nc the row and column counts of the rotated matrix;
+// nc <= 128.
 // --------------------------------------------------------------------------
 struct SvdLds {
   double s[128];
@@ -158,20 +164,22 @@ struct SvdLds {
 
 TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
                     double discard, int cap, double deg_tol,
-                    zd* Wc, zd* Vc, SvdLds& SL, BlkScratch& S) {
+                    zd* Wc, zd* Uc, zd* Tg, SvdLds& SL, BlkScratch& S, void* glds) {
   const int tid = tjm_tid();
-  const bool tr = m < n;                 // work on G^H so that columns <= rows
+  const bool tr = absorb_left;           // rotate the columns of G^H (-> V)
   const int p = tr ? n : m;              // rows of the working matrix
   const int nc = tr ? m : n;             // columns of the working matrix
+  double f2 = 0.0;
   for (int e = tid; e < p * nc; e += TJM_NT) {
     int c = e / p, r = e % p;            // Wc[c][r] = Gw[r][c]
-    Wc[e] = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
+    zd x = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
+    Wc[e] = x;
+    f2 += abs2(x);
   }
-  for (int e = tid; e < nc * nc; e += TJM_NT) {
-    int c = e / nc, r = e % nc;
-    Vc[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
-  }
-  tjm_sync();
+  // columns below 1e-14 ||G||_F carry weight < 1e-28 of the total, far
+  // below any truncation threshold: they are not rotated (rotating them only
+  // stirs rounding noise and never converges)
+  const double zero2 = 1e-28 * blk_sum(f2, S);
   const int np = (nc + 1) & ~1;          // players, a dummy if nc is odd
   const int npair = np / 2;
   int tpp = 64;
@@ -179,11 +187,6 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   const int ngrp = TJM_NT / tpp;
   const int g = tid / tpp, gl = tid % tpp;
   const double tol = 2.220446049250313e-16 * sqrt((double)p);
-  // columns whose norm is below 1e-18 of ||G||_F are exact zeros: rotating
-  // them only stirs rounding noise (and can never converge)
-  double f2 = 0.0;
-  for (int e = tid; e < p * nc; e += TJM_NT) f2 += abs2(Wc[e]);
-  const double zero2 = 1e-36 * blk_sum(f2, S);
   for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
     if (tid == 0) SL.rotated = 0;
     tjm_sync();
@@ -217,13 +220,6 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
             zd x = wa[r], y = eph * wb[r];
             wa[r] = cs * x - sn * y;
             wb[r] = sn * x + cs * y;
-          }
-          zd* va = Vc + (long)a * nc;
-          zd* vb = Vc + (long)b * nc;
-          for (int r = gl; r < nc; r += tpp) {
-            zd x = va[r], y = eph * vb[r];
-            va[r] = cs * x - sn * y;
-            vb[r] = sn * x + cs * y;
           }
           if (gl == 0) SL.rotated = 1;
         }
@@ -259,37 +255,31 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   }
   tjm_sync();
   const int k = SL.k;
-  // U_j = w_{o_j} / s_{o_j} (p x k), V_j = v_{o_j} (nc x k)
-  // not transposed: G = U S V^H -> left rows m = p, right columns n = nc
-  // transposed:     G = V S U^H -> left rows m = nc, right columns n = p
+  // kept orthonormal vectors of Gw in sorted order: Uc[j][r] = w_{o_j}[r] / s
+  for (int e = tid; e < k * p; e += TJM_NT) {
+    int j = e / p, r = e % p;
+    int o = SL.order[j];
+    Uc[e] = (1.0 / SL.s[o]) * Wc[(long)o * p + r];
+  }
+  tjm_sync();
   if (!tr) {
+    // G = U S V^H with U from the rotated columns: right = U^H G = S V^H
+    blk_cgemm<double>(k, n, m, 1, true, cmat((const zd*)Uc, p, 0, false, true), cmat(G, n), Tg, n, 0, false, glds);
+    tjm_sync();
     for (int e = tid; e < m * k; e += TJM_NT) {
       int r = e / k, j = e % k;
-      int o = SL.order[j];
-      double s = SL.s[o];
-      zd u = Wc[(long)o * p + r];
-      left[e] = absorb_left ? u : (1.0 / s) * u;
+      left[e] = Uc[(long)j * p + r];
     }
-    for (int e = tid; e < k * n; e += TJM_NT) {
-      int j = e / n, c = e % n;
-      int o = SL.order[j];
-      zd v = conjg(Vc[(long)o * nc + c]);
-      right[e] = absorb_left ? v : SL.s[o] * v;
-    }
+    for (int e = tid; e < k * n; e += TJM_NT) right[e] = Tg[e];
   } else {
-    for (int e = tid; e < m * k; e += TJM_NT) {
-      int r = e / k, j = e % k;
-      int o = SL.order[j];
-      zd v = Vc[(long)o * nc + r];
-      left[e] = absorb_left ? SL.s[o] * v : v;
-    }
+    // G^H = V S U^H with V from the rotated columns: left = G V = U S
+    blk_cgemm<double>(m, k, n, 1, true, cmat(G, n), cmat((const zd*)Uc, p, 0, true, false), Tg, k, 0, false, glds);
+    tjm_sync();
     for (int e = tid; e < k * n; e += TJM_NT) {
       int j = e / n, c = e % n;
-      int o = SL.order[j];
-      double s = SL.s[o];
-      zd u = conjg(Wc[(long)o * p + c]);
-      right[e] = absorb_left ? (1.0 / s) * u : u;
+      right[e] = conjg(Uc[(long)j * p + c]);
     }
+    for (int e = tid; e < m * k; e += TJM_NT) left[e] = Tg[e];
   }
   tjm_sync();
   return k;

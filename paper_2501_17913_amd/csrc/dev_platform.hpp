@@ -29,3 +29,6 @@ TJM_DEV float tjm_shfl_xor(float v, int m) { return __shfl_xor(v, m, TJM_WAVE); 
 TJM_DEV int tjm_shfl_xor(int v, int m) { return __shfl_xor(v, m, TJM_WAVE); }
 
 TJM_DEV uint32_t tjm_mulhi(uint32_t a, uint32_t b) { return __umulhi(a, b); }
+
+// constant-rate (100 MHz) device clock, for phase timing
+TJM_DEV unsigned long long tjm_clock() { return (unsigned long long)wall_clock64(); }

@@ -23,11 +23,12 @@
 #include "tjm_params.h"
 
 struct Lds {
+  alignas(16) char gemm[GEMM_LDS_BYTES];
   BlkScratch S;
   QrLds qr;
   SvdLds sv;
   LanczosLds lz;
-  unsigned long long st[8];
+  unsigned long long st[TJM_NSTAT];
   int item;
   int pick;
   double rho[4];
@@ -67,6 +68,7 @@ template <typename Tc> struct Tjm {
   TJM_DEV zc* envp(int bond) { return env + (long)slot[bond] * P.env_cap; }
   TJM_DEV zc* spare() { return env + (long)slot[L + 1] * P.env_cap; }
   TJM_DEV void count(int i, unsigned long long n) { if (tjm_tid() == 0) sh.st[i] += n; }
+  TJM_DEV void since(int i, unsigned long long t0) { if (tjm_tid() == 0) sh.st[i] += tjm_clock() - t0; }
   TJM_DEV static zd* site(zd* mps, const TjmParams& P, int s) { return mps + P.site_off[s]; }
 
   // ------------------------------------------------------------------
@@ -76,6 +78,7 @@ template <typename Tc> struct Tjm {
   // ------------------------------------------------------------------
   TJM_DEV void mix(int Dout, int A, int dph, int B, const int* rp, const MixEnt* ent,
                    const zc* src, zc* dst) {
+    const unsigned long long t0 = tjm_clock();
     const long per = (long)A * dph * B;
     const long tot = (long)Dout * per;
     for (long e = tjm_tid(); e < tot; e += TJM_NT) {
@@ -94,6 +97,7 @@ template <typename Tc> struct Tjm {
       }
       dst[e] = cmk(xr, xi);
     }
+    since(TJM_ST_T_MIX, t0);
   }
   TJM_DEV unsigned long long mix_nnz(int Dout, int dph, const int* rp) {
     return (unsigned long long)(rp[Dout * dph] - rp[0]);
@@ -108,34 +112,38 @@ template <typename Tc> struct Tjm {
 
   // L_{s+1}[w'][b'][b] = sum L_s[w][a'][a] conj(A[a'][s'][b']) W[w][w'][s'][s] A[a][s][b]
   TJM_DEV void lupdate(int s, const zd* A, int chl, int chr, const zc* Lold, zc* Lnew) {
+    const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
     blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
-                  T1, d * chr, (long)chl * d * chr, false);
+                  T1, d * chr, (long)chl * d * chr, false, sh.gemm);
     tjm_sync();
     mix(Dr, chl, d, chr, rp, P.mixL, T1, T2);
     tjm_sync();
     blk_cgemm<Tc>(chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
-                  cmat((const zc*)T2, chr, (long)chl * d * chr), Lnew, chr, (long)chr * chr, false);
+                  cmat((const zc*)T2, chr, (long)chl * d * chr), Lnew, chr, (long)chr * chr, false, sh.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chr * chr * chl * d);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dr, d, rp) * chl * chr);
+    since(TJM_ST_T_CONTRACT, t0);
   }
 
   // R_{s-1}[w][a][a'] = sum B[a][s][b] R_s[w'][b][b'] W[w][w'][s'][s] conj(B[a'][s'][b'])
   TJM_DEV void rupdate(int s, const zd* B, int chl, int chr, const zc* Rold, zc* Rnew) {
+    const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixR_ptr + (long)s * (P.Dmax * d + 1);
     blk_cgemm<Tc>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
-                  T1, chr, (long)chl * d * chr, false);
+                  T1, chr, (long)chl * d * chr, false, sh.gemm);
     tjm_sync();
     mix(Dl, chl, d, chr, rp, P.mixR, T1, T2);
     tjm_sync();
     blk_cgemm<Tc>(chl, chl, d * chr, Dl, false, cmat((const zc*)T2, d * chr, (long)chl * d * chr),
-                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false);
+                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, sh.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dl, d, rp) * chl * chr);
+    since(TJM_ST_T_CONTRACT, t0);
   }
 
   // ------------------------------------------------------------------
@@ -144,58 +152,66 @@ template <typename Tc> struct Tjm {
   struct H1 {            // site s: degree-6 network
     Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
     TJM_DEV void apply(const zd* q, zd* y) {
+      const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
       const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
       blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
-                    t->T1, d * chr, (long)chl * d * chr, false);
+                    t->T1, d * chr, (long)chl * d * chr, false, t->sh.gemm);
       tjm_sync();
       t->mix(Dr, chl, d, chr, rp, P.mixL, t->T1, t->T2);
       tjm_sync();
       blk_cgemm<Tc>(chl * d, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d * chr),
-                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false);
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chl * d * chr * chr);
       t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d, rp) * chl * chr);
+      t->since(TJM_ST_T_CONTRACT, t0);
     }
   };
 
   struct H2 {            // sites s, s+1: degree-8 network
     Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
     TJM_DEV void apply(const zd* q, zd* y) {
+      const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, d2 = d * d, Dl = P.mpoD[s], Dr = P.mpoD[s + 2];
       const int* rp = P.mix2_ptr + (long)s * (P.Dmax * d2 + 1);
       blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
-                    t->T1, d2 * chr, (long)chl * d2 * chr, false);
+                    t->T1, d2 * chr, (long)chl * d2 * chr, false, t->sh.gemm);
       tjm_sync();
       t->mix(Dr, chl, d2, chr, rp, P.mix2, t->T1, t->T2);
       tjm_sync();
       blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d2 * chr),
-                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false);
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d2 * chr + (unsigned long long)Dr * chl * d2 * chr * chr);
       t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d2, rp) * chl * chr);
+      t->since(TJM_ST_T_CONTRACT, t0);
     }
   };
 
   struct H0 {            // bond b: degree-4 network, C is kl x kr
     Tjm* t; int D, kl, kr; const zc* Le; const zc* Re;
     TJM_DEV void apply(const zd* q, zd* y) {
+      const unsigned long long t0 = tjm_clock();
       blk_cgemm<Tc>(kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
-                    t->T1, kr, (long)kl * kr, false);
+                    t->T1, kr, (long)kl * kr, false, t->sh.gemm);
       tjm_sync();
       blk_cgemm<Tc>(kl, kr, kr, D, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
-                    cmat(Re, kr, (long)kr * kr), y, kr, 0, false);
+                    cmat(Re, kr, (long)kr * kr), y, kr, 0, false, t->sh.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)D * kl * kl * kr + (unsigned long long)D * kl * kr * kr);
+      t->since(TJM_ST_T_CONTRACT, t0);
     }
   };
 
   template <class Op> TJM_DEV void expm(Op& op, zd* vec, int n, double t) {
+    const unsigned long long t0 = tjm_clock();
     int it = blk_expm(op, vec, n, t, P.krylov_max, P.krylov_tol, Q, w, sh.lz, sh.S);
     count(TJM_ST_KRYLOV, (unsigned long long)it);
     count(TJM_ST_EXPM, 1ull);
+    since(TJM_ST_T_EXPM, t0);
   }
 
   // ------------------------------------------------------------------
@@ -207,32 +223,39 @@ template <typename Tc> struct Tjm {
 
   // next (k x d x c) = C (k x m) . next (m x d x c), via v
   TJM_DEV void absorb_right(zd* next, int k, int m, int c) {
-    blk_cgemm<double>(k, d * c, m, 1, true, cmat((const zd*)Cb, m), cmat((const zd*)next, d * c), v, d * c, 0, false);
+    const unsigned long long t0 = tjm_clock();
+    blk_cgemm<double>(k, d * c, m, 1, true, cmat((const zd*)Cb, m), cmat((const zd*)next, d * c), v, d * c, 0, false, sh.gemm);
     tjm_sync();
     copy(next, v, (long)k * d * c);
     tjm_sync();
+    since(TJM_ST_T_ABSORB, t0);
   }
   // prev (p x d x k) = prev (p x d x m) . C (m x k), via v
   TJM_DEV void absorb_left(zd* prev, int p, int m, int k) {
-    blk_cgemm<double>(p * d, k, m, 1, true, cmat((const zd*)prev, m), cmat((const zd*)Cb, k), v, k, 0, false);
+    const unsigned long long t0 = tjm_clock();
+    blk_cgemm<double>(p * d, k, m, 1, true, cmat((const zd*)prev, m), cmat((const zd*)Cb, k), v, k, 0, false, sh.gemm);
     tjm_sync();
     copy(prev, v, (long)p * d * k);
     tjm_sync();
+    since(TJM_ST_T_ABSORB, t0);
   }
 
   // QR of M_s as (chl d) x chr: M_s <- Q, Cb <- R (k x chr); returns k
   TJM_DEV int qr_site(zd* Ms, int chl, int chr) {
+    const unsigned long long t0 = tjm_clock();
     const int m = chl * d;
     copy(X, Ms, (long)m * chr);
     tjm_sync();
     blk_qr(m, chr, X, Ms, Cb, sh.qr, sh.S);
     count(TJM_ST_FACT, 1ull);
+    since(TJM_ST_T_QR, t0);
     return m < chr ? m : chr;
   }
 
   // LQ of M_s as chl x (d chr): M_s <- B (k x d chr, orthonormal rows),
   // Cb <- C (chl x k); returns k
   TJM_DEV int lq_site(zd* Ms, int chl, int chr) {
+    const unsigned long long t0 = tjm_clock();
     const int n = d * chr;
     for (long e = tjm_tid(); e < (long)n * chl; e += TJM_NT) {      // X = M^H (n x chl)
       int i = (int)(e / chl), j = (int)(e % chl);
@@ -251,6 +274,7 @@ template <typename Tc> struct Tjm {
     }
     tjm_sync();
     count(TJM_ST_FACT, 1ull);
+    since(TJM_ST_T_QR, t0);
     return k;
   }
 
@@ -275,8 +299,10 @@ template <typename Tc> struct Tjm {
   TJM_DEV void svd_move_right(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
-    const int k = blk_svd(chl * d, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+    const unsigned long long ts_ = tjm_clock();
+    const int k = blk_svd(chl * d, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
     count(TJM_ST_FACT, 1ull);
+    since(TJM_ST_T_SVD, ts_);
     absorb_right(site(mps, P, s + 1), k, chr, cn);
     if (tjm_tid() == 0) bd[s + 1] = k;
     tjm_sync();
@@ -285,8 +311,10 @@ template <typename Tc> struct Tjm {
   TJM_DEV void svd_move_left(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
-    const int k = blk_svd(chl, d * chr, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+    const unsigned long long ts_ = tjm_clock();
+    const int k = blk_svd(chl, d * chr, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
     count(TJM_ST_FACT, 1ull);
+    since(TJM_ST_T_SVD, ts_);
     absorb_left(site(mps, P, s - 1), cp, chl, k);
     if (tjm_tid() == 0) bd[s] = k;
     tjm_sync();
@@ -317,13 +345,17 @@ template <typename Tc> struct Tjm {
       const int chl = bd[s], chm = bd[s + 1], chr = bd[s + 2];
       if (chm < P.chi_max) {
         count(TJM_ST_TWO_SITE, 1ull);
+        const unsigned long long tt_ = tjm_clock();
         blk_cgemm<double>(chl * d, d * chr, chm, 1, true, cmat((const zd*)Ms, chm), cmat((const zd*)Mn, d * chr),
-                          v, d * chr, 0, false);
+                          v, d * chr, 0, false, sh.gemm);
         tjm_sync();
+        since(TJM_ST_T_ABSORB, tt_);
         H2 op{this, s, chl, chr, envp(s), envp(s + 2)};
         expm(op, v, chl * d * d * chr, tau);
-        const int k = blk_svd(chl * d, d * chr, v, Ms, Mn, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+        const unsigned long long ts_ = tjm_clock();
+    const int k = blk_svd(chl * d, d * chr, v, Ms, Mn, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
         count(TJM_ST_FACT, 1ull);
+        since(TJM_ST_T_SVD, ts_);
         if (tjm_tid() == 0) bd[s + 1] = k;
         tjm_sync();
         lupdate(s, Ms, chl, k, envp(s), envp(s + 1));
@@ -361,13 +393,17 @@ template <typename Tc> struct Tjm {
       const int chp = bd[s - 1], chl = bd[s], chr = bd[s + 1];
       if (chl < P.chi_max) {
         count(TJM_ST_TWO_SITE, 1ull);
+        const unsigned long long tt_ = tjm_clock();
         blk_cgemm<double>(chp * d, d * chr, chl, 1, true, cmat((const zd*)Mp, chl), cmat((const zd*)Ms, d * chr),
-                          v, d * chr, 0, false);
+                          v, d * chr, 0, false, sh.gemm);
         tjm_sync();
+        since(TJM_ST_T_ABSORB, tt_);
         H2 op{this, s - 1, chp, chr, envp(s - 1), envp(s + 1)};
         expm(op, v, chp * d * d * chr, tau);
-        const int k = blk_svd(chp * d, d * chr, v, Mp, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, sh.sv, sh.S);
+        const unsigned long long ts_ = tjm_clock();
+    const int k = blk_svd(chp * d, d * chr, v, Mp, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
         count(TJM_ST_FACT, 1ull);
+        since(TJM_ST_T_SVD, ts_);
         if (tjm_tid() == 0) bd[s] = k;
         tjm_sync();
         rupdate(s, Ms, k, chr, envp(s + 1), envp(s));
@@ -573,6 +609,7 @@ template <typename Tc> struct Tjm {
   }
 
   int traj_id;
+  unsigned long long t_begin;
 
   // ------------------------------------------------------------------
   // Schedule (Eqs. TimeEvolutionFunctions, SimulationStep)
@@ -586,12 +623,16 @@ template <typename Tc> struct Tjm {
     tjm_sync();
   }
   TJM_DEV void stats_begin() {
-    for (int i = tjm_tid(); i < 8; i += TJM_NT) sh.st[i] = 0ull;
+    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) sh.st[i] = 0ull;
+    tjm_sync();
+    if (tjm_tid() == 0) t_begin = tjm_clock();
     tjm_sync();
   }
   TJM_DEV void stats_end(int traj) {
     tjm_sync();
-    for (int i = tjm_tid(); i < 8; i += TJM_NT) P.tstats[(long)traj * 8 + i] += sh.st[i];
+    if (tjm_tid() == 0) sh.st[TJM_ST_T_TOTAL] += tjm_clock() - t_begin;
+    tjm_sync();
+    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) P.tstats[(long)traj * TJM_NSTAT + i] += sh.st[i];
   }
 
   // Psi(0): product state, canonicalised; t = 0 observables; Phi = F_0 Psi(0)

@@ -418,7 +418,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   size_t freeb = 0, totalb = 0;
   RCHK(hipMemGetInfo(&freeb, &totalb));
   const double per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_obs * 8.0 + 2.0 * n * 4 +
-                          (r->record_bonds ? (double)n * (L + 1) * 4 : 0.0) + 8 * 8 + 4;
+                          (r->record_bonds ? (double)n * (L + 1) * 4 : 0.0) + TJM_NSTAT * 8 + 4;
   const double avail = 0.85 * (double)freeb - per_traj * n_traj;
   if (avail < (double)P.scratch_stride) return bail(TJM_E_NOMEM, "not enough device memory for the run");
   workers = std::min<long>(workers, (long)(avail / (double)P.scratch_stride));
@@ -453,7 +453,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   if (r->record_bonds) {
     RCHK(dalloc(r, (size_t)n_traj * n * (L + 1) * 4, &p)); P.blog = (int*)p; r->d_blog = P.blog;
   }
-  RCHK(dalloc(r, (size_t)n_traj * 8 * 8, &p)); P.tstats = (unsigned long long*)p; r->d_stats = P.tstats;
+  RCHK(dalloc(r, (size_t)n_traj * TJM_NSTAT * 8, &p)); P.tstats = (unsigned long long*)p; r->d_stats = P.tstats;
   RCHK(dalloc(r, (size_t)n_traj * 4, &p)); P.tflags = (int*)p; r->d_flags = P.tflags;
   RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
   RCHK(dalloc(r, 256, &p)); P.counter = (int*)p;
@@ -507,10 +507,11 @@ static void collect_stats(tjm_model* m, Run* r) {
   s.step_kernel_ms_last = r->step_ms_last;
   s.step_launches = r->step_launches;
   s.device_bytes = r->bytes;
-  std::vector<unsigned long long> st((size_t)r->n_traj * 8);
+  std::vector<unsigned long long> st((size_t)r->n_traj * TJM_NSTAT);
   if (hipMemcpy(st.data(), r->d_stats, st.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return;
   for (int t = 0; t < r->n_traj; ++t) {
-    const unsigned long long* q = &st[(size_t)t * 8];
+    const unsigned long long* q = &st[(size_t)t * TJM_NSTAT];
+    for (int i = 0; i < 7; ++i) s.phase_s[i] += 1e-8 * (double)q[TJM_ST_T_TOTAL + i];
     s.cmac_mfma += q[TJM_ST_CMAC_MFMA]; s.cmac_mix += q[TJM_ST_CMAC_MIX];
     s.krylov_iters += q[TJM_ST_KRYLOV]; s.expm_calls += q[TJM_ST_EXPM];
     s.one_site += q[TJM_ST_ONE_SITE]; s.two_site += q[TJM_ST_TWO_SITE];
@@ -679,22 +680,24 @@ extern "C" tjm_status tjm_selftest_qr(int m, int n, const double* X, double* Q, 
 
 extern "C" tjm_status tjm_selftest_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                                        int absorb_left, double* left, double* right, double* S, int* k) {
-  if (m < 1 || n < 1 || std::min(m, n) > 128 || std::max(m, n) > 256 || cap < 1 || !G || !left || !right || !S || !k)
+  if (m < 1 || n < 1 || (absorb_left ? m : n) > 128 || std::max(m, n) > 256 || cap < 1 || !G || !left || !right ||
+      !S || !k)
     return fail(nullptr, TJM_E_INVAL, "svd sizes");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
-  const int nc = std::min(m, n), p = std::max(m, n);
+  const int nc = absorb_left ? m : n, p = absorb_left ? n : m;
   DevScope ds;
-  double *dG, *dl, *dr, *dS, *dW, *dV;
+  double *dG, *dl, *dr, *dS, *dW, *dU, *dT;
   int* dk;
   STCHK(ds.put(G, 2L * m * n, &dG));
   STCHK(ds.put((const double*)nullptr, 2L * m * nc, &dl));
   STCHK(ds.put((const double*)nullptr, 2L * nc * n, &dr));
   STCHK(ds.put((const double*)nullptr, nc, &dS));
   STCHK(ds.put((const double*)nullptr, 2L * p * nc, &dW));
-  STCHK(ds.put((const double*)nullptr, 2L * nc * nc, &dV));
+  STCHK(ds.put((const double*)nullptr, 2L * nc * p, &dU));
+  STCHK(ds.put((const double*)nullptr, 2L * m * n, &dT));
   STCHK(ds.put((const int*)nullptr, 1, &dk));
-  STCHK(tjm_launch_st_svd(m, n, dG, discard, cap, deg_tol, absorb_left, dl, dr, dS, dk, dW, dV));
+  STCHK(tjm_launch_st_svd(m, n, dG, discard, cap, deg_tol, absorb_left, dl, dr, dS, dk, dW, dU, dT));
   STCHK(hipDeviceSynchronize());
   STCHK(hipMemcpy(k, dk, 4, hipMemcpyDeviceToHost));
   const int kk = *k;

@@ -20,7 +20,7 @@ hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_b
 hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R);
 hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                              int absorb_left, double* left, double* right, double* S, int* k,
-                             double* Wc, double* Vc);
+                             double* Wc, double* Uc, double* Tg);
 hipError_t tjm_launch_st_expm(int n, const double* H, double* v, double t, int kmax, double tol,
                               double* Q, double* w, int* iters);
 hipError_t tjm_launch_st_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1,

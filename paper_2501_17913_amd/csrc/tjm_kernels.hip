@@ -84,8 +84,9 @@ template <typename T>
 __global__ __launch_bounds__(TJM_NT) void st_cgemm_kernel(int M, int N, int K, int nb, int sum,
     const zd* A, int lda, long bsA, int tA, int cA, const zd* B, int ldb, long bsB, int tB, int cB,
     zd* C, int ldc, long cs, int acc) {
+  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
   blk_cgemm<T>(M, N, K, nb, sum != 0, cmat(A, lda, bsA, tA != 0, cA != 0),
-               cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0);
+               cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, gl);
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* Q, zd* R) {
@@ -95,10 +96,11 @@ __global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* 
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_svd_kernel(int m, int n, const zd* G, double discard,
-    int cap, double deg_tol, int absorb, zd* left, zd* right, double* Sout, int* kout, zd* Wc, zd* Vc) {
+    int cap, double deg_tol, int absorb, zd* left, zd* right, double* Sout, int* kout, zd* Wc, zd* Uc, zd* Tg) {
   __shared__ BlkScratch S;
   __shared__ SvdLds SL;
-  int k = blk_svd(m, n, G, left, right, absorb != 0, discard, cap, deg_tol, Wc, Vc, SL, S);
+  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
+  int k = blk_svd(m, n, G, left, right, absorb != 0, discard, cap, deg_tol, Wc, Uc, Tg, SL, S, gl);
   if (threadIdx.x == 0) *kout = k;
   for (int j = threadIdx.x; j < k; j += TJM_NT) Sout[j] = SL.s[SL.order[j]];
 }
@@ -106,8 +108,9 @@ __global__ __launch_bounds__(TJM_NT) void st_svd_kernel(int m, int n, const zd* 
 struct DenseOp {
   const zd* H;
   int n;
+  void* gl;
   TJM_DEV void apply(const zd* q, zd* y) {
-    blk_cgemm<double>(n, 1, n, 1, true, cmat(H, n), cmat(q, 1), y, 1, 0, false);
+    blk_cgemm<double>(n, 1, n, 1, true, cmat(H, n), cmat(q, 1), y, 1, 0, false, gl);
     tjm_sync();
   }
 };
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(TJM_NT) void st_expm_kernel(int n, const zd* H, zd*
     int kmax, double tol, zd* Q, zd* w, int* iters) {
   __shared__ BlkScratch S;
   __shared__ LanczosLds Lz;
-  DenseOp op{H, n};
+  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
+  DenseOp op{H, n, gl};
   int it = blk_expm(op, v, n, t, kmax, tol, Q, w, Lz, S);
   if (threadIdx.x == 0) *iters = it;
 }
@@ -151,9 +155,9 @@ hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R) {
 
 hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                              int absorb_left, double* left, double* right, double* S, int* k,
-                             double* Wc, double* Vc) {
+                             double* Wc, double* Uc, double* Tg) {
   hipLaunchKernelGGL(st_svd_kernel, dim3(1), dim3(TJM_NT), 0, 0, m, n, (const zd*)G, discard, cap,
-                     deg_tol, absorb_left, (zd*)left, (zd*)right, S, k, (zd*)Wc, (zd*)Vc);
+                     deg_tol, absorb_left, (zd*)left, (zd*)right, S, k, (zd*)Wc, (zd*)Uc, (zd*)Tg);
   return hipGetLastError();
 }
 

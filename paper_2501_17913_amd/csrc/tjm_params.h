@@ -56,7 +56,7 @@ struct TjmParams {
   double* obs;                       // [n_traj][n_steps+1][n_obs]
   int* jlog;                         // [n_traj][2*n_steps]
   int* blog;                         // [n_traj][n_steps][L+1] (if record_bonds)
-  unsigned long long* tstats;        // [n_traj][8]
+  unsigned long long* tstats;        // [n_traj][TJM_NSTAT]
   int* tflags;                       // [n_traj] nonzero: numerical failure
 
   // per-worker scratch (byte offsets inside one worker's block)
@@ -82,5 +82,14 @@ enum {
   TJM_ST_ONE_SITE = 4,    // 1TDVP bond updates
   TJM_ST_TWO_SITE = 5,    // 2TDVP bond updates
   TJM_ST_FACT = 6,        // QR + SVD factorisations
-  TJM_ST_JUMPS = 7        // jumps applied
+  TJM_ST_JUMPS = 7,       // jumps applied
+  // device-clock ticks (100 MHz) spent by the trajectory's workgroup in:
+  TJM_ST_T_TOTAL = 8,     //   the whole step function
+  TJM_ST_T_CONTRACT = 9,  //   effective-Hamiltonian and environment contractions
+  TJM_ST_T_MIX = 10,      //   ... of which the MPO mixing stage
+  TJM_ST_T_SVD = 11,      //   SVD factorisations
+  TJM_ST_T_QR = 12,       //   QR / LQ factorisations
+  TJM_ST_T_EXPM = 13,     //   Lanczos exponentials (including their contractions)
+  TJM_ST_T_ABSORB = 14,   //   bond-matrix absorption and two-site products
+  TJM_NSTAT = 16
 };

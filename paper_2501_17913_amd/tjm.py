@@ -42,10 +42,14 @@ class Stats(C.Structure):
                 ("krylov_iters", C.c_ulonglong), ("expm_calls", C.c_ulonglong),
                 ("one_site", C.c_ulonglong), ("two_site", C.c_ulonglong),
                 ("factorizations", C.c_ulonglong), ("jumps", C.c_ulonglong),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8)]
+
+    PHASES = ("total", "contract", "mix", "svd", "qr", "expm", "absorb")
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_s"}
+        d["phase_s"] = {k: self.phase_s[i] for i, k in enumerate(self.PHASES)}
+        return d
 
 
 _dp = C.POINTER(C.c_double)
@@ -168,7 +172,7 @@ class Model:
     def run(self, n_traj, dt, T, chi_max, observables, seed, options=None, traces=False):
         """Whole run; returns dict with mean, sem (and per_traj, jumps, bonds)."""
         opt = options or default_options()
-        n = int(round(T / dt))
+        n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
         sites, ops = self._obs(observables)
         no = len(observables)
         mean = np.zeros((n + 1, no))
@@ -193,7 +197,7 @@ class Model:
     def begin(self, n_traj, dt, T, chi_max, observables, seed, options=None):
         opt = options or default_options()
         sites, ops = self._obs(observables)
-        self._n = int(round(T / dt))
+        self._n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
         self._no = len(observables)
         self._nt = n_traj
         self._rec = bool(opt.record_bonds)
@@ -261,9 +265,9 @@ def selftest_svd(G, discard=1e-12, cap=1 << 30, deg_tol=1e-12, absorb_left=False
     G = _c128(G)
     m, n = G.shape
     nc = min(m, n)
-    left = np.zeros(m * nc, np.complex128)
-    right = np.zeros(nc * n, np.complex128)
-    S = np.zeros(nc)
+    left = np.zeros(m * max(m, n), np.complex128)
+    right = np.zeros(max(m, n) * n, np.complex128)
+    S = np.zeros(max(m, n))
     k = C.c_int(0)
     _st(lib.tjm_selftest_svd(m, n, G.view(np.float64).ctypes.data_as(_dp), discard, min(cap, 1 << 30), deg_tol,
                              int(absorb_left), left.view(np.float64).ctypes.data_as(_dp),
