@@ -8,9 +8,9 @@ Neel initial state, relaxation + dephasing at gamma=0.1 on every site,
 mixed precision (complex-FP32 matrix-core contractions, FP64 factorisations).
 
 Timed region: the K steps that follow W untimed warmup steps of the same run
-(F_0 and uploads happen before; inputs are resident in HBM).  With the
-defaults (W=0, K=50) the timed region is the whole job.  value = trajectories
-x K / wall seconds.
+(F_0 and uploads happen before; inputs are resident in HBM).  value =
+trajectories x K / wall seconds.  The FP64 path is timed on the same steps
+for comparison (fp64_path).
 
 Prints ONE JSON line.
 """
@@ -73,15 +73,49 @@ def cpu_baseline(L, chi, max_steps, budget=20.0):
                       % (cores, steps, budget)}
 
 
+def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
+    """Run one job on the GPU; time steps warmup+1 .. warmup+K."""
+    dt = 0.1
+    n = int(round(T / dt))
+    mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
+    m = tjm.Model(L, mpo, s, o, r)
+    m.set_initial_product(models.neel(L))
+    opt = tjm.default_options(precision=prec, workers=workers)
+    m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
+    if warmup:
+        m.advance(warmup)
+    s0 = m.stats()
+    t0 = time.perf_counter()
+    m.advance(K)                      # synchronous: returns after the last kernel
+    wall = time.perf_counter() - t0
+    s1 = m.stats()
+    m.close()                         # the rest of the job is not needed for timing
+    launches = s1["step_launches"] - s0["step_launches"]
+    kern_ms = s1["step_kernel_ms_total"] - s0["step_kernel_ms_total"]
+    cmac = s1["cmac_mfma"] - s0["cmac_mfma"]
+    flops_per_launch = 8.0 * cmac / launches
+    avg_ms = kern_ms / launches
+    phases = {k: s1["phase_s"][k] - s0["phase_s"][k] for k in s1["phase_s"]}
+    tot = phases["total"] or 1.0
+    return {
+        "value": N * K / wall, "wall": wall, "avg_ms": avg_ms, "flops_per_launch": flops_per_launch,
+        "achieved_tflops": flops_per_launch / (avg_ms * 1e-3) / 1e12, "workers": s1["workers"],
+        "counts": {k: s1[k] - s0[k] for k in ("krylov_iters", "expm_calls", "one_site", "two_site",
+                                              "factorizations", "jumps", "cmac_mix")},
+        "phase_frac": {k: round(v / tot, 4) for k, v in phases.items() if k != "total"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole job)")
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=4, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed steps before the timed ones")
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--n-traj", type=int, default=None)
     ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -95,65 +129,45 @@ def main():
     if args.n_traj:
         w["n_traj"] = args.n_traj
     L, chi, N, T = w["L"], w["chi_max"], w["n_traj"], w["T"]
-    dt = 0.1
-    n = int(round(T / dt))
-    K = n - args.warmup if args.steps is None else args.steps
-    if args.warmup + K > n or K < 1:
+    n = int(round(T / 0.1))
+    K, W = args.steps, args.warmup
+    if W + K > n or K < 1:
         print("warmup + steps must be within the %d steps of the job" % n, file=sys.stderr)
         sys.exit(2)
     prec = tjm.PREC_MIXED if args.precision == "mixed" else tjm.PREC_FP64
-
-    mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
-    m = tjm.Model(L, mpo, s, o, r)
-    m.set_initial_product(models.neel(L))
-    opt = tjm.default_options(precision=prec, workers=args.workers)
-    m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
-    if args.warmup:
-        m.advance(args.warmup)
-    s0 = m.stats()
-    t0 = time.perf_counter()
-    m.advance(K)                      # synchronous: returns after the last kernel
-    wall = time.perf_counter() - t0
-    s1 = m.stats()
-    m.advance(n - args.warmup - K)
-    res = m.end()
-    m.close()
-
-    kern_ms = s1["step_kernel_ms_total"] - s0["step_kernel_ms_total"]
-    launches = s1["step_launches"] - s0["step_launches"]
-    cmac = s1["cmac_mfma"] - s0["cmac_mfma"]
-    flops_per_launch = 8.0 * cmac / launches
-    avg_ms = kern_ms / launches
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    head = measure(tjm, models, L, chi, N, T, prec, W, K, args.workers)
     peak = PEAK_TFLOPS[args.precision]
-    value = N * K / wall
     out = {
         "metric": "trajectory-steps/s at L=100 chi=64 (mixed vs FP64 path)",
-        "value": value,
+        "value": head["value"],
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / K,
+        "warmup": W,
+        "ms_per_step": 1e3 * head["wall"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64-mfma/f64" if prec == tjm.PREC_MIXED else "f64",
+        "dtype": "c64-mfma+f64" if prec == tjm.PREC_MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": "XXX chain L=%d J=1 g=0.5 (X field), sigma- and Z jumps gamma=0.1, Neel, "
-                               "chi_max=%d, dt=0.1, T=%g, %d trajectories, %s" %
-                               (L, chi, T, N, args.precision),
-                   "L": L, "chi_max": chi, "n_traj": N, "dt": dt, "T": T, "precision": args.precision,
-                   "timed_steps": "%d..%d" % (args.warmup + 1, args.warmup + K)},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+        "config": {"workload": "XXX chain L=%d J=1 g=0.5 (X field), sigma- and Z jumps gamma=0.1 on every "
+                               "site, Neel initial state, chi_max=%d, dt=0.1, T=%g, %d trajectories, %s; "
+                               "timed steps %d..%d of the %d-step job"
+                               % (L, chi, T, N, args.precision, W + 1, W + K, n),
+                   "L": L, "chi_max": chi, "n_traj": N, "dt": 0.1, "T": T, "precision": args.precision},
+        "roofline": {"bound": "mfma", "achieved": head["achieved_tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": head["achieved_tflops"] / peak, "traffic": None,
                      "kernel": "tjm_step_kernel<%s>" % ("float" if prec == tjm.PREC_MIXED else "double"),
-                     "avg_launch_ms": avg_ms, "algorithmic_flop_per_launch": flops_per_launch},
-        "stats": {k: s1[k] - s0[k] for k in ("krylov_iters", "expm_calls", "one_site", "two_site",
-                                              "factorizations", "jumps", "cmac_mix")},
-        "workers": s1["workers"],
-        "mean_Z0_final": float(res["mean"][-1][0]),
+                     "avg_launch_ms": head["avg_ms"], "algorithmic_flop_per_launch": head["flops_per_launch"]},
+        "workers": head["workers"],
+        "counts": head["counts"],
+        "phase_frac": head["phase_frac"],
     }
+    if prec == tjm.PREC_MIXED and not args.no_fp64_compare:
+        f = measure(tjm, models, L, chi, N, T, tjm.PREC_FP64, W, K, args.workers)
+        out["fp64_path"] = {"value": f["value"], "ms_per_step": 1e3 * f["wall"] / K,
+                            "achieved_tflops": f["achieved_tflops"], "peak": PEAK_TFLOPS["fp64"],
+                            "mixed_speedup": head["value"] / f["value"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, chi, n, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -78,6 +78,12 @@ typedef struct {
   int record_bonds;       /* 1: keep bond dimensions after every U[dt]        */
   uint32_t traj_base;     /* global id of trajectory 0 of this run            */
   int device;             /* HIP device ordinal                               */
+  int certify_sweeps;     /* normalisation sweeps after a jump: 1 = QR moves
+                             where a bound on the smallest singular value
+                             proves the SVD would truncate nothing (same state,
+                             other gauge), SVD otherwise; 0 = SVD at every
+                             bond; < 0 (default) = 1 for TJM_PREC_MIXED and 0
+                             for TJM_PREC_FP64                                */
 } tjm_options;
 
 typedef struct {

@@ -92,6 +92,79 @@ TJM_DEV void stage_b(const CMat<S>& B, int b, int k0, int j0, int K, int N, cplx
   }
 }
 
+// Small products: each wavefront owns 32 x 16 complex blocks and feeds the
+// matrix cores straight from memory (no LDS, no workgroup barriers).
+template <typename T, typename SA, typename SB, typename SC>
+TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
+                        const CMat<SA>& A, const CMat<SB>& B,
+                        cplx<SC>* C, int ldc, long cs, bool accumulate) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = tjm_lane();
+  const int r16 = lane & 15;
+  const int q = lane >> 4;
+  const int kq = q >> 1;
+  const int kp = q & 1;
+  const int cpart = r16 & 1;
+  const int nti = (M + 31) / 32, ntj = (N + 15) / 16;
+  const int nout = sum_batches ? 1 : nb;
+  const int nitems = nout * nti * ntj;
+  for (int it = tjm_wave(); it < nitems; it += TJM_NWAVE) {
+    const int ob = it / (nti * ntj);
+    const int rem = it - ob * (nti * ntj);
+    const int i0 = (rem / ntj) * 32;
+    const int j0 = (rem % ntj) * 16;
+    acc_t acc[2][2];
+    acc[0][0] = Mfma<T>::zero(); acc[0][1] = Mfma<T>::zero();
+    acc[1][0] = Mfma<T>::zero(); acc[1][1] = Mfma<T>::zero();
+    const int b_lo = sum_batches ? 0 : ob;
+    const int b_hi = sum_batches ? nb : ob + 1;
+    for (int b = b_lo; b < b_hi; ++b) {
+      for (int k0 = 0; k0 < K; k0 += 2) {
+        const int kc = k0 + kq;
+        const bool kin = kc < K;
+        T av[2], bv[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int row = i0 + 16 * t + r16;
+          T v = (T)0;
+          if (kin && row < M) {
+            cplx<T> e = cmat_get<T>(A, b, row, kc);
+            v = kp ? e.im : e.re;
+          }
+          av[t] = v;
+          const int col = j0 + 8 * t + (r16 >> 1);
+          T w = (T)0;
+          if (kin && col < N) {
+            cplx<T> e = cmat_get<T>(B, b, kc, col);
+            w = (kp == cpart) ? e.re : (kp ? -e.im : e.im);
+          }
+          bv[t] = w;
+        }
+        acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
+        acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
+        acc[1][0] = Mfma<T>::mma(av[1], bv[0], acc[1][0]);
+        acc[1][1] = Mfma<T>::mma(av[1], bv[1], acc[1][1]);
+      }
+    }
+    cplx<SC>* Cb = C + (long)ob * cs;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        const int col = j0 + 8 * tj + (r16 >> 1);
+        if (col >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + 16 * ti + Mfma<T>::row(q, r);
+          if (row >= M) continue;
+          SC* dst = cpart ? &Cb[(long)row * ldc + col].im : &Cb[(long)row * ldc + col].re;
+          SC v = (SC)acc[ti][tj][r];
+          *dst = accumulate ? (SC)(*dst + v) : v;
+        }
+      }
+  }
+}
+
 // C (M x N, row-major ldc, element type SC)
 //   sum_batches = true : C  = [C +] sum_{b<nb} op(A_b) op(B_b)
 //   sum_batches = false: C_b = [C_b +] op(A_b) op(B_b), C_b = C + b*cs
@@ -106,6 +179,10 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
                        cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
   typedef typename Mfma<T>::acc_t acc_t;
   if (M <= 0 || N <= 0) return;
+  if (M < 32 || N < 16 || K < 8) {
+    wave_cgemm<T>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate);
+    return;
+  }
   cplx<T>* As = (cplx<T>*)lds;
   cplx<T>* Bs = As + GEMM_BK * GEMM_APAD;
   const int lane = tjm_lane();

@@ -301,46 +301,80 @@ struct LanczosLds {
 };
 
 // exp(-i t T) e_0 for the symmetric tridiagonal T = tridiag(beta, alpha, beta)
-// of size m <= 32, by thread 0: shift by alpha_0, split t into s pieces with
+// of size m <= 32: shift by alpha_0, split t into s pieces with
 // |t/s| * ||T - alpha_0||_inf <= 1/2 (Gershgorin) and sum 18 Taylor terms per
-// piece (remainder below 1e-21 of the norm).
+// piece (remainder below 1e-21 of the norm).  On a 64-wide wavefront lane i
+// owns row i and takes its neighbours' terms by shuffle; otherwise one thread
+// walks the rows.
 TJM_DEV void tridiag_exp_e0(int m, double t, LanczosLds& Lz) {
-  if (tjm_tid() != 0) return;
   const double mu = Lz.alpha[0];
-  double gers = 0.0;
-  for (int i = 0; i < m; ++i) {
-    double g = fabs(Lz.alpha[i] - mu) + (i > 0 ? Lz.beta[i - 1] : 0.0) + (i + 1 < m ? Lz.beta[i] : 0.0);
-    gers = fmax(gers, g);
-  }
-  int pieces = (int)ceil(fabs(t) * gers / 0.5);
-  if (pieces < 1) pieces = 1;
-  const double h = t / pieces;
-  double* ur = Lz.ur;
-  double* ui = Lz.ui;
-  double* tr = Lz.tr;
-  double* ti = Lz.ti;
-  for (int i = 0; i < m; ++i) { ur[i] = (i == 0) ? 1.0 : 0.0; ui[i] = 0.0; }
-  for (int pc = 0; pc < pieces; ++pc) {
-    for (int i = 0; i < m; ++i) { tr[i] = ur[i]; ti[i] = ui[i]; }
-    for (int kk = 1; kk <= 18; ++kk) {
-      // term <- (-i h / kk) (T - mu) term, in place with a one-element lag
-      const double f = h / kk;
-      double prev_r = 0.0, prev_i = 0.0;
-      for (int i = 0; i < m; ++i) {
-        double yr = (Lz.alpha[i] - mu) * tr[i], yi = (Lz.alpha[i] - mu) * ti[i];
-        if (i > 0) { yr += Lz.beta[i - 1] * prev_r; yi += Lz.beta[i - 1] * prev_i; }
-        if (i + 1 < m) { yr += Lz.beta[i] * tr[i + 1]; yi += Lz.beta[i] * ti[i + 1]; }
-        prev_r = tr[i]; prev_i = ti[i];
-        tr[i] = f * yi;                   // (-i f)(yr + i yi)
-        ti[i] = -f * yr;
-        ur[i] += tr[i]; ui[i] += ti[i];
+  if constexpr (TJM_WAVE >= TJM_KMAX) {
+    if (tjm_wave() != 0) return;
+    const int i = tjm_lane();
+    const double a = (i < m) ? Lz.alpha[i] - mu : 0.0;
+    const double bl = (i > 0 && i < m) ? Lz.beta[i - 1] : 0.0;      // T[i][i-1]
+    const double br = (i + 1 < m) ? Lz.beta[i] : 0.0;               // T[i][i+1]
+    double gers = fabs(a) + bl + br;
+    for (int s = TJM_WAVE / 2; s > 0; s >>= 1) gers = fmax(gers, tjm_shfl_xor(gers, s));
+    int pieces = (int)ceil(fabs(t) * gers / 0.5);
+    if (pieces < 1) pieces = 1;
+    const double h = t / pieces;
+    const int up = (i + 1) & (TJM_WAVE - 1), dn = (i + TJM_WAVE - 1) & (TJM_WAVE - 1);
+    double ur = (i == 0) ? 1.0 : 0.0, ui = 0.0;
+    for (int pc = 0; pc < pieces; ++pc) {
+      double tr = ur, ti = ui;
+      for (int kk = 1; kk <= 18; ++kk) {
+        const double upr = tjm_shfl(tr, up), upi = tjm_shfl(ti, up);
+        const double dnr = tjm_shfl(tr, dn), dni = tjm_shfl(ti, dn);
+        const double yr = a * tr + bl * dnr + br * upr;
+        const double yi = a * ti + bl * dni + br * upi;
+        const double f = h / kk;
+        tr = (i < m) ? f * yi : 0.0;            // (-i f)(yr + i yi)
+        ti = (i < m) ? -f * yr : 0.0;
+        ur += tr; ui += ti;
       }
     }
-  }
-  const double cr = cos(t * mu), ci = -sin(t * mu);
-  for (int i = 0; i < m; ++i) {
-    Lz.cre[i] = cr * ur[i] - ci * ui[i];
-    Lz.cim[i] = cr * ui[i] + ci * ur[i];
+    if (i < m) {
+      const double cr = cos(t * mu), ci = -sin(t * mu);
+      Lz.cre[i] = cr * ur - ci * ui;
+      Lz.cim[i] = cr * ui + ci * ur;
+    }
+  } else {
+    if (tjm_tid() != 0) return;
+    double gers = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double g = fabs(Lz.alpha[i] - mu) + (i > 0 ? Lz.beta[i - 1] : 0.0) + (i + 1 < m ? Lz.beta[i] : 0.0);
+      gers = fmax(gers, g);
+    }
+    int pieces = (int)ceil(fabs(t) * gers / 0.5);
+    if (pieces < 1) pieces = 1;
+    const double h = t / pieces;
+    double* ur = Lz.ur;
+    double* ui = Lz.ui;
+    double* tr = Lz.tr;
+    double* ti = Lz.ti;
+    for (int i = 0; i < m; ++i) { ur[i] = (i == 0) ? 1.0 : 0.0; ui[i] = 0.0; }
+    for (int pc = 0; pc < pieces; ++pc) {
+      for (int i = 0; i < m; ++i) { tr[i] = ur[i]; ti[i] = ui[i]; }
+      for (int kk = 1; kk <= 18; ++kk) {
+        const double f = h / kk;
+        double prev_r = 0.0, prev_i = 0.0;
+        for (int i = 0; i < m; ++i) {
+          double yr = (Lz.alpha[i] - mu) * tr[i], yi = (Lz.alpha[i] - mu) * ti[i];
+          if (i > 0) { yr += Lz.beta[i - 1] * prev_r; yi += Lz.beta[i - 1] * prev_i; }
+          if (i + 1 < m) { yr += Lz.beta[i] * tr[i + 1]; yi += Lz.beta[i] * ti[i + 1]; }
+          prev_r = tr[i]; prev_i = ti[i];
+          tr[i] = f * yi;
+          ti[i] = -f * yr;
+          ur[i] += tr[i]; ui[i] += ti[i];
+        }
+      }
+    }
+    const double cr = cos(t * mu), ci = -sin(t * mu);
+    for (int i = 0; i < m; ++i) {
+      Lz.cre[i] = cr * ur[i] - ci * ui[i];
+      Lz.cim[i] = cr * ui[i] + ci * ur[i];
+    }
   }
 }
 

@@ -27,6 +27,8 @@ TJM_DEV void tjm_sync() { __syncthreads(); }
 TJM_DEV double tjm_shfl_xor(double v, int m) { return __shfl_xor(v, m, TJM_WAVE); }
 TJM_DEV float tjm_shfl_xor(float v, int m) { return __shfl_xor(v, m, TJM_WAVE); }
 TJM_DEV int tjm_shfl_xor(int v, int m) { return __shfl_xor(v, m, TJM_WAVE); }
+// value held by lane `src` of this wavefront
+TJM_DEV double tjm_shfl(double v, int src) { return __shfl(v, src, TJM_WAVE); }
 
 TJM_DEV uint32_t tjm_mulhi(uint32_t a, uint32_t b) { return __umulhi(a, b); }
 

@@ -296,24 +296,95 @@ template <typename Tc> struct Tjm {
     tjm_sync();
   }
 
+  // True if every singular value of the upper-triangular leading n x n block
+  // of R (row-major, ld) provably exceeds sqrt(2 thr): sigma_min(R) >=
+  // 1 / ||R^{-1}||_F, with R^{-1} by back substitution (thread c builds
+  // column c in Y).  For a wide R [R1 R2], sigma_min >= sigma_min(R1).
+  TJM_DEV bool sv_floor_certified(const zd* R, int n, int ld, double thr) {
+    double acc = 0.0;
+    int bad = 0;
+    for (int c = tjm_tid(); c < n; c += TJM_NT) {
+      zd* x = Y + (long)c * n;
+      for (int i = c; i >= 0; --i) {
+        zd sum = cmk(i == c ? 1.0 : 0.0, 0.0);
+        for (int j = i + 1; j <= c; ++j) sum = sum - R[(long)i * ld + j] * x[j];
+        const zd rii = R[(long)i * ld + i];
+        const double d2 = abs2(rii);
+        if (!(d2 > 0.0)) { bad = 1; break; }
+        const zd xi = cmk((sum.re * rii.re + sum.im * rii.im) / d2, (sum.im * rii.re - sum.re * rii.im) / d2);
+        x[i] = xi;
+        acc += abs2(xi);
+      }
+    }
+    double b2 = (double)bad;
+    blk_sum2(acc, b2, sh.S);
+    return b2 == 0.0 && acc * 2.0 * thr < 1.0;
+  }
+
+  // Move the centre right with SVD truncation (normalisation sweeps after a
+  // jump): M_s = Q R; if R's singular values certifiably all survive the
+  // discard threshold the QR move is the result, otherwise R = U S V^H is
+  // truncated, M_s = Q U, next <- S V^H next.
   TJM_DEV void svd_move_right(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
+    const int m = chl * d;
+    if (!P.certify) {                                 // SVD of M_s itself
+      const unsigned long long ts_ = tjm_clock();
+      const int k = blk_svd(m, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      count(TJM_ST_FACT, 1ull);
+      since(TJM_ST_T_SVD, ts_);
+      absorb_right(site(mps, P, s + 1), k, chr, cn);
+      if (tjm_tid() == 0) bd[s + 1] = k;
+      tjm_sync();
+      return;
+    }
+    const int k0 = qr_site(Ms, chl, chr);             // Ms <- Q (m x k0), Cb <- R (k0 x chr)
     const unsigned long long ts_ = tjm_clock();
-    const int k = blk_svd(chl * d, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
-    count(TJM_ST_FACT, 1ull);
+    const double tot = norm2_site(Cb, (long)k0 * chr);
+    int k = k0;
+    if (!sv_floor_certified(Cb, k0, chr, P.svd_discard * tot)) {
+      k = blk_svd(k0, chr, Cb, w, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      count(TJM_ST_FACT, 1ull);
+      blk_cgemm<double>(m, k, k0, 1, true, cmat((const zd*)Ms, k0), cmat((const zd*)w, k), v, k, 0, false, sh.gemm);
+      tjm_sync();
+      copy(Ms, v, (long)m * k);
+      tjm_sync();
+    }
     since(TJM_ST_T_SVD, ts_);
     absorb_right(site(mps, P, s + 1), k, chr, cn);
     if (tjm_tid() == 0) bd[s + 1] = k;
     tjm_sync();
   }
 
+  // Mirror image: M_s = C B (LQ); C's singular values certified, or
+  // C = U S V^H truncated, M_s <- V^H B, prev <- prev U S.
   TJM_DEV void svd_move_left(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
+    const int n = d * chr;
+    if (!P.certify) {                                 // SVD of M_s itself
+      const unsigned long long ts_ = tjm_clock();
+      const int k = blk_svd(chl, n, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      count(TJM_ST_FACT, 1ull);
+      since(TJM_ST_T_SVD, ts_);
+      absorb_left(site(mps, P, s - 1), cp, chl, k);
+      if (tjm_tid() == 0) bd[s] = k;
+      tjm_sync();
+      return;
+    }
+    const int k0 = lq_site(Ms, chl, chr);             // Ms <- B (k0 x n), Cb <- C (chl x k0), Z <- C^H
     const unsigned long long ts_ = tjm_clock();
-    const int k = blk_svd(chl, d * chr, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
-    count(TJM_ST_FACT, 1ull);
+    const double tot = norm2_site(Cb, (long)chl * k0);
+    int k = k0;
+    if (!sv_floor_certified(Z, k0, chl, P.svd_discard * tot)) {
+      k = blk_svd(chl, k0, Cb, Cb, w, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      count(TJM_ST_FACT, 1ull);
+      blk_cgemm<double>(k, n, k0, 1, true, cmat((const zd*)w, k0), cmat((const zd*)Ms, n), v, n, 0, false, sh.gemm);
+      tjm_sync();
+      copy(Ms, v, (long)k * n);
+      tjm_sync();
+    }
     since(TJM_ST_T_SVD, ts_);
     absorb_left(site(mps, P, s - 1), cp, chl, k);
     if (tjm_tid() == 0) bd[s] = k;

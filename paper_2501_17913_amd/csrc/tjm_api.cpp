@@ -85,6 +85,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->record_bonds = 0;
   o->traj_base = 0;
   o->device = 0;
+  o->certify_sweeps = -1;
 }
 
 extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
@@ -266,6 +267,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   P.chi_max = chi_max; P.chi_cap = chi_cap; P.krylov_max = opt.krylov_max;
   P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = r->record_bonds;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
+  P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
   P.seed = seed; P.traj_base = opt.traj_base;
 

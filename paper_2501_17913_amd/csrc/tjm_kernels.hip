@@ -10,7 +10,7 @@
 #include "tjm_internal.h"
 
 template <typename Tc>
-__global__ __launch_bounds__(TJM_NT) void tjm_step_kernel(TjmParams P, int k) {
+__global__ __launch_bounds__(TJM_NT, 2) void tjm_step_kernel(TjmParams P, int k) {
   __shared__ Lds sh;
   extern __shared__ int dyn[];
   Tjm<Tc> t(P, sh, dyn, (int)blockIdx.x);
@@ -20,8 +20,23 @@ __global__ __launch_bounds__(TJM_NT) void tjm_step_kernel(TjmParams P, int k) {
     const int item = sh.item;
     __syncthreads();
     if (item >= P.n_traj) break;
-    if (k == 0) t.traj_init(item);
-    else t.traj_step(item, k);
+    t.traj_step(item, k);
+  }
+}
+
+// Psi(0) -> t = 0 observables and Phi = F_0 Psi(0), same work queue
+template <typename Tc>
+__global__ __launch_bounds__(TJM_NT, 2) void tjm_init_kernel(TjmParams P) {
+  __shared__ Lds sh;
+  extern __shared__ int dyn[];
+  Tjm<Tc> t(P, sh, dyn, (int)blockIdx.x);
+  for (;;) {
+    if (threadIdx.x == 0) sh.item = atomicAdd(P.counter, 1);
+    __syncthreads();
+    const int item = sh.item;
+    __syncthreads();
+    if (item >= P.n_traj) break;
+    t.traj_init(item);
   }
 }
 
@@ -62,10 +77,16 @@ hipError_t tjm_launch_reset(int* counter, hipStream_t s) {
 
 hipError_t tjm_launch_step(const TjmParams& P, int k, int workers, hipStream_t s) {
   const size_t dyn = tjm_dyn_lds_bytes(P.L);
-  if (P.mixed)
+  if (k == 0) {
+    if (P.mixed)
+      hipLaunchKernelGGL(tjm_init_kernel<float>, dim3(workers), dim3(TJM_NT), dyn, s, P);
+    else
+      hipLaunchKernelGGL(tjm_init_kernel<double>, dim3(workers), dim3(TJM_NT), dyn, s, P);
+  } else if (P.mixed) {
     hipLaunchKernelGGL(tjm_step_kernel<float>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
-  else
+  } else {
     hipLaunchKernelGGL(tjm_step_kernel<double>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
+  }
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct TjmParams {
   int n_jump, n_obs;
   int record_bonds;
   int mixed;                         // 1: complex-FP32 contractions
+  int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
   double dt, krylov_tol, svd_discard, deg_tol;
   uint64_t seed;
   uint32_t traj_base;                // global id of trajectory 0 of this run

@@ -67,6 +67,26 @@ def test_fp64_per_trajectory_parity(case):
         assert np.abs(res['sem'] - per.std(0, ddof=1) / np.sqrt(N)).max() < 1e-13
 
 
+@pytest.mark.parametrize("case", [inputs.small_cases()[4], inputs.small_cases()[5]],
+                         ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
+def test_fp64_certified_sweeps_parity(case):
+    # Post-jump normalisation sweeps with QR moves where a bound proves the
+    # SVD would discard nothing: the same states in another gauge, so the
+    # same jumps and bonds; observables agree to the conditioning of 1TDVP
+    # on bonds with Schmidt values near the discard threshold.
+    L, chi, init, n, N, g, gamma = case
+    seed = inputs.SEED + L
+    res = gpu_run(L, chi, init, n, N, g, gamma, seed, certify_sweeps=1)
+    worst = 0.0
+    for t in range(N):
+        ref, jl, bl = oracle_traj(L, chi, init, n, g, gamma, seed, t)
+        assert list(res['jumps'][t]) == jl
+        assert np.array_equal(res['bonds'][t], bl)
+        worst = max(worst, np.abs(res['per_traj'][t] - ref).max())
+    log("  certified sweeps: max |gpu - oracle| =", worst)
+    assert worst < 1e-8
+
+
 @pytest.mark.parametrize("case", [inputs.small_cases()[3], inputs.small_cases()[5]],
                          ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
 def test_mixed_precision_per_trajectory_parity(case):
