@@ -90,6 +90,8 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
     wall = time.perf_counter() - t0
     s1 = m.stats()
     m.close()                         # the rest of the job is not needed for timing
+    if s1["failed_traj"]:
+        raise RuntimeError("%d trajectories hit a non-finite norm" % s1["failed_traj"])
     launches = s1["step_launches"] - s0["step_launches"]
     kern_ms = s1["step_kernel_ms_total"] - s0["step_kernel_ms_total"]
     cmac = s1["cmac_mfma"] - s0["cmac_mfma"]

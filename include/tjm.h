@@ -103,6 +103,9 @@ typedef struct {
    * exponentials including their contractions, [6] bond-matrix absorption
    * and two-site products, [7] unused                                       */
   double phase_s[8];
+  int failed_traj;                /* trajectories flagged with a non-finite
+                                     norm so far (tjm_run_end then returns
+                                     TJM_E_NUMERIC)                           */
 } tjm_stats;
 
 /* Fills *opt with the defaults listed above. */

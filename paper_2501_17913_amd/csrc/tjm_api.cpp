@@ -463,6 +463,9 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
   RCHK(hipEventCreate(&r->ev0));
   RCHK(hipEventCreate(&r->ev1));
+  // The zero fills and uploads above run on the null stream, which a
+  // non-blocking stream does not wait for: finish them before any launch.
+  RCHK(hipDeviceSynchronize());
 
   // ---- F_0 ------------------------------------------------------------------
   RCHK(tjm_launch_reset(P.counter, r->stream));
@@ -519,6 +522,9 @@ static void collect_stats(tjm_model* m, Run* r) {
     s.one_site += q[TJM_ST_ONE_SITE]; s.two_site += q[TJM_ST_TWO_SITE];
     s.factorizations += q[TJM_ST_FACT]; s.jumps += q[TJM_ST_JUMPS];
   }
+  std::vector<int> fl(r->n_traj);
+  if (hipMemcpy(fl.data(), r->d_flags, fl.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+  for (int t = 0; t < r->n_traj; ++t) s.failed_traj += fl[t] != 0;
 }
 
 extern "C" tjm_status tjm_get_stats(const tjm_model* m, tjm_stats* out) {

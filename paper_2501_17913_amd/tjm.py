@@ -42,7 +42,7 @@ class Stats(C.Structure):
                 ("krylov_iters", C.c_ulonglong), ("expm_calls", C.c_ulonglong),
                 ("one_site", C.c_ulonglong), ("two_site", C.c_ulonglong),
                 ("factorizations", C.c_ulonglong), ("jumps", C.c_ulonglong),
-                ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8)]
+                ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8), ("failed_traj", C.c_int)]
 
     PHASES = ("total", "contract", "mix", "svd", "qr", "expm", "absorb")
 
