@@ -10,10 +10,16 @@ mixed precision (complex-FP32 matrix-core contractions, FP64 factorisations).
 Timed region: the K steps that follow W untimed warmup steps of the same run
 (F_0 and uploads happen before; inputs are resident in HBM).  value =
 trajectories x K / wall seconds.  The FP64 path is timed on the same steps
-for comparison (fp64_path).
+for trajectory ids 0..511 (fp64_path).
+
+roofline.traffic (HBM bytes per launch of the step kernel) comes from the
+FETCH_SIZE / WRITE_SIZE counter summary in profiles/, scaled by the same
+counters read for a plain copy of known size (--copy-calibration), and is
+reported only while the kernel sources still hash to the profiled ones.
 
 Prints ONE JSON line.
 """
+import hashlib
 import argparse
 import json
 import multiprocessing as mp
@@ -31,6 +37,34 @@ WORKLOADS = {
 }
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
 SEED = 0x250117913
+CSRC = os.path.join(ROOT, "paper_2501_17913_amd", "csrc")
+TRAFFIC = os.path.join(ROOT, "profiles", "tjm_step_kernel_C3_traffic.json")
+
+
+def kernel_sha():
+    """Hash of the device sources: counters taken from other sources are stale."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hpp", ".hip", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(workload, precision, W, K):
+    """Calibrated HBM bytes per step launch from the committed counter
+    summary, or None if it does not cover these sources and this window."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload or t.get("precision") != precision
+            or t.get("warmup") != W or t.get("steps") != K):
+        return None
+    fetch = sum(t["fetch_kib"]) / len(t["fetch_kib"]) * t["fetch_scale"]
+    write = sum(t["write_kib"]) / len(t["write_kib"]) * t["write_scale"]
+    return 1024.0 * (fetch + write)
 
 
 def _oracle_worker(args):
@@ -73,6 +107,11 @@ def cpu_baseline(L, chi, max_steps, budget=20.0):
                       % (cores, steps, budget)}
 
 
+def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
+    ms = tjm.selftest_copy(n_bytes, reps)
+    return {"copy_bytes": n_bytes, "reps": reps, "avg_ms": ms, "GB/s": 2 * n_bytes / (ms * 1e-3) / 1e9}
+
+
 def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
     """Run one job on the GPU; time steps warmup+1 .. warmup+K."""
     dt = 0.1
@@ -111,7 +150,7 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4, help="timed steps")
+    ap.add_argument("--steps", type=int, default=6, help="timed steps")
     ap.add_argument("--warmup", type=int, default=0, help="untimed steps before the timed ones")
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
@@ -120,12 +159,19 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy kernel used to calibrate the traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2501_17913_amd import models, tjm
+
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(tjm)), flush=True)
+        return
 
     w = dict(WORKLOADS[args.workload])
     if args.n_traj:
@@ -158,7 +204,8 @@ def main():
                                % (L, chi, T, N, args.precision, W + 1, W + K, n),
                    "L": L, "chi_max": chi, "n_traj": N, "dt": 0.1, "T": T, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": head["achieved_tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": head["achieved_tflops"] / peak, "traffic": None,
+                     "frac": head["achieved_tflops"] / peak,
+                     "traffic": traffic_per_launch(args.workload, args.precision, W, K),
                      "kernel": "tjm_step_kernel<%s>" % ("float" if prec == tjm.PREC_MIXED else "double"),
                      "avg_launch_ms": head["avg_ms"], "algorithmic_flop_per_launch": head["flops_per_launch"]},
         "workers": head["workers"],
@@ -166,8 +213,9 @@ def main():
         "phase_frac": head["phase_frac"],
     }
     if prec == tjm.PREC_MIXED and not args.no_fp64_compare:
-        f = measure(tjm, models, L, chi, N, T, tjm.PREC_FP64, W, K, args.workers)
-        out["fp64_path"] = {"value": f["value"], "ms_per_step": 1e3 * f["wall"] / K,
+        nf = min(N, args.fp64_traj)
+        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, args.workers)
+        out["fp64_path"] = {"value": f["value"], "n_traj": nf, "ms_per_step": 1e3 * f["wall"] / K,
                             "achieved_tflops": f["achieved_tflops"], "peak": PEAK_TFLOPS["fp64"],
                             "mixed_speedup": head["value"] / f["value"]}
     if not args.no_cpu_baseline:

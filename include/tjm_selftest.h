@@ -56,6 +56,13 @@ tjm_status tjm_selftest_expm(int n, const double *H, const double *v, double t,
 tjm_status tjm_selftest_philox(int count, const uint32_t *ctr, uint32_t k0, uint32_t k1,
                                uint32_t *out);
 
+/* A plain device-to-device streaming copy of n_bytes (a multiple of 16, at
+ * most 16 GiB) between two buffers the call allocates, launched reps times
+ * (1..1000) on the null stream; *avg_ms receives the mean launch time.  It
+ * reads and writes exactly n_bytes per launch, which calibrates the HBM
+ * traffic counters (FETCH_SIZE, WRITE_SIZE) against known byte counts. */
+tjm_status tjm_selftest_copy(long n_bytes, int reps, double *avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

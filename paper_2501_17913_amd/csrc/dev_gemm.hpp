@@ -12,6 +12,7 @@
 // the store.
 #pragma once
 #include <dev_common.hpp>
+#include <dev_operand.hpp>
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -36,67 +37,75 @@ template <> struct Mfma<float> {
   }
 };
 
-// A complex matrix operand op(X) with X stored row-major (leading dimension
-// ld) as cplx<S>; batch b starts bs elements after batch b-1.
-//   trans = false: op(X)[i][k] = X[i][k]     trans = true: op(X)[i][k] = X[k][i]
-//   conj applies complex conjugation on top.
-template <typename S> struct CMat {
-  const cplx<S>* p;
-  int ld;
-  long bs;
-  bool trans;
-  bool conj;
-};
-
-template <typename S> TJM_DEV CMat<S> cmat(const cplx<S>* p, int ld, long bs = 0,
-                                           bool trans = false, bool conj = false) {
-  CMat<S> m; m.p = p; m.ld = ld; m.bs = bs; m.trans = trans; m.conj = conj; return m;
-}
-
-template <typename T, typename S>
-TJM_DEV cplx<T> cmat_get(const CMat<S>& m, int b, int i, int k) {
-  const cplx<S>* q = m.p + (long)b * m.bs + (m.trans ? ((long)k * m.ld + i) : ((long)i * m.ld + k));
-  cplx<S> v = *q;
-  return cmk((T)v.re, m.conj ? (T)(-v.im) : (T)v.im);
-}
-
 // LDS staging of one k-chunk: A panel (BM x BK) stored k-major, B panel
 // (BK x BN) stored row-major, both converted to the compute type; padded rows
-// keep the fragment reads free of bank conflicts.
+// keep the fragment reads free of bank conflicts.  A chunk is first loaded
+// into registers (so the loads of chunk c+1 are in flight while chunk c runs
+// on the matrix cores), then stored to LDS.
 constexpr int GEMM_BM = 64, GEMM_BN = 32, GEMM_BK = 16;
 constexpr int GEMM_APAD = GEMM_BM + 2, GEMM_BPAD = GEMM_BN + 2;
 constexpr int GEMM_LDS_BYTES = (GEMM_BK * GEMM_APAD + GEMM_BK * GEMM_BPAD) * 16;
+constexpr int GEMM_AE = GEMM_BM * GEMM_BK / TJM_NT;   // A elements per thread
+constexpr int GEMM_BE = GEMM_BK * GEMM_BN / TJM_NT;   // B elements per thread
+static_assert(GEMM_AE * TJM_NT == GEMM_BM * GEMM_BK && GEMM_BE * TJM_NT == GEMM_BK * GEMM_BN,
+              "the workgroup must tile the staging panels exactly");
 
-template <typename T, typename S>
-TJM_DEV void stage_a(const CMat<S>& A, int b, int i0, int k0, int M, int K, cplx<T>* As) {
-  // element (i, k) of the panel; walk the index that is contiguous in memory
-  for (int e = tjm_tid(); e < GEMM_BM * GEMM_BK; e += TJM_NT) {
-    int i, k;
-    if (A.trans) { i = e % GEMM_BM; k = e / GEMM_BM; }
-    else { k = e % GEMM_BK; i = e / GEMM_BK; }
-    cplx<T> v = cmk((T)0, (T)0);
-    if (i0 + i < M && k0 + k < K) v = cmat_get<T>(A, b, i0 + i, k0 + k);
-    As[k * GEMM_APAD + i] = v;
-  }
+// panel coordinates of the u-th element a thread stages
+TJM_DEV void a_coord(bool trans, int u, int& i, int& k) {
+  const int e = tjm_tid() + u * TJM_NT;
+  if (trans) { i = e % GEMM_BM; k = e / GEMM_BM; }
+  else { k = e % GEMM_BK; i = e / GEMM_BK; }
+}
+TJM_DEV void b_coord(bool trans, int u, int& k, int& j) {
+  const int e = tjm_tid() + u * TJM_NT;
+  if (trans) { k = e % GEMM_BK; j = e / GEMM_BK; }
+  else { j = e % GEMM_BN; k = e / GEMM_BN; }
 }
 
-template <typename T, typename S>
-TJM_DEV void stage_b(const CMat<S>& B, int b, int k0, int j0, int K, int N, cplx<T>* Bs) {
-  for (int e = tjm_tid(); e < GEMM_BK * GEMM_BN; e += TJM_NT) {
+template <typename T, class OA, class OB>
+TJM_DEV void gemm_load(const OA& A, const OB& B, int b, int i0, int j0, int k0, int M, int N, int K,
+                       cplx<T>* ra, cplx<T>* rb) {
+  int ia[GEMM_AE], ka[GEMM_AE], kb[GEMM_BE], jb[GEMM_BE];
+  bool oa[GEMM_AE], ob[GEMM_BE];
+#pragma unroll
+  for (int u = 0; u < GEMM_AE; ++u) {
+    int i, k;
+    a_coord(A.trans, u, i, k);
+    ia[u] = i0 + i; ka[u] = k0 + k;
+    oa[u] = ia[u] < M && ka[u] < K;
+  }
+#pragma unroll
+  for (int u = 0; u < GEMM_BE; ++u) {
     int k, j;
-    if (B.trans) { k = e % GEMM_BK; j = e / GEMM_BK; }
-    else { j = e % GEMM_BN; k = e / GEMM_BN; }
-    cplx<T> v = cmk((T)0, (T)0);
-    if (k0 + k < K && j0 + j < N) v = cmat_get<T>(B, b, k0 + k, j0 + j);
-    Bs[k * GEMM_BPAD + j] = v;
+    b_coord(B.trans, u, k, j);
+    kb[u] = k0 + k; jb[u] = j0 + j;
+    ob[u] = kb[u] < K && jb[u] < N;
+  }
+  A.template gather<T, GEMM_AE>(b, ia, ka, oa, ra);
+  B.template gather<T, GEMM_BE>(b, kb, jb, ob, rb);
+}
+
+template <typename T>
+TJM_DEV void gemm_store(bool ta, bool tb, const cplx<T>* ra, const cplx<T>* rb, cplx<T>* As, cplx<T>* Bs) {
+#pragma unroll
+  for (int u = 0; u < GEMM_AE; ++u) {
+    int i, k;
+    a_coord(ta, u, i, k);
+    As[k * GEMM_APAD + i] = ra[u];
+  }
+#pragma unroll
+  for (int u = 0; u < GEMM_BE; ++u) {
+    int k, j;
+    b_coord(tb, u, k, j);
+    Bs[k * GEMM_BPAD + j] = rb[u];
   }
 }
 
 // Small products: each wavefront owns 32 x 16 complex blocks and feeds the
 // matrix cores straight from memory (no LDS, no workgroup barriers).
-template <typename T, typename SA, typename SB, typename SC>
+template <typename T, class OA, class OB, typename SC>
 TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
-                        const CMat<SA>& A, const CMat<SB>& B,
+                        const OA& A, const OB& B,
                         cplx<SC>* C, int ldc, long cs, bool accumulate) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int lane = tjm_lane();
@@ -119,6 +128,7 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
     const int b_lo = sum_batches ? 0 : ob;
     const int b_hi = sum_batches ? nb : ob + 1;
     for (int b = b_lo; b < b_hi; ++b) {
+#pragma unroll 2
       for (int k0 = 0; k0 < K; k0 += 2) {
         const int kc = k0 + kq;
         const bool kin = kc < K;
@@ -128,14 +138,14 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
           const int row = i0 + 16 * t + r16;
           T v = (T)0;
           if (kin && row < M) {
-            cplx<T> e = cmat_get<T>(A, b, row, kc);
+            cplx<T> e = A.template get<T>(b, row, kc);
             v = kp ? e.im : e.re;
           }
           av[t] = v;
           const int col = j0 + 8 * t + (r16 >> 1);
           T w = (T)0;
           if (kin && col < N) {
-            cplx<T> e = cmat_get<T>(B, b, kc, col);
+            cplx<T> e = B.template get<T>(b, kc, col);
             w = (kp == cpart) ? e.re : (kp ? -e.im : e.im);
           }
           bv[t] = w;
@@ -173,9 +183,9 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
 // workgroup walks 64 x 32 (complex) output tiles, staging k-chunks of 16 in
 // LDS (`lds`, GEMM_LDS_BYTES); wavefront w owns the 32 x 16 sub-tile
 // (w / 2, w % 2).  The caller synchronises before reading C.
-template <typename T, typename SA, typename SB, typename SC>
+template <typename T, class OA, class OB, typename SC>
 TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
-                       const CMat<SA>& A, const CMat<SB>& B,
+                       const OA& A, const OB& B,
                        cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
   typedef typename Mfma<T>::acc_t acc_t;
   if (M <= 0 || N <= 0) return;
@@ -196,6 +206,7 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
   const int nti = (M + GEMM_BM - 1) / GEMM_BM, ntj = (N + GEMM_BN - 1) / GEMM_BN;
   const int nout = sum_batches ? 1 : nb;
   const int ntiles = nout * nti * ntj;
+  const int nkc = (K + GEMM_BK - 1) / GEMM_BK;
   for (int it = 0; it < ntiles; ++it) {
     const int ob = it / (nti * ntj);
     const int rem = it - ob * (nti * ntj);
@@ -205,29 +216,32 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
     acc[0][0] = Mfma<T>::zero(); acc[0][1] = Mfma<T>::zero();
     acc[1][0] = Mfma<T>::zero(); acc[1][1] = Mfma<T>::zero();
     const int b_lo = sum_batches ? 0 : ob;
-    const int b_hi = sum_batches ? nb : ob + 1;
-    for (int b = b_lo; b < b_hi; ++b) {
-      for (int k0 = 0; k0 < K; k0 += GEMM_BK) {
-        stage_a<T>(A, b, i0, k0, M, K, As);
-        stage_b<T>(B, b, k0, j0, K, N, Bs);
-        tjm_sync();
-        const int kend = K - k0 < GEMM_BK ? K - k0 : GEMM_BK;
-        for (int kk = 0; kk < kend; kk += 2) {
-          const int kc = kk + kq;                 // < GEMM_BK; zero-padded past K
-          T av[2], bv[2];
+    const int nchunk = (sum_batches ? nb : 1) * nkc;
+    cplx<T> ra[GEMM_AE], rb[GEMM_BE];
+    gemm_load<T>(A, B, b_lo, i0, j0, 0, M, N, K, ra, rb);
+    for (int c = 0; c < nchunk; ++c) {
+      tjm_sync();                                  // LDS free again
+      gemm_store<T>(A.trans, B.trans, ra, rb, As, Bs);
+      tjm_sync();
+      if (c + 1 < nchunk) {                        // next chunk in flight
+        const int cn = c + 1;
+        gemm_load<T>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * GEMM_BK, M, N, K, ra, rb);
+      }
+#pragma unroll 2
+      for (int kk = 0; kk < GEMM_BK; kk += 2) {    // zero-padded past K
+        const int kc = kk + kq;
+        T av[2], bv[2];
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const cplx<T> ea = As[kc * GEMM_APAD + wi + 16 * t + r16];
-            av[t] = kp ? ea.im : ea.re;
-            const cplx<T> eb = Bs[kc * GEMM_BPAD + wj + 8 * t + (r16 >> 1)];
-            bv[t] = (kp == cpart) ? eb.re : (kp ? -eb.im : eb.im);
-          }
-          acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
-          acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
-          acc[1][0] = Mfma<T>::mma(av[1], bv[0], acc[1][0]);
-          acc[1][1] = Mfma<T>::mma(av[1], bv[1], acc[1][1]);
+        for (int t = 0; t < 2; ++t) {
+          const cplx<T> ea = As[kc * GEMM_APAD + wi + 16 * t + r16];
+          av[t] = kp ? ea.im : ea.re;
+          const cplx<T> eb = Bs[kc * GEMM_BPAD + wj + 8 * t + (r16 >> 1)];
+          bv[t] = (kp == cpart) ? eb.re : (kp ? -eb.im : eb.im);
         }
-        tjm_sync();
+        acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
+        acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
+        acc[1][0] = Mfma<T>::mma(av[1], bv[0], acc[1][0]);
+        acc[1][1] = Mfma<T>::mma(av[1], bv[1], acc[1][1]);
       }
     }
     cplx<SC>* Cb = C + (long)ob * cs;
@@ -247,4 +261,5 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
         }
       }
   }
+  tjm_sync();                                      // LDS free for the caller
 }

@@ -237,11 +237,15 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
     if (tjm_lane() == 0) SL.s[c] = sqrt(a);
   }
   tjm_sync();
+  // a non-finite norm sorts as -1, so the order is a permutation whatever
+  // the data (the trajectory is flagged later by its norm check)
   for (int c = tid; c < nc; c += TJM_NT) {
-    const double sc = SL.s[c];
+    double sc = SL.s[c];
+    if (!(sc == sc) || sc > 1.7e308) sc = -1.0;
     int rank = 0;
     for (int i = 0; i < nc; ++i) {
       double si = SL.s[i];
+      if (!(si == si) || si > 1.7e308) si = -1.0;
       if (si > sc || (si == sc && i < c)) ++rank;
     }
     SL.order[rank] = c;

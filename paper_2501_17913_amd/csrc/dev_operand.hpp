@@ -1,0 +1,173 @@
+// Operands of the workgroup GEMM.
+//
+// An operand is any object with
+//   bool trans;                                 which index is contiguous
+//   template <typename T> cplx<T> get(int b, int i, int k) const;
+//   template <typename T, int NE> void gather(int b, const int* i, const int* k,
+//                                             const bool* ok, cplx<T>* out) const;
+// get returns element (i, k) of batch b converted to the compute type T;
+// gather fetches NE elements at once (zero where ok is false), so that their
+// loads are in flight together.  trans = false means k (the second index)
+// runs contiguously in memory, trans = true means i does; the stager walks
+// the contiguous index across neighbouring threads.
+#pragma once
+#include <dev_common.hpp>
+#include "tjm_params.h"
+
+// A stored complex matrix: op(X) with X row-major (leading dimension ld) as
+// cplx<S>; batch b starts bs elements after batch b-1.
+//   trans = false: op(X)[i][k] = X[i][k]     trans = true: op(X)[i][k] = X[k][i]
+//   conj applies complex conjugation on top.
+template <typename S> struct CMat {
+  const cplx<S>* p;
+  int ld;
+  long bs;
+  bool trans;
+  bool conj;
+  template <typename T> TJM_DEV cplx<T> get(int b, int i, int k) const {
+    const cplx<S> v = p[(long)b * bs + (trans ? ((long)k * ld + i) : ((long)i * ld + k))];
+    return cmk((T)v.re, conj ? (T)(-v.im) : (T)v.im);
+  }
+  template <typename T, int NE>
+  TJM_DEV void gather(int b, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) out[u] = ok[u] ? get<T>(b, ii[u], kk[u]) : cmk((T)0, (T)0);
+  }
+};
+
+template <typename S> TJM_DEV CMat<S> cmat(const cplx<S>* p, int ld, long bs = 0,
+                                           bool trans = false, bool conj = false) {
+  CMat<S> m; m.p = p; m.ld = ld; m.bs = bs; m.trans = trans; m.conj = conj; return m;
+}
+
+// sum over the nonzeros (wi, si, v) of one mixing row of v * x(wi, si)
+template <typename T, typename S>
+TJM_DEV cplx<T> mix_row(const int* rp, const MixEnt* ent, int row, const cplx<S>* base, long sw, long ss) {
+  T xr = 0, xi = 0;
+  const int q1 = rp[row + 1];
+  for (int q = rp[row]; q < q1; ++q) {
+    const MixEnt m = ent[q];
+    const cplx<S> x = base[(long)m.w * sw + (long)m.s * ss];
+    const T mr = (T)m.re, mi = (T)m.im;
+    xr += mr * (T)x.re - mi * (T)x.im;
+    xi += mr * (T)x.im + mi * (T)x.re;
+  }
+  return cmk(xr, xi);
+}
+
+// NE mixed elements; element u sums row row[u] at offset base[u].  When all
+// rows agree (the staging layouts make them agree) the row's nonzeros are
+// read once and the NE source loads of each nonzero are issued together.
+template <typename T, typename S, int NE>
+TJM_DEV void mix_gather(const int* rp, const MixEnt* ent, const cplx<S>* src, long sw, long ss,
+                        const int* row, const long* base, const bool* ok, cplx<T>* out) {
+  // only in-range elements name a mixing row (an out-of-range one may not)
+  int r0 = -1;
+  bool same = true;
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    if (!ok[u]) continue;
+    if (r0 < 0) r0 = row[u];
+    else same = same && row[u] == r0;
+  }
+  if (r0 < 0) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) out[u] = cmk((T)0, (T)0);
+    return;
+  }
+  if (same) {
+    T xr[NE], xi[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) { xr[u] = 0; xi[u] = 0; }
+    const int q1 = rp[r0 + 1];
+    for (int q = rp[r0]; q < q1; ++q) {
+      const MixEnt m = ent[q];
+      const long off = (long)m.w * sw + (long)m.s * ss;
+      const T mr = (T)m.re, mi = (T)m.im;
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        if (!ok[u]) continue;
+        const cplx<S> x = src[base[u] + off];
+        xr[u] += mr * (T)x.re - mi * (T)x.im;
+        xi[u] += mr * (T)x.im + mi * (T)x.re;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) out[u] = ok[u] ? cmk(xr[u], xi[u]) : cmk((T)0, (T)0);
+  } else {
+#pragma unroll
+    for (int u = 0; u < NE; ++u)
+      out[u] = ok[u] ? mix_row<T>(rp, ent, row[u], src + base[u], sw, ss) : cmk((T)0, (T)0);
+  }
+}
+
+// The MPO-mixed stage-1 result, formed while it is staged (never stored).
+// src holds, for every input channel wi, the rows (a, si) of width nb_:
+// src[wi][a][si][b] at wi * sw + a * sa + si * ss + b.  For output channel
+// wo (the batch):
+//   MixRows:  op_wo[(a, so)][b] = sum_{(wi, si, v) in row (wo, so)} v src[wi][a][si][b]
+//   MixCols:  op_wo[a][(so, b)] = the same sum
+// with the mixing rows indexed wo * dph + so.
+template <typename S> struct MixRows {
+  const cplx<S>* src;
+  const int* rp;
+  const MixEnt* ent;
+  int dph;
+  long sw, sa, ss;
+  bool trans;
+  template <typename T> TJM_DEV cplx<T> get(int wo, int i, int b) const {
+    const int a = i / dph, so = i - a * dph;
+    return mix_row<T>(rp, ent, wo * dph + so, src + (long)a * sa + b, sw, ss);
+  }
+  template <typename T, int NE>
+  TJM_DEV void gather(int wo, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+    int row[NE];
+    long base[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int a = ii[u] / dph, so = ii[u] - a * dph;
+      row[u] = wo * dph + so;
+      base[u] = (long)a * sa + kk[u];
+    }
+    mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
+  }
+};
+
+template <typename S> struct MixCols {
+  const cplx<S>* src;
+  const int* rp;
+  const MixEnt* ent;
+  int dph, nb_;
+  long sw, sa, ss;
+  bool trans;
+  template <typename T> TJM_DEV cplx<T> get(int wo, int a, int k) const {
+    const int so = k / nb_, b = k - so * nb_;
+    return mix_row<T>(rp, ent, wo * dph + so, src + (long)a * sa + b, sw, ss);
+  }
+  template <typename T, int NE>
+  TJM_DEV void gather(int wo, const int* aa, const int* kk, const bool* ok, cplx<T>* out) const {
+    int row[NE];
+    long base[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int so = kk[u] / nb_, b = kk[u] - so * nb_;
+      row[u] = wo * dph + so;
+      base[u] = (long)aa[u] * sa + b;
+    }
+    mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
+  }
+};
+
+template <typename S>
+TJM_DEV MixRows<S> mix_rows(const cplx<S>* src, const int* rp, const MixEnt* ent, int dph, long sw, long sa,
+                            long ss) {
+  MixRows<S> m; m.src = src; m.rp = rp; m.ent = ent; m.dph = dph; m.sw = sw; m.sa = sa; m.ss = ss;
+  m.trans = false; return m;
+}
+
+template <typename S>
+TJM_DEV MixCols<S> mix_cols(const cplx<S>* src, const int* rp, const MixEnt* ent, int dph, int nb_, long sw,
+                            long sa, long ss) {
+  MixCols<S> m; m.src = src; m.rp = rp; m.ent = ent; m.dph = dph; m.nb_ = nb_; m.sw = sw; m.sa = sa;
+  m.ss = ss; m.trans = false; return m;
+}

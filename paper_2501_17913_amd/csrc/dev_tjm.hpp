@@ -42,7 +42,7 @@ template <typename Tc> struct Tjm {
   int* bA;            // LDS [L+1]: bonds of the sampling MPS
   int* bB;            // LDS [L+1]: bonds of the sampling-layer copy
   // worker scratch
-  zc* env; zd* smps; zd* Q; zd* w; zd* v; zc* T1; zc* T2; zd* X; zd* Y; zd* Z; zd* Cb; double* wts;
+  zc* env; zd* smps; zd* Q; zd* w; zd* v; zc* T1; zd* X; zd* Y; zd* Z; zd* Cb; double* wts;
   int d, L;
 
   TJM_DEV Tjm(const TjmParams& p, Lds& s, int* dyn, int worker) : P(p), sh(s) {
@@ -57,12 +57,14 @@ template <typename Tc> struct Tjm {
     w = (zd*)(base + P.off_w);
     v = (zd*)(base + P.off_v);
     T1 = (zc*)(base + P.off_T1);
-    T2 = (zc*)(base + P.off_T2);
     X = (zd*)(base + P.off_X);
     Y = (zd*)(base + P.off_Y);
     Z = (zd*)(base + P.off_Z);
     Cb = (zd*)(base + P.off_C);
     wts = (double*)(base + P.off_wts);
+    if (tjm_tid() == 0)                              // environment slot of each bond
+      for (int b = 0; b < L + 2; ++b) slot[b] = b;
+    tjm_sync();
   }
 
   TJM_DEV zc* envp(int bond) { return env + (long)slot[bond] * P.env_cap; }
@@ -71,34 +73,6 @@ template <typename Tc> struct Tjm {
   TJM_DEV void since(int i, unsigned long long t0) { if (tjm_tid() == 0) sh.st[i] += tjm_clock() - t0; }
   TJM_DEV static zd* site(zd* mps, const TjmParams& P, int s) { return mps + P.site_off[s]; }
 
-  // ------------------------------------------------------------------
-  // MPO mixing stage: dst[wo][a][so][b] = sum_{(wi,si,val) in row (wo,so)}
-  //                                       val * src[wi][a][si][b]
-  // (src has dph physical values per channel, dst the same)
-  // ------------------------------------------------------------------
-  TJM_DEV void mix(int Dout, int A, int dph, int B, const int* rp, const MixEnt* ent,
-                   const zc* src, zc* dst) {
-    const unsigned long long t0 = tjm_clock();
-    const long per = (long)A * dph * B;
-    const long tot = (long)Dout * per;
-    for (long e = tjm_tid(); e < tot; e += TJM_NT) {
-      int wo = (int)(e / per);
-      long r = e - wo * per;
-      int a = (int)(r / ((long)dph * B));
-      int r2 = (int)(r - (long)a * dph * B);
-      int so = r2 / B, b = r2 % B;
-      int row = wo * dph + so;
-      Tc xr = 0, xi = 0;
-      for (int q = rp[row]; q < rp[row + 1]; ++q) {
-        MixEnt m = ent[q];
-        zc x = src[(long)m.w * per + ((long)a * dph + m.s) * B + b];
-        xr += (Tc)m.re * x.re - (Tc)m.im * x.im;
-        xi += (Tc)m.re * x.im + (Tc)m.im * x.re;
-      }
-      dst[e] = cmk(xr, xi);
-    }
-    since(TJM_ST_T_MIX, t0);
-  }
   TJM_DEV unsigned long long mix_nnz(int Dout, int dph, const int* rp) {
     return (unsigned long long)(rp[Dout * dph] - rp[0]);
   }
@@ -118,10 +92,9 @@ template <typename Tc> struct Tjm {
     blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
                   T1, d * chr, (long)chl * d * chr, false, sh.gemm);
     tjm_sync();
-    mix(Dr, chl, d, chr, rp, P.mixL, T1, T2);
-    tjm_sync();
     blk_cgemm<Tc>(chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
-                  cmat((const zc*)T2, chr, (long)chl * d * chr), Lnew, chr, (long)chr * chr, false, sh.gemm);
+                  mix_rows((const zc*)T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
+                  Lnew, chr, (long)chr * chr, false, sh.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chr * chr * chl * d);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dr, d, rp) * chl * chr);
@@ -136,9 +109,8 @@ template <typename Tc> struct Tjm {
     blk_cgemm<Tc>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
                   T1, chr, (long)chl * d * chr, false, sh.gemm);
     tjm_sync();
-    mix(Dl, chl, d, chr, rp, P.mixR, T1, T2);
-    tjm_sync();
-    blk_cgemm<Tc>(chl, chl, d * chr, Dl, false, cmat((const zc*)T2, d * chr, (long)chl * d * chr),
+    blk_cgemm<Tc>(chl, chl, d * chr, Dl, false,
+                  mix_cols((const zc*)T1, rp, P.mixR, d, chr, (long)chl * d * chr, (long)d * chr, (long)chr),
                   cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, sh.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
@@ -159,9 +131,8 @@ template <typename Tc> struct Tjm {
       blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
                     t->T1, d * chr, (long)chl * d * chr, false, t->sh.gemm);
       tjm_sync();
-      t->mix(Dr, chl, d, chr, rp, P.mixL, t->T1, t->T2);
-      tjm_sync();
-      blk_cgemm<Tc>(chl * d, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d * chr),
+      blk_cgemm<Tc>(chl * d, chr, chr, Dr, true,
+                    mix_rows((const zc*)t->T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
                     cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chl * d * chr * chr);
@@ -180,9 +151,8 @@ template <typename Tc> struct Tjm {
       blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
                     t->T1, d2 * chr, (long)chl * d2 * chr, false, t->sh.gemm);
       tjm_sync();
-      t->mix(Dr, chl, d2, chr, rp, P.mix2, t->T1, t->T2);
-      tjm_sync();
-      blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true, cmat((const zc*)t->T2, chr, (long)chl * d2 * chr),
+      blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true,
+                    mix_rows((const zc*)t->T1, rp, P.mix2, d2, (long)chl * d2 * chr, (long)d2 * chr, (long)chr),
                     cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d2 * chr + (unsigned long long)Dr * chl * d2 * chr * chr);
@@ -584,14 +554,192 @@ template <typename Tc> struct Tjm {
   }
 
   // ------------------------------------------------------------------
+  // Transfer-matrix environments of an MPS in any gauge (FP64):
+  //   right R_s = sum_sig M_s^sig R_{s+1} M_s^sig^H  (b_s x b_s, R_L = 1),
+  //   left  F_{s+1} = sum_sig M_s^sig^H F_s M_s^sig   (F_0 = 1),
+  // and rho_s[sig][sig'] = Tr(F_s M_s^sig R_{s+1} M_s^sig'^H), the
+  // (unnormalised) reduced density matrix of site s; <psi|psi> = R_0.
+  // R_s lives in environment slot s (free during the jump process).
+  // ------------------------------------------------------------------
+  TJM_DEV zd* renv(int s) { return (zd*)envp(s); }
+
+  TJM_DEV double envs_right(const zd* mps, const int* bd) {
+    const unsigned long long t0 = tjm_clock();
+    zd* RL = renv(L);
+    if (tjm_tid() == 0) RL[0] = cmk(1.0, 0.0);
+    tjm_sync();
+    for (int s = L - 1; s >= 0; --s) {
+      const zd* M = site((zd*)mps, P, s);
+      const int chl = bd[s], chr = bd[s + 1];
+      blk_cgemm<double>(chl * d, chr, chr, 1, true, cmat(M, chr), cmat((const zd*)renv(s + 1), chr), X, chr, 0,
+                        false, sh.gemm);
+      tjm_sync();
+      blk_cgemm<double>(chl, chl, d * chr, 1, true, cmat((const zd*)X, d * chr), cmat(M, d * chr, 0, true, true),
+                        renv(s), chl, 0, false, sh.gemm);
+      tjm_sync();
+      count(TJM_ST_CMAC_FP64, 2ull * chl * d * chr * chr);
+    }
+    since(TJM_ST_T_ENV, t0);
+    return renv(0)[0].re;
+  }
+
+  // Left sweep of F with rho_s at every site: jump weights (wts) and/or the
+  // site observables (obs_out, normalised by Tr rho).  Needs envs_right.
+  TJM_DEV void envs_left_rho(const zd* mps, const int* bd, bool weights, double* obs_out) {
+    const unsigned long long t0 = tjm_clock();
+    zd* F = Y;
+    zd* Fn = Z;
+    if (tjm_tid() == 0) F[0] = cmk(1.0, 0.0);
+    tjm_sync();
+    for (int s = 0; s < L; ++s) {
+      const zd* M = site((zd*)mps, P, s);
+      const int chl = bd[s], chr = bd[s + 1];
+      // V = F M  (chl x d chr),  U = V R_{s+1}  ((chl d) x chr)
+      blk_cgemm<double>(chl, d * chr, chl, 1, true, cmat((const zd*)F, chl), cmat(M, d * chr), X, d * chr, 0,
+                        false, sh.gemm);
+      tjm_sync();
+      blk_cgemm<double>(chl * d, chr, chr, 1, true, cmat((const zd*)X, chr), cmat((const zd*)renv(s + 1), chr),
+                        Cb, chr, 0, false, sh.gemm);
+      tjm_sync();
+      double r00 = 0, r11 = 0, rr = 0, ri = 0;
+      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
+        const int a = (int)(e / chr), b = (int)(e % chr);
+        const zd u0 = Cb[((long)a * 2 + 0) * chr + b], u1 = Cb[((long)a * 2 + 1) * chr + b];
+        const zd m0 = M[((long)a * 2 + 0) * chr + b], m1 = M[((long)a * 2 + 1) * chr + b];
+        r00 += cdotc(m0, u0).re;
+        r11 += cdotc(m1, u1).re;
+        const zd c = cdotc(m1, u0);                 // U^0 conj(M^1)
+        rr += c.re; ri += c.im;
+      }
+      blk_sum4(r00, r11, rr, ri, sh.S);
+      if (tjm_tid() == 0) {
+        sh.rho[0] = r00; sh.rho[1] = r11; sh.rho[2] = rr; sh.rho[3] = ri;
+        if (weights)
+          for (int q = P.jptr[s]; q < P.jptr[s + 1]; ++q) {
+            const int j = P.jidx[q];
+            wts[j] = P.jump_rate[j] * tr_l_rho_ld((const zd*)P.jump_op + (long)j * 4);
+          }
+      }
+      tjm_sync();
+      if (obs_out) measure(s, obs_out);
+      if (s + 1 < L) {                               // F_{s+1} = M^H V over (a, sig)
+        blk_cgemm<double>(chr, chr, chl * d, 1, true, cmat(M, chr, 0, true, true), cmat((const zd*)X, chr), Fn, chr,
+                          0, false, sh.gemm);
+        tjm_sync();
+        zd* t = F; F = Fn; Fn = t;
+      }
+      count(TJM_ST_CMAC_FP64, (unsigned long long)chl * chl * d * chr + (unsigned long long)chl * d * chr * chr +
+                                  (s + 1 < L ? (unsigned long long)chr * chr * chl * d : 0ull));
+    }
+    since(TJM_ST_T_ENV, t0);
+  }
+
+  // pick the jump from wts (rule of Sec. "Stochastic jump process" with the
+  // weights normalised by their sum): first index whose running sum exceeds
+  // r W; -1 if W <= 1e-300
+  TJM_DEV int pick_jump(double r) {
+    if (tjm_tid() == 0) {
+      double tot = 0.0;
+      for (int j = 0; j < P.n_jump; ++j) tot += wts[j];
+      int m = -1;
+      if (tot > 1e-300) {
+        const double thr = r * tot;
+        double cum = 0.0;
+        for (int j = 0; j < P.n_jump; ++j) {
+          cum += wts[j];
+          if (cum > thr) { m = j; break; }
+        }
+        if (m < 0)
+          for (int j = P.n_jump - 1; j >= 0; --j)
+            if (wts[j] > 0.0) { m = j; break; }
+      }
+      sh.pick = m;
+    }
+    tjm_sync();
+    return sh.pick;
+  }
+
+  // apply jump m at its site (centre there), normalise, then the
+  // normalisation sweeps through successive SVDs: site -> right end -> 0
+  TJM_DEV void apply_jump(zd* mps, int* bd, int m, double* obs_out) {
+    const int sj = P.jump_site[m];
+    zd* M = site(mps, P, sj);
+    const zd* Op = (const zd*)P.jump_op + (long)m * 4;
+    const int chl = bd[sj], chr = bd[sj + 1];
+    for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
+      int a = (int)(e / chr), b = (int)(e % chr);
+      zd in0 = M[((long)a * 2 + 0) * chr + b], in1 = M[((long)a * 2 + 1) * chr + b];
+      M[((long)a * 2 + 0) * chr + b] = Op[0] * in0 + Op[1] * in1;
+      M[((long)a * 2 + 1) * chr + b] = Op[2] * in0 + Op[3] * in1;
+    }
+    tjm_sync();
+    const long n = (long)chl * d * chr;
+    const double nn = norm2_site(M, n);
+    scale_site(M, n, 1.0 / sqrt(nn));
+    count(TJM_ST_JUMPS, 1ull);
+    for (int s = sj; s < L - 1; ++s) svd_move_right(mps, bd, s);
+    for (int s = L - 1; s >= 1; --s) {
+      if (obs_out) { site_rho(site(mps, P, s), bd[s], bd[s + 1]); measure(s, obs_out); }
+      svd_move_left(mps, bd, s);
+    }
+    finish(mps, bd, obs_out);
+  }
+
+  // ------------------------------------------------------------------
   // Jump process J_eps (Sec. "Stochastic jump process").  Entry: centre at
-  // site 0.  Exit: normalised, centre at site 0.  If obs_out is non-null,
-  // the site observables of the final state are written there.
+  // site 0, the other sites right-canonical.  Exit (if keep): normalised,
+  // centre at site 0, other sites right-canonical.  If obs_out is non-null,
+  // the site observables of the resulting state are written there; a state
+  // that is not kept is only measured.
   // Returns the applied jump index, -1 for none, -2 on a non-finite norm.
+  //
+  // The decisions are those of the sweep order of the paper (QR sweep to the
+  // right end for delta p, LQ sweep back for the weights, QR moves to the
+  // jump site): delta p = 1 - <psi|psi> and the weights are gauge-invariant
+  // traces, taken here from transfer-matrix environments, and the QR / LQ
+  // moves change no bond dimension when b_{s+1} <= d b_s and b_s <= d b_{s+1}
+  // for every bond; otherwise (or with P.sweep_jumps) the sweeps are run as
+  // printed.
   // ------------------------------------------------------------------
   TJM_DEV int jump_process(zd* mps, int* bd, const double* Dtab, uint32_t step, uint32_t branch,
-                           double* obs_out) {
+                           double* obs_out, bool keep) {
     dissipate(mps, bd, Dtab);
+    if (tjm_tid() == 0) {
+      int ok = P.sweep_jumps ? 0 : 1;
+      for (int b = 0; b < L && ok; ++b)
+        if (bd[b + 1] > d * bd[b] || bd[b] > d * bd[b + 1]) ok = 0;
+      sh.pick = ok;
+    }
+    tjm_sync();
+    if (!sh.pick) return jump_process_sweeps(mps, bd, step, branch, obs_out);
+    const double nrm2 = envs_right(mps, bd);
+    if (!(nrm2 == nrm2) || nrm2 > 1e300) return -2;
+    const double dp = nrm2 < 1.0 ? 1.0 - nrm2 : 0.0;
+    double eps, r;
+    tjm_draws(P.seed, P.traj_base + (uint32_t)traj_id, step, branch, eps, r);
+    int m = -1;
+    if (eps < dp) {
+      envs_left_rho(mps, bd, true, obs_out);
+      m = pick_jump(r);
+    } else if (obs_out) {
+      envs_left_rho(mps, bd, false, obs_out);
+    }
+    if (m < 0) {                                        // no jump: normalise
+      if (keep) {
+        for (int s = L - 1; s >= 1; --s) lq_move_left(mps, bd, s);
+        finish(mps, bd, nullptr);
+      }
+      return -1;
+    }
+    const int sj = P.jump_site[m];
+    for (int s = L - 1; s > sj; --s) lq_move_left(mps, bd, s);
+    for (int s = 0; s < sj; ++s) qr_move_right(mps, bd, s);
+    apply_jump(mps, bd, m, obs_out);
+    return m;
+  }
+
+  // The jump process with the sweeps in the printed order (entry after D).
+  TJM_DEV int jump_process_sweeps(zd* mps, int* bd, uint32_t step, uint32_t branch, double* obs_out) {
     for (int s = 0; s < L - 1; ++s) qr_move_right(mps, bd, s);
     const long nlast = (long)bd[L - 1] * d * bd[L];
     const double nrm2 = norm2_site(site(mps, P, L - 1), nlast);
@@ -619,54 +767,14 @@ template <typename Tc> struct Tjm {
       if (obs_out) measure(s, obs_out);
       if (s > 0) lq_move_left(mps, bd, s);
     }
-    if (tjm_tid() == 0) {
-      double tot = 0.0;
-      for (int j = 0; j < P.n_jump; ++j) tot += wts[j];
-      int m = -1;
-      if (tot > 1e-300) {
-        const double thr = r * tot;
-        double cum = 0.0;
-        for (int j = 0; j < P.n_jump; ++j) {
-          cum += wts[j];
-          if (cum > thr) { m = j; break; }
-        }
-        if (m < 0)
-          for (int j = P.n_jump - 1; j >= 0; --j)
-            if (wts[j] > 0.0) { m = j; break; }
-      }
-      sh.pick = m;
-    }
-    tjm_sync();
-    const int m = sh.pick;
+    const int m = pick_jump(r);
     if (m < 0) {
       finish(mps, bd, nullptr);
       return -1;
     }
     const int sj = P.jump_site[m];
     for (int s = 0; s < sj; ++s) qr_move_right(mps, bd, s);
-    {
-      zd* M = site(mps, P, sj);
-      const zd* Op = (const zd*)P.jump_op + (long)m * 4;
-      const int chl = bd[sj], chr = bd[sj + 1];
-      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
-        int a = (int)(e / chr), b = (int)(e % chr);
-        zd in0 = M[((long)a * 2 + 0) * chr + b], in1 = M[((long)a * 2 + 1) * chr + b];
-        M[((long)a * 2 + 0) * chr + b] = Op[0] * in0 + Op[1] * in1;
-        M[((long)a * 2 + 1) * chr + b] = Op[2] * in0 + Op[3] * in1;
-      }
-      tjm_sync();
-      const long n = (long)chl * d * chr;
-      const double nn = norm2_site(M, n);
-      scale_site(M, n, 1.0 / sqrt(nn));
-    }
-    count(TJM_ST_JUMPS, 1ull);
-    // normalisation through successive SVDs: jump site -> right end -> site 0
-    for (int s = sj; s < L - 1; ++s) svd_move_right(mps, bd, s);
-    for (int s = L - 1; s >= 1; --s) {
-      if (obs_out) { site_rho(site(mps, P, s), bd[s], bd[s + 1]); measure(s, obs_out); }
-      svd_move_left(mps, bd, s);
-    }
-    finish(mps, bd, obs_out);
+    apply_jump(mps, bd, m, obs_out);
     return m;
   }
 
@@ -724,7 +832,7 @@ template <typename Tc> struct Tjm {
       lq_move_left(mps, bA, s);
     }
     finish(mps, bA, o0);
-    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
+    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr, true);
     if (tjm_tid() == 0) {
       P.jlog[(long)traj * 2 * P.n_steps] = m;
       if (m == -2) P.tflags[traj] = 1;
@@ -738,6 +846,10 @@ template <typename Tc> struct Tjm {
   TJM_DEV void traj_step(int traj, int k) {
     traj_id = traj;
     stats_begin();
+    if (P.tflags[traj]) {            // already non-finite: no further work
+      stats_end(traj);
+      return;
+    }
     zd* mps = (zd*)P.mps + (long)traj * P.mps_cap;
     load_bonds(bA, P.bonds + (long)traj * (L + 1));
     tdvp(mps, bA);
@@ -746,9 +858,9 @@ template <typename Tc> struct Tjm {
     for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
     tjm_sync();
     double* ok = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
-    int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok);
+    int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok, false);
     int mm = -1;
-    if (k < P.n_steps) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr);
+    if (k < P.n_steps && ms != -2) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr, true);
     if (tjm_tid() == 0) {
       int* jl = P.jlog + (long)traj * 2 * P.n_steps;
       jl[2 * k - 1] = ms;

@@ -86,6 +86,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->traj_base = 0;
   o->device = 0;
   o->certify_sweeps = -1;
+  o->sweep_jumps = 1;
 }
 
 extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
@@ -268,6 +269,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = r->record_bonds;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
+  P.sweep_jumps = opt.sweep_jumps ? 1 : 0;
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
   P.seed = seed; P.traj_base = opt.traj_base;
 
@@ -390,7 +392,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   // ---- worker scratch layout ---------------------------------------------
   const long csz = P.mixed ? 8 : 16;
   P.vec_cap = (long)chic * chic * d * d;
-  P.env_cap = (long)Dm * chic * chic;
+  P.env_cap = (long)std::max(Dm, 2) * chic * chic;   // also holds an FP64 chi x chi transfer environment
   P.t_cap = (long)Dm * P.vec_cap;
   P.mat_cap = (long)d * chic * d * chic;
   long o = 0;
@@ -400,7 +402,6 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   P.off_w = o; o = align256(o + P.vec_cap * 16);
   P.off_v = o; o = align256(o + P.vec_cap * 16);
   P.off_T1 = o; o = align256(o + P.t_cap * csz);
-  P.off_T2 = o; o = align256(o + P.t_cap * csz);
   P.off_X = o; o = align256(o + P.mat_cap * 16);
   P.off_Y = o; o = align256(o + P.mat_cap * 16);
   P.off_Z = o; o = align256(o + P.mat_cap * 16);
@@ -521,6 +522,7 @@ static void collect_stats(tjm_model* m, Run* r) {
     s.krylov_iters += q[TJM_ST_KRYLOV]; s.expm_calls += q[TJM_ST_EXPM];
     s.one_site += q[TJM_ST_ONE_SITE]; s.two_site += q[TJM_ST_TWO_SITE];
     s.factorizations += q[TJM_ST_FACT]; s.jumps += q[TJM_ST_JUMPS];
+    s.cmac_env += q[TJM_ST_CMAC_FP64];
   }
   std::vector<int> fl(r->n_traj);
   if (hipMemcpy(fl.data(), r->d_flags, fl.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
@@ -747,5 +749,32 @@ extern "C" tjm_status tjm_selftest_philox(int count, const uint32_t* ctr, uint32
   STCHK(tjm_launch_st_philox(count, dc, k0, k1, dout));
   STCHK(hipDeviceSynchronize());
   STCHK(hipMemcpy(out, dout, 16L * count, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_selftest_copy(long n_bytes, int reps, double* avg_ms) {
+  if (n_bytes < 16 || n_bytes % 16 != 0 || n_bytes > (16L << 30) || reps < 1 || reps > 1000 || !avg_ms)
+    return fail(nullptr, TJM_E_INVAL, "copy sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
+  DevScope ds;
+  char *src, *dst;
+  STCHK(ds.put((const char*)nullptr, n_bytes, &src));
+  STCHK(ds.put((const char*)nullptr, n_bytes, &dst));
+  hipDeviceProp_t prop;
+  STCHK(hipGetDeviceProperties(&prop, 0));
+  hipEvent_t e0, e1;
+  STCHK(hipEventCreate(&e0));
+  STCHK(hipEventCreate(&e1));
+  STCHK(hipDeviceSynchronize());
+  STCHK(hipEventRecord(e0, 0));
+  for (int i = 0; i < reps; ++i) STCHK(tjm_launch_st_copy(src, dst, n_bytes / 16, 8 * prop.multiProcessorCount, 0));
+  STCHK(hipEventRecord(e1, 0));
+  STCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  STCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
   return TJM_OK;
 }

@@ -25,3 +25,4 @@ hipError_t tjm_launch_st_expm(int n, const double* H, double* v, double t, int k
                               double* Q, double* w, int* iters);
 hipError_t tjm_launch_st_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
                                 uint32_t* out);
+hipError_t tjm_launch_st_copy(const void* src, void* dst, long n16, int blocks, hipStream_t s);

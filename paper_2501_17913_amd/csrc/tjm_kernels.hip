@@ -154,6 +154,18 @@ __global__ void st_philox_kernel(int count, const uint32_t* ctr, uint32_t k0, ui
   for (int j = 0; j < 4; ++j) out[4 * i + j] = c[j];
 }
 
+// Plain streaming copy (calibration of the HBM traffic counters): every
+// byte of src is read once and every byte of dst written once.
+__global__ void st_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t tjm_launch_st_copy(const void* src, void* dst, long n16, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(st_copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
 hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_batches,
                                const double* A, int lda, long bsA, int transA, int conjA,
                                const double* B, int ldb, long bsB, int transB, int conjB,

@@ -22,6 +22,7 @@ struct TjmParams {
   int record_bonds;
   int mixed;                         // 1: complex-FP32 contractions
   int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
+  int sweep_jumps;                   // 1: jump process with the sweeps in the printed order
   double dt, krylov_tol, svd_discard, deg_tol;
   uint64_t seed;
   uint32_t traj_base;                // global id of trajectory 0 of this run
@@ -67,7 +68,7 @@ struct TjmParams {
   long off_smps;                     // mps_cap complex doubles
   long off_Q, vec_cap;               // krylov_max vectors of vec_cap complex doubles
   long off_w, off_v;                 // vec_cap complex doubles each
-  long off_T1, off_T2, t_cap;        // t_cap complex (T_c) each
+  long off_T1, t_cap;                // stage buffer, t_cap complex (T_c)
   long off_X, off_Y, off_Z, off_C, mat_cap;   // mat_cap complex doubles each
   long off_wts;                      // n_jump doubles
 
@@ -87,10 +88,11 @@ enum {
   // device-clock ticks (100 MHz) spent by the trajectory's workgroup in:
   TJM_ST_T_TOTAL = 8,     //   the whole step function
   TJM_ST_T_CONTRACT = 9,  //   effective-Hamiltonian and environment contractions
-  TJM_ST_T_MIX = 10,      //   ... of which the MPO mixing stage
+  TJM_ST_T_ENV = 10,      //   transfer-matrix environment sweeps of the jump process
   TJM_ST_T_SVD = 11,      //   SVD factorisations
   TJM_ST_T_QR = 12,       //   QR / LQ factorisations
   TJM_ST_T_EXPM = 13,     //   Lanczos exponentials (including their contractions)
   TJM_ST_T_ABSORB = 14,   //   bond-matrix absorption and two-site products
+  TJM_ST_CMAC_FP64 = 15,  // complex multiply-adds of those environment sweeps (FP64)
   TJM_NSTAT = 16
 };

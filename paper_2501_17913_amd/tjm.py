@@ -23,7 +23,7 @@ EXPORTED = [
     "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_run", "tjm_run_traces",
     "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_get_stats", "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
-    "tjm_selftest_expm", "tjm_selftest_philox",
+    "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
 ]
 
 
@@ -31,7 +31,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("chi_cap", C.c_int), ("svd_discard", C.c_double),
                 ("krylov_max", C.c_int), ("krylov_tol", C.c_double), ("deg_tol", C.c_double),
                 ("workers", C.c_int), ("record_bonds", C.c_int), ("traj_base", C.c_uint32),
-                ("device", C.c_int), ("certify_sweeps", C.c_int)]
+                ("device", C.c_int), ("certify_sweeps", C.c_int), ("sweep_jumps", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -42,9 +42,10 @@ class Stats(C.Structure):
                 ("krylov_iters", C.c_ulonglong), ("expm_calls", C.c_ulonglong),
                 ("one_site", C.c_ulonglong), ("two_site", C.c_ulonglong),
                 ("factorizations", C.c_ulonglong), ("jumps", C.c_ulonglong),
-                ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8), ("failed_traj", C.c_int)]
+                ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8), ("failed_traj", C.c_int),
+                ("cmac_env", C.c_ulonglong)]
 
-    PHASES = ("total", "contract", "mix", "svd", "qr", "expm", "absorb")
+    PHASES = ("total", "contract", "env", "svd", "qr", "expm", "absorb")
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_s"}
@@ -95,6 +96,8 @@ lib.tjm_selftest_expm.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, C.c_do
 lib.tjm_selftest_expm.restype = C.c_int
 lib.tjm_selftest_philox.argtypes = [C.c_int, _up, C.c_uint32, C.c_uint32, _up]
 lib.tjm_selftest_philox.restype = C.c_int
+lib.tjm_selftest_copy.argtypes = [C.c_long, C.c_int, _dp]
+lib.tjm_selftest_copy.restype = C.c_int
 
 
 class TjmError(RuntimeError):
@@ -292,3 +295,10 @@ def selftest_philox(counters, k0, k1):
     out = np.zeros_like(c)
     _st(lib.tjm_selftest_philox(c.shape[0], c.ctypes.data_as(_up), k0, k1, out.ctypes.data_as(_up)))
     return out
+
+
+def selftest_copy(n_bytes, reps=5):
+    """Mean duration (ms) of a plain streaming copy of n_bytes on the device."""
+    ms = C.c_double(0.0)
+    _st(lib.tjm_selftest_copy(int(n_bytes), int(reps), C.byref(ms)))
+    return ms.value
