@@ -68,43 +68,34 @@ def traffic_per_launch(workload, precision, W, K):
 
 
 def _oracle_worker(args):
-    L, chi, steps, traj, budget = args
+    L, chi, steps, traj = args
     from oracle import model as om, mps_tjm
     Ws = om.xxx_mpo(L, 1.0, 0.5)
     jumps = om.relax_dephase_jumps(L, 0.1, 0.1)
     obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
     sv = om.product_site_vectors(L, [l % 2 for l in range(L)])
-    start = time.time()
-    best = (0, 1.0)
-    n = 1
-    while n <= steps:                    # runs of 1, 2, 4, ... steps until the budget is used
-        t0 = time.time()
-        mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, n, obs, SEED, traj,
-                               mps_tjm.Options(chi_max=chi))
-        el = time.time() - t0
-        best = (n, el)
-        if time.time() - start + 2.5 * el > budget:
-            break
-        n *= 2
-    return best
+    t0 = time.time()
+    mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, steps, obs, SEED, traj,
+                           mps_tjm.Options(chi_max=chi))
+    return steps, time.time() - t0
 
 
-def cpu_baseline(L, chi, max_steps, budget=20.0):
+def cpu_baseline(L, chi, steps=5):
     """The oracle as it stands on the host cores, one trajectory per process
-    (different trajectory ids).  Each process runs its trajectory for 1, 2,
-    4, ... steps while the time budget lasts; its rate is the longest
-    completed run's steps over that run's time."""
+    (trajectory ids 0..cores-1), each run for the first `steps` steps of the
+    job; rate = sum over processes of steps / seconds."""
     cores = max(1, min(os.cpu_count() or 1, 16))
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[v] = "1"                     # one core per trajectory, as in the paper's runs
+    res = []
     with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(L, chi, max_steps, t, budget) for t in range(cores)])
+        for r in pool.imap_unordered(_oracle_worker, [(L, chi, steps, t) for t in range(cores)]):
+            res.append(r)
+            print("  cpu baseline: %d of %d trajectories done" % (len(res), cores), file=sys.stderr, flush=True)
     rate = sum(n / el for n, el in res)
-    steps = min(n for n, _ in res)
     return {"value": rate, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 NumPy MPS-TJM of the same chain, %d trajectories (one per core), "
-                      "steps 1..%d from the Neel state (the cheaper early steps), ~%.0fs budget"
-                      % (cores, steps, budget)}
+            "sample": "FP64 NumPy MPS-TJM of the same chain and seed, trajectory ids 0..%d (one per core), "
+                      "steps 1..%d from the Neel state, each run from F_0" % (cores - 1, steps)}
 
 
 def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
@@ -121,11 +112,15 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
     m.set_initial_product(models.neel(L))
     opt = tjm.default_options(precision=prec, workers=workers)
     m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
-    if warmup:
-        m.advance(warmup)
+    for k in range(warmup):
+        m.advance(1)
+        print("  warmup step %d of %d done" % (k + 1, warmup), file=sys.stderr, flush=True)
     s0 = m.stats()
     t0 = time.perf_counter()
-    m.advance(K)                      # synchronous: returns after the last kernel
+    for k in range(K):                # each advance returns after its launch has finished
+        m.advance(1)
+        print("  %s step %d of %d done at %.1fs" % ("mixed" if prec == tjm.PREC_MIXED else "fp64", warmup + k + 1,
+                                                    warmup + K, time.perf_counter() - t0), file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     s1 = m.stats()
     m.close()                         # the rest of the job is not needed for timing
@@ -158,7 +153,7 @@ def main():
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-steps", type=int, default=5, help="steps per trajectory of the CPU oracle sample")
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel used to calibrate the traffic counters")
@@ -219,7 +214,7 @@ def main():
                             "achieved_tflops": f["achieved_tflops"], "peak": PEAK_TFLOPS["fp64"],
                             "mixed_speedup": head["value"] / f["value"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(L, chi, n, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(L, chi, min(args.cpu_steps, n))
     print(json.dumps(out), flush=True)
 
 

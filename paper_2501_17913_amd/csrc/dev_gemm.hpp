@@ -42,61 +42,73 @@ template <> struct Mfma<float> {
 // keep the fragment reads free of bank conflicts.  A chunk is first loaded
 // into registers (so the loads of chunk c+1 are in flight while chunk c runs
 // on the matrix cores), then stored to LDS.
-constexpr int GEMM_BM = 64, GEMM_BN = 32, GEMM_BK = 16;
+// The k-chunk is 32 complex for f32 and 16 for f64 operands, so that both
+// fill the same staging area (and a chunk keeps the matrix cores busy long
+// enough to hide the next chunk's loads).
+constexpr int GEMM_BM = 64, GEMM_BN = 32;
+template <typename T> struct GemmK { static constexpr int BK = 16; };
+template <> struct GemmK<float> { static constexpr int BK = 32; };
 constexpr int GEMM_APAD = GEMM_BM + 2, GEMM_BPAD = GEMM_BN + 2;
-constexpr int GEMM_LDS_BYTES = (GEMM_BK * GEMM_APAD + GEMM_BK * GEMM_BPAD) * 16;
-constexpr int GEMM_AE = GEMM_BM * GEMM_BK / TJM_NT;   // A elements per thread
-constexpr int GEMM_BE = GEMM_BK * GEMM_BN / TJM_NT;   // B elements per thread
-static_assert(GEMM_AE * TJM_NT == GEMM_BM * GEMM_BK && GEMM_BE * TJM_NT == GEMM_BK * GEMM_BN,
-              "the workgroup must tile the staging panels exactly");
+constexpr int GEMM_LDS_BYTES = (16 * GEMM_APAD + 16 * GEMM_BPAD) * 16;
+static_assert((GemmK<float>::BK * GEMM_APAD + GemmK<float>::BK * GEMM_BPAD) * 8 <= GEMM_LDS_BYTES,
+              "f32 staging fits the f64-sized area");
+template <typename T> struct GemmE {
+  static constexpr int BK = GemmK<T>::BK;
+  static constexpr int AE = GEMM_BM * BK / TJM_NT;   // A elements per thread
+  static constexpr int BE = BK * GEMM_BN / TJM_NT;   // B elements per thread
+  static_assert(AE * TJM_NT == GEMM_BM * BK && BE * TJM_NT == BK * GEMM_BN,
+                "the workgroup must tile the staging panels exactly");
+};
 
 // panel coordinates of the u-th element a thread stages
-TJM_DEV void a_coord(bool trans, int u, int& i, int& k) {
+template <int BK> TJM_DEV void a_coord(bool trans, int u, int& i, int& k) {
   const int e = tjm_tid() + u * TJM_NT;
   if (trans) { i = e % GEMM_BM; k = e / GEMM_BM; }
-  else { k = e % GEMM_BK; i = e / GEMM_BK; }
+  else { k = e % BK; i = e / BK; }
 }
-TJM_DEV void b_coord(bool trans, int u, int& k, int& j) {
+template <int BK> TJM_DEV void b_coord(bool trans, int u, int& k, int& j) {
   const int e = tjm_tid() + u * TJM_NT;
-  if (trans) { k = e % GEMM_BK; j = e / GEMM_BK; }
+  if (trans) { k = e % BK; j = e / BK; }
   else { j = e % GEMM_BN; k = e / GEMM_BN; }
 }
 
 template <typename T, class OA, class OB>
 TJM_DEV void gemm_load(const OA& A, const OB& B, int b, int i0, int j0, int k0, int M, int N, int K,
                        cplx<T>* ra, cplx<T>* rb) {
-  int ia[GEMM_AE], ka[GEMM_AE], kb[GEMM_BE], jb[GEMM_BE];
-  bool oa[GEMM_AE], ob[GEMM_BE];
+  constexpr int BK = GemmE<T>::BK, AE = GemmE<T>::AE, BE = GemmE<T>::BE;
+  int ia[AE], ka[AE], kb[BE], jb[BE];
+  bool oa[AE], ob[BE];
 #pragma unroll
-  for (int u = 0; u < GEMM_AE; ++u) {
+  for (int u = 0; u < AE; ++u) {
     int i, k;
-    a_coord(A.trans, u, i, k);
+    a_coord<BK>(A.trans, u, i, k);
     ia[u] = i0 + i; ka[u] = k0 + k;
     oa[u] = ia[u] < M && ka[u] < K;
   }
 #pragma unroll
-  for (int u = 0; u < GEMM_BE; ++u) {
+  for (int u = 0; u < BE; ++u) {
     int k, j;
-    b_coord(B.trans, u, k, j);
+    b_coord<BK>(B.trans, u, k, j);
     kb[u] = k0 + k; jb[u] = j0 + j;
     ob[u] = kb[u] < K && jb[u] < N;
   }
-  A.template gather<T, GEMM_AE>(b, ia, ka, oa, ra);
-  B.template gather<T, GEMM_BE>(b, kb, jb, ob, rb);
+  A.template gather<T, AE>(b, ia, ka, oa, ra);
+  B.template gather<T, BE>(b, kb, jb, ob, rb);
 }
 
 template <typename T>
 TJM_DEV void gemm_store(bool ta, bool tb, const cplx<T>* ra, const cplx<T>* rb, cplx<T>* As, cplx<T>* Bs) {
+  constexpr int BK = GemmE<T>::BK, AE = GemmE<T>::AE, BE = GemmE<T>::BE;
 #pragma unroll
-  for (int u = 0; u < GEMM_AE; ++u) {
+  for (int u = 0; u < AE; ++u) {
     int i, k;
-    a_coord(ta, u, i, k);
+    a_coord<BK>(ta, u, i, k);
     As[k * GEMM_APAD + i] = ra[u];
   }
 #pragma unroll
-  for (int u = 0; u < GEMM_BE; ++u) {
+  for (int u = 0; u < BE; ++u) {
     int k, j;
-    b_coord(tb, u, k, j);
+    b_coord<BK>(tb, u, k, j);
     Bs[k * GEMM_BPAD + j] = rb[u];
   }
 }
@@ -193,8 +205,9 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
     wave_cgemm<T>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate);
     return;
   }
+  constexpr int BK = GemmE<T>::BK;
   cplx<T>* As = (cplx<T>*)lds;
-  cplx<T>* Bs = As + GEMM_BK * GEMM_APAD;
+  cplx<T>* Bs = As + BK * GEMM_APAD;
   const int lane = tjm_lane();
   const int r16 = lane & 15;
   const int q = lane >> 4;           // k sub-index 0..3 inside one instruction
@@ -206,7 +219,7 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
   const int nti = (M + GEMM_BM - 1) / GEMM_BM, ntj = (N + GEMM_BN - 1) / GEMM_BN;
   const int nout = sum_batches ? 1 : nb;
   const int ntiles = nout * nti * ntj;
-  const int nkc = (K + GEMM_BK - 1) / GEMM_BK;
+  const int nkc = (K + BK - 1) / BK;
   for (int it = 0; it < ntiles; ++it) {
     const int ob = it / (nti * ntj);
     const int rem = it - ob * (nti * ntj);
@@ -217,7 +230,7 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
     acc[1][0] = Mfma<T>::zero(); acc[1][1] = Mfma<T>::zero();
     const int b_lo = sum_batches ? 0 : ob;
     const int nchunk = (sum_batches ? nb : 1) * nkc;
-    cplx<T> ra[GEMM_AE], rb[GEMM_BE];
+    cplx<T> ra[GemmE<T>::AE], rb[GemmE<T>::BE];
     gemm_load<T>(A, B, b_lo, i0, j0, 0, M, N, K, ra, rb);
     for (int c = 0; c < nchunk; ++c) {
       tjm_sync();                                  // LDS free again
@@ -225,10 +238,10 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
       tjm_sync();
       if (c + 1 < nchunk) {                        // next chunk in flight
         const int cn = c + 1;
-        gemm_load<T>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * GEMM_BK, M, N, K, ra, rb);
+        gemm_load<T>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * BK, M, N, K, ra, rb);
       }
 #pragma unroll 2
-      for (int kk = 0; kk < GEMM_BK; kk += 2) {    // zero-padded past K
+      for (int kk = 0; kk < BK; kk += 2) {         // zero-padded past K
         const int kc = kk + kq;
         T av[2], bv[2];
 #pragma unroll
