@@ -13,59 +13,88 @@
 #define TJM_KMAX 32                 // largest Krylov dimension supported
 
 // --------------------------------------------------------------------------
-// Householder QR.  X (m x n, ld n) is destroyed.  On return Q (m x k, ld k)
-// and R (k x n, ld n) hold the thin factors, k = min(m, n), with
-// diag(R) real >= 0.  hv (>= k doubles of LDS-or-global scratch) is used for
-// the reflector scales.
+// Householder QR.  X (m x n, ld n, m <= 128) is destroyed.  On return Q
+// (m x k, ld k) and R (k x n, ld n) hold the thin factors, k = min(m, n),
+// with diag(R) real >= 0.
+//
+// Reflector of column j (x = rows j.. of the current column, x0 its first
+// entry): beta = -(x0/|x0|) ||x||, v = x with v0 = x0 - beta,
+// H_j = I - (2/||v||^2) v v^H; a zero column gives H_j = I.  Each step
+// copies v to LDS once; groups of QR_TPC threads own one trailing column,
+// each thread a strided set of its rows held in registers between the dot
+// product and the update; the group that updates column j+1 also returns
+// its norm below the diagonal for the next step.
 // --------------------------------------------------------------------------
+constexpr int QR_MROWS = 128;
+constexpr int QR_TPC = TJM_NT >= 16 ? 16 : 1;                   // threads per column
+constexpr int QR_RPT = (QR_MROWS + QR_TPC - 1) / QR_TPC;        // rows per thread
+
 struct QrLds {
-  double vnorm2[128];
-  double bre[128], bim[128];      // diagonal of R before the gauge fix
+  double vnorm2[QR_MROWS];
+  double bre[QR_MROWS], bim[QR_MROWS];  // diagonal of R before the gauge fix
+  zd v[QR_MROWS];                       // reflector of the current step
+  double a2next;                        // ||column j+1, rows j+1..||^2
 };
 
 TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) {
   const int k = m < n ? m : n;
   const int tid = tjm_tid();
-  const int TPC = TJM_NT >= 16 ? 16 : 1;        // threads per column
-  const int ngrp = TJM_NT / TPC;
-  const int g = tid / TPC, gl = tid % TPC;
+  const int ngrp = TJM_NT / QR_TPC;
+  const int g = tid / QR_TPC, gl = tid % QR_TPC;
+  double a2 = 0.0;
+  for (int i = tid; i < m; i += TJM_NT) a2 += abs2(X[(long)i * n]);
+  a2 = blk_sum(a2, S);
   for (int j = 0; j < k; ++j) {
-    double a2 = 0.0;
-    for (int i = j + tid; i < m; i += TJM_NT) a2 += abs2(X[(long)i * n + j]);
-    a2 = blk_sum(a2, S);
-    if (tid == 0) {
-      zd x0 = X[(long)j * n + j];
-      double ax0 = sqrt(abs2(x0));
-      double al = sqrt(a2);
-      if (al == 0.0) {
-        H.vnorm2[j] = 0.0; H.bre[j] = 0.0; H.bim[j] = 0.0;
-      } else {
-        zd ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
-        zd beta = cmk(-ph.re * al, -ph.im * al);
-        X[(long)j * n + j] = x0 - beta;           // v0 = x0 + ph * alpha
-        H.vnorm2[j] = 2.0 * al * (al + ax0);
-        H.bre[j] = beta.re; H.bim[j] = beta.im;
-      }
+    const int mr = m - j;
+    if (j > 0) a2 = H.a2next;
+    const zd x0 = X[(long)j * n + j];
+    const double ax0 = sqrt(abs2(x0));
+    const double al = sqrt(a2);
+    zd beta = cmk(0.0, 0.0), v0 = x0;
+    double vn = 0.0;
+    if (al > 0.0) {
+      const zd ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+      beta = cmk(-ph.re * al, -ph.im * al);
+      v0 = x0 - beta;                             // v0 = x0 + ph * alpha
+      vn = 2.0 * al * (al + ax0);
     }
+    for (int i = tid; i < mr; i += TJM_NT) H.v[i] = i == 0 ? v0 : X[(long)(j + i) * n + j];
+    if (tid == 0) { H.vnorm2[j] = vn; H.bre[j] = beta.re; H.bim[j] = beta.im; }
     tjm_sync();
-    const double vn = H.vnorm2[j];
-    if (vn > 0.0) {
-      const double f = 2.0 / vn;
-      for (int c = j + 1 + g; c < n; c += ngrp) {
-        double sr = 0.0, si = 0.0;
-        for (int i = j + gl; i < m; i += TPC) {
-          zd v = X[(long)i * n + j], x = X[(long)i * n + c];
-          zd p = cdotc(v, x);
-          sr += p.re; si += p.im;
-        }
-        sr = grp_sum(sr, TPC); si = grp_sum(si, TPC);
-        zd s = cmk(f * sr, f * si);
-        for (int i = j + gl; i < m; i += TPC) {
-          zd v = X[(long)i * n + j];
-          X[(long)i * n + c] = X[(long)i * n + c] - s * v;
+    const double f = vn > 0.0 ? 2.0 / vn : 0.0;
+    for (int c = j + 1 + g; c < n; c += ngrp) {
+      zd x[QR_RPT];
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int t = 0; t < QR_RPT; ++t) {
+        const int i = gl + QR_TPC * t;
+        x[t] = i < mr ? X[(long)(j + i) * n + c] : cmk(0.0, 0.0);
+        const zd p = cdotc(i < mr ? H.v[i] : cmk(0.0, 0.0), x[t]);
+        sr += p.re; si += p.im;
+      }
+      if (vn > 0.0) {
+        const zd sc = cmk(f * grp_sum(sr, QR_TPC), f * grp_sum(si, QR_TPC));
+#pragma unroll
+        for (int t = 0; t < QR_RPT; ++t) {
+          const int i = gl + QR_TPC * t;
+          if (i < mr) {
+            x[t] = x[t] - sc * H.v[i];
+            X[(long)(j + i) * n + c] = x[t];
+          }
         }
       }
+      if (c == j + 1) {                           // norm of the next column below its diagonal
+        double q = 0.0;
+#pragma unroll
+        for (int t = 0; t < QR_RPT; ++t) {
+          const int i = gl + QR_TPC * t;
+          if (i >= 1 && i < mr) q += abs2(x[t]);
+        }
+        q = grp_sum(q, QR_TPC);
+        if (gl == 0) H.a2next = q;
+      }
     }
+    if (tid == 0) X[(long)j * n + j] = v0;        // reflector head, for Q
     tjm_sync();
   }
   // R (upper triangle of X, diagonal beta), then the gauge fix
@@ -84,18 +113,26 @@ TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) 
   tjm_sync();
   for (int j = k - 1; j >= 0; --j) {
     const double vn = H.vnorm2[j];
-    if (vn > 0.0) {
-      const double f = 2.0 / vn;
-      for (int c = j + g; c < k; c += ngrp) {
-        double sr = 0.0, si = 0.0;
-        for (int i = j + gl; i < m; i += TPC) {
-          zd p = cdotc(X[(long)i * n + j], Q[(long)i * k + c]);
-          sr += p.re; si += p.im;
-        }
-        sr = grp_sum(sr, TPC); si = grp_sum(si, TPC);
-        zd s = cmk(f * sr, f * si);
-        for (int i = j + gl; i < m; i += TPC)
-          Q[(long)i * k + c] = Q[(long)i * k + c] - s * X[(long)i * n + j];
+    if (!(vn > 0.0)) continue;                    // identity reflector
+    const int mr = m - j;
+    for (int i = tid; i < mr; i += TJM_NT) H.v[i] = X[(long)(j + i) * n + j];
+    tjm_sync();
+    const double f = 2.0 / vn;
+    for (int c = j + g; c < k; c += ngrp) {
+      zd x[QR_RPT];
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int t = 0; t < QR_RPT; ++t) {
+        const int i = gl + QR_TPC * t;
+        x[t] = i < mr ? Q[(long)(j + i) * k + c] : cmk(0.0, 0.0);
+        const zd p = cdotc(i < mr ? H.v[i] : cmk(0.0, 0.0), x[t]);
+        sr += p.re; si += p.im;
+      }
+      const zd sc = cmk(f * grp_sum(sr, QR_TPC), f * grp_sum(si, QR_TPC));
+#pragma unroll
+      for (int t = 0; t < QR_RPT; ++t) {
+        const int i = gl + QR_TPC * t;
+        if (i < mr) Q[(long)(j + i) * k + c] = x[t] - sc * H.v[i];
       }
     }
     tjm_sync();
@@ -221,7 +258,7 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
             wa[r] = cs * x - sn * y;
             wb[r] = sn * x + cs * y;
           }
-          if (gl == 0) SL.rotated = 1;
+          if (gl == 0) atomicOr(&SL.rotated, 1);
         }
       }
       tjm_sync();
