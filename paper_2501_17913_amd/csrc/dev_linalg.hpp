@@ -435,35 +435,37 @@ TJM_DEV int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol,
   for (int j = 0; j < m_max; ++j) {
     const zd* qj = Q + (long)j * n;
     op.apply(qj, w);                                   // w = H q_j
-    double al = 0.0;
-    for (int e = tid; e < n; e += TJM_NT) al += cdotc(qj[e], w[e]).re;
-    al = blk_sum(al, S);
-    const double bprev = j > 0 ? Lz.beta[j - 1] : 0.0;
-    const zd* qp = j > 0 ? Q + (long)(j - 1) * n : Q;
-    for (int e = tid; e < n; e += TJM_NT) {
-      zd x = w[e] - al * qj[e];
-      if (j > 0) x = x - bprev * qp[e];
-      w[e] = x;
-    }
-    // full re-orthogonalisation: w -= Q (Q^H w) against q_0..q_j
+    // one classical Gram-Schmidt pass against q_0..q_j (alpha_j = Re h_j,
+    // the three-term part included): h = Q^H w with w read once per block
+    // of four basis vectors
     const int nq = j + 1;
-    for (int i = 0; i < nq; ++i) {
-      const zd* qi = Q + (long)i * n;
-      double hr = 0.0, hi = 0.0;
+    for (int i0 = 0; i0 < nq; i0 += 4) {
+      double hr[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
       for (int e = tid; e < n; e += TJM_NT) {
-        zd p = cdotc(qi[e], w[e]);
-        hr += p.re; hi += p.im;
+        const zd x = w[e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (i0 + u >= nq) continue;
+          const zd p = cdotc(Q[(long)(i0 + u) * n + e], x);
+          hr[u] += p.re; hi[u] += p.im;
+        }
       }
-      for (int s = TJM_WAVE / 2; s > 0; s >>= 1) { hr += tjm_shfl_xor(hr, s); hi += tjm_shfl_xor(hi, s); }
-      if (tjm_lane() == 0) { Lz.red[tjm_wave()][2 * i] = hr; Lz.red[tjm_wave()][2 * i + 1] = hi; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        for (int s = TJM_WAVE / 2; s > 0; s >>= 1) { hr[u] += tjm_shfl_xor(hr[u], s); hi[u] += tjm_shfl_xor(hi[u], s); }
+        if (tjm_lane() == 0 && i0 + u < nq) {
+          Lz.red[tjm_wave()][2 * (i0 + u)] = hr[u];
+          Lz.red[tjm_wave()][2 * (i0 + u) + 1] = hi[u];
+        }
+      }
     }
     tjm_sync();
     for (int i = tid; i < nq; i += TJM_NT) {
       double hr = 0.0, hi = 0.0;
       for (int wv = 0; wv < TJM_NWAVE; ++wv) { hr += Lz.red[wv][2 * i]; hi += Lz.red[wv][2 * i + 1]; }
       Lz.hre[i] = hr; Lz.him[i] = hi;
+      if (i == j) Lz.alpha[j] = hr;
     }
-    if (tid == 0) Lz.alpha[j] = al;
     tjm_sync();
     double bn = 0.0;
     for (int e = tid; e < n; e += TJM_NT) {
