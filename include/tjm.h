@@ -150,6 +150,20 @@ tjm_status tjm_create(tjm_model **out, int L, int d, const int *mpo_bond, const 
 tjm_status tjm_set_initial_product(tjm_model *m, const double *site_vec);
 
 /*
+ * Sets Psi(0) to a general MPS (Sec. "Algorithm / Initialization": the
+ * initial state is given as an MPS):
+ *   bond     L+1 bond dimensions, bond[0] = bond[L] = 1, 1 <= bond[l] <= 64
+ *   tensors  the site tensors M_l[s][a][b] (s < d, a < bond[l], b < bond[l+1],
+ *            the paper's layout), concatenated over l, interleaved complex
+ * Any gauge and any nonzero norm: each trajectory starts from the state
+ * brought to right-canonical form by an LQ sweep from the right end and
+ * normalised.  A run rejects (TJM_E_INVAL) an MPS with a bond above
+ * min(chi_cap, d^l, d^(L-l)).  Errors: TJM_E_INVAL (NULL, bonds, non-finite
+ * entries).  The library copies the input.
+ */
+tjm_status tjm_set_initial_mps(tjm_model *m, const int *bond, const double *tensors);
+
+/*
  * One whole run (Sec. "Algorithm"): N = n_traj trajectories from t = 0 to
  * T = n dt (n = T/dt must be an integer within 1e-9), chi_max the bond
  * dimension at which dynamic TDVP switches to 1TDVP, and single-site

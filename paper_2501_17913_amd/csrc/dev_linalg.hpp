@@ -192,6 +192,8 @@ TJM_DEV int trunc_rank(F s, int n, double discard, int cap, double deg_tol) {
 // (m x n), with p, nc the row and column counts of the rotated matrix;
 // nc <= 128.
 // --------------------------------------------------------------------------
+constexpr int SVD_LDS_BYTES = 64 * 64 * 16;   // a working matrix of up to 4096 complex doubles
+
 struct SvdLds {
   double s[128];
   int order[128];
@@ -206,6 +208,9 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   const bool tr = absorb_left;           // rotate the columns of G^H (-> V)
   const int p = tr ? n : m;              // rows of the working matrix
   const int nc = tr ? m : n;             // columns of the working matrix
+  // the working matrix is rotated in LDS (glds, SVD_LDS_BYTES) when it fits,
+  // else in the global array Wc; glds is free until the final product
+  if ((long)p * nc * 16 <= SVD_LDS_BYTES) Wc = (zd*)glds;
   double f2 = 0.0;
   for (int e = tid; e < p * nc; e += TJM_NT) {
     int c = e / p, r = e % p;            // Wc[c][r] = Gw[r][c]

@@ -22,8 +22,10 @@
 #include <dev_linalg.hpp>
 #include "tjm_params.h"
 
+constexpr int LDS_WORK_BYTES = GEMM_LDS_BYTES > SVD_LDS_BYTES ? GEMM_LDS_BYTES : SVD_LDS_BYTES;
+
 struct Lds {
-  alignas(16) char gemm[GEMM_LDS_BYTES];
+  alignas(16) char gemm[LDS_WORK_BYTES];   // GEMM staging, or the SVD working matrix
   BlkScratch S;
   QrLds qr;
   SvdLds sv;
@@ -819,19 +821,41 @@ template <typename Tc> struct Tjm {
     traj_id = traj;
     stats_begin();
     zd* mps = (zd*)P.mps + (long)traj * P.mps_cap;
-    for (int b = tjm_tid(); b <= L; b += TJM_NT) bA[b] = 1;
-    for (long e = tjm_tid(); e < (long)L * d; e += TJM_NT) {
-      int s = (int)(e / d), q = (int)(e % d);
-      site(mps, P, s)[q] = ((const zd*)P.init_sites)[e];
-    }
-    tjm_sync();
     double* o0 = P.obs + (long)traj * (P.n_steps + 1) * P.n_obs;
-    for (int s = L - 1; s >= 1; --s) {
-      site_rho(site(mps, P, s), bA[s], bA[s + 1]);
-      measure(s, o0);
-      lq_move_left(mps, bA, s);
+    if (P.init_mps) {
+      // a general MPS: right-canonical from the right end and normalised
+      // (centre at site 0); the t = 0 observables come from a copy whose
+      // centre is swept back to the right
+      for (int b = tjm_tid(); b <= L; b += TJM_NT) bA[b] = P.init_bonds[b];
+      tjm_sync();
+      for (int s = 0; s < L; ++s)
+        copy(site(mps, P, s), site((zd*)P.init_tensors, P, s), (long)bA[s] * d * bA[s + 1]);
+      tjm_sync();
+      for (int s = L - 1; s >= 1; --s) lq_move_left(mps, bA, s);
+      finish(mps, bA, nullptr);
+      for (int s = 0; s < L; ++s) copy(site(smps, P, s), site(mps, P, s), (long)bA[s] * d * bA[s + 1]);
+      for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
+      tjm_sync();
+      for (int s = 0; s < L; ++s) {
+        site_rho(site(smps, P, s), bB[s], bB[s + 1]);
+        measure(s, o0);
+        if (s + 1 < L) qr_move_right(smps, bB, s);
+      }
+    } else {
+      // a product state: bonds 1, measured while its centre is swept left
+      for (int b = tjm_tid(); b <= L; b += TJM_NT) bA[b] = 1;
+      for (long e = tjm_tid(); e < (long)L * d; e += TJM_NT) {
+        int s = (int)(e / d), q = (int)(e % d);
+        site(mps, P, s)[q] = ((const zd*)P.init_sites)[e];
+      }
+      tjm_sync();
+      for (int s = L - 1; s >= 1; --s) {
+        site_rho(site(mps, P, s), bA[s], bA[s + 1]);
+        measure(s, o0);
+        lq_move_left(mps, bA, s);
+      }
+      finish(mps, bA, o0);
     }
-    finish(mps, bA, o0);
     int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr, true);
     if (tjm_tid() == 0) {
       P.jlog[(long)traj * 2 * P.n_steps] = m;

@@ -48,6 +48,8 @@ struct tjm_model {
   std::vector<cd> jop;                // [n_jump][d][d]
   std::vector<double> jrate;
   std::vector<cd> init;               // [L][d]
+  std::vector<int> init_bond;         // non-empty: Psi(0) is the MPS init_mps
+  std::vector<cd> init_mps;           // M_l[s][a][b] concatenated
   std::string err;
   Run* run = nullptr;
   tjm_stats last{};
@@ -151,6 +153,23 @@ extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_b
   return TJM_OK;
 }
 
+extern "C" tjm_status tjm_set_initial_mps(tjm_model* m, const int* bond, const double* t) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (!bond || !t) return fail(m, TJM_E_INVAL, "bond / tensors is NULL");
+  const int L = m->L, d = m->d;
+  if (bond[0] != 1 || bond[L] != 1) return fail(m, TJM_E_INVAL, "boundary bonds of the initial MPS must be 1");
+  long n = 0;
+  for (int l = 0; l < L; ++l) {
+    if (bond[l + 1] < 1 || bond[l + 1] > 64) return fail(m, TJM_E_INVAL, "initial MPS bonds must be in 1..64");
+    n += (long)d * bond[l] * bond[l + 1];
+  }
+  if (!finite_arr(t, 2 * n)) return fail(m, TJM_E_INVAL, "initial MPS has non-finite entries");
+  m->init_bond.assign(bond, bond + L + 1);
+  m->init_mps.resize(n);
+  for (long i = 0; i < n; ++i) m->init_mps[i] = cd(t[2 * i], t[2 * i + 1]);
+  return TJM_OK;
+}
+
 extern "C" tjm_status tjm_set_initial_product(tjm_model* m, const double* v) {
   if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
   if (!v) return fail(m, TJM_E_INVAL, "site_vec is NULL");
@@ -163,6 +182,8 @@ extern "C" tjm_status tjm_set_initial_product(tjm_model* m, const double* v) {
     for (int q = 0; q < m->d; ++q)
       m->init[(size_t)s * m->d + q] = f * cd(v[2 * (s * m->d + q)], v[2 * (s * m->d + q) + 1]);
   }
+  m->init_bond.clear();
+  m->init_mps.clear();
   return TJM_OK;
 }
 
@@ -387,6 +408,26 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   std::vector<long> soff(L + 1, 0);
   for (int s = 0; s < L; ++s) soff[s + 1] = soff[s] + (long)bcap[s] * d * bcap[s + 1];
   P.mps_cap = std::max<long>(soff[L], 1);
+  // Psi(0) as an MPS: bonds within the caps, tensors to the device layout
+  std::vector<double> init_t;
+  if (!m->init_bond.empty()) {
+    for (int b = 0; b <= L; ++b)
+      if (m->init_bond[b] > bcap[b])
+        return bail(TJM_E_INVAL, "initial MPS bond " + std::to_string(b) + " exceeds min(chi_cap, d^l, d^(L-l))");
+    init_t.assign(2 * P.mps_cap, 0.0);
+    long off = 0;
+    for (int l = 0; l < L; ++l) {
+      const int a = m->init_bond[l], bb = m->init_bond[l + 1];
+      for (int q = 0; q < d; ++q)
+        for (int i = 0; i < a; ++i)
+          for (int j = 0; j < bb; ++j) {
+            const cd x = m->init_mps[off + ((long)q * a + i) * bb + j];    // M_l[s][a][b]
+            const long e = soff[l] + ((long)i * d + q) * bb + j;           // device M[a][s][b]
+            init_t[2 * e] = x.real(); init_t[2 * e + 1] = x.imag();
+          }
+      off += (long)d * a * bb;
+    }
+  }
   const int chic = *std::max_element(bcap.begin(), bcap.end());
 
   // ---- worker scratch layout ---------------------------------------------
@@ -446,6 +487,9 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   RCHK(upload(r, oidx, (int**)&P.oidx));
   RCHK(upload(r, obsd, (double**)&P.obs_op));
   RCHK(upload(r, initd, (double**)&P.init_sites));
+  P.init_mps = m->init_bond.empty() ? 0 : 1;
+  RCHK(upload(r, init_t, (double**)&P.init_tensors));
+  RCHK(upload(r, m->init_bond, (int**)&P.init_bonds));
   RCHK(upload(r, soff, (long**)&P.site_off));
   RCHK(upload(r, bcap, (int**)&P.bond_cap));
   void* p = nullptr;

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(TJM_NT) void st_svd_kernel(int m, int n, const zd* 
     int cap, double deg_tol, int absorb, zd* left, zd* right, double* Sout, int* kout, zd* Wc, zd* Uc, zd* Tg) {
   __shared__ BlkScratch S;
   __shared__ SvdLds SL;
-  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
+  __shared__ alignas(16) char gl[SVD_LDS_BYTES > GEMM_LDS_BYTES ? SVD_LDS_BYTES : GEMM_LDS_BYTES];
   int k = blk_svd(m, n, G, left, right, absorb != 0, discard, cap, deg_tol, Wc, Uc, Tg, SL, S, gl);
   if (threadIdx.x == 0) *kout = k;
   for (int j = threadIdx.x; j < k; j += TJM_NT) Sout[j] = SL.s[SL.order[j]];

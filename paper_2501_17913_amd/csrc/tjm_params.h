@@ -46,6 +46,9 @@ struct TjmParams {
   const int* oidx;
   const double* obs_op;              // [n_obs][d][d] complex
   const double* init_sites;          // [L][d] complex product state
+  int init_mps;                      // 1: Psi(0) is the MPS below instead of init_sites
+  const double* init_tensors;        // Psi(0) site tensors in the trajectory layout (site_off), complex
+  const int* init_bonds;             // [L+1] bonds of Psi(0)
 
   // layout of one trajectory MPS (complex doubles)
   const long* site_off;              // [L+1]

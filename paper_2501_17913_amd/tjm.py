@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NUMERI
                 5: "E_UNSUPPORTED", 6: "E_BUSY"}
 
 EXPORTED = [
-    "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_run", "tjm_run_traces",
+    "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps", "tjm_run",
+    "tjm_run_traces",
     "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_get_stats", "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
@@ -64,6 +65,8 @@ lib.tjm_create.argtypes = [C.POINTER(_vp), C.c_int, C.c_int, _ip, _dp, C.c_int, 
 lib.tjm_create.restype = C.c_int
 lib.tjm_set_initial_product.argtypes = [_vp, _dp]
 lib.tjm_set_initial_product.restype = C.c_int
+lib.tjm_set_initial_mps.argtypes = [_vp, _ip, _dp]
+lib.tjm_set_initial_mps.restype = C.c_int
 lib.tjm_run.argtypes = [_vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_uint64,
                         C.POINTER(Options), _dp, _dp]
 lib.tjm_run.restype = C.c_int
@@ -165,6 +168,15 @@ class Model:
     def set_initial_product(self, site_vecs):
         v = _c128(site_vecs).reshape(-1)
         self._check(lib.tjm_set_initial_product(self.h, v.view(np.float64).ctypes.data_as(_dp)))
+
+    def set_initial_mps(self, tensors):
+        """Psi(0) as an MPS: tensors[l] has shape (d, bond[l], bond[l+1])."""
+        ts = [_c128(t) for t in tensors]
+        if len(ts) != self.L:
+            raise ValueError("need one tensor per site")
+        bond = np.array([1] + [t.shape[2] for t in ts], dtype=np.int32)
+        flat = np.concatenate([t.reshape(-1) for t in ts])
+        self._check(lib.tjm_set_initial_mps(self.h, _iptr(bond), flat.view(np.float64).ctypes.data_as(_dp)))
 
     @staticmethod
     def _obs(observables):

@@ -120,6 +120,24 @@ def test_initial_product_validation():
     m.set_initial_product(models.neel(4))
 
 
+def test_initial_mps_validation():
+    m = _model()
+    rng = np.random.default_rng(7)
+    good = [rng.normal(size=(2, a, b)) + 0j for a, b in [(1, 2), (2, 4), (4, 2), (2, 1)]]
+    m.set_initial_mps(good)
+    with pytest.raises(tjm.TjmError) as e:                 # right boundary bond must be 1
+        m.set_initial_mps(good[:3] + [rng.normal(size=(2, 2, 2)) + 0j])
+    assert e.value.status == tjm.E_INVAL
+    bad = [t.copy() for t in good]
+    bad[2][0, 0, 0] = np.inf
+    with pytest.raises(tjm.TjmError) as e:
+        m.set_initial_mps(bad)
+    assert e.value.status == tjm.E_INVAL
+    with pytest.raises(ValueError):
+        m.set_initial_mps(good[:3])
+    m.set_initial_product(models.neel(4))                 # back to a product state
+
+
 @pytest.mark.parametrize("kw,expect", [
     (dict(n_traj=0), tjm.E_INVAL), (dict(dt=0.0), tjm.E_INVAL), (dict(T=0.25), tjm.E_INVAL),
     (dict(chi_max=0), tjm.E_INVAL), (dict(obs_site=9), tjm.E_INVAL),

@@ -161,6 +161,35 @@ def test_c3_launch_mixed_sampled_trajectories():
     _large("C3", 2, tjm.PREC_MIXED, (0, 4095))
 
 
+def test_fp64_general_initial_mps_parity():
+    # Psi(0) a random MPS, unnormalised and in no particular gauge, with one
+    # rank-deficient bond (b_3 > d b_2 is allowed and kept, as the oracle keeps it)
+    L, chi, n, N, g, gamma = 6, 8, 6, 8, 0.5, 0.15
+    seed = inputs.SEED + 61
+    rng = np.random.default_rng(61)
+    bonds = [1, 2, 2, 5, 4, 2, 1]
+    psi0 = [rng.normal(size=(2, bonds[l], bonds[l + 1])) + 1j * rng.normal(size=(2, bonds[l], bonds[l + 1]))
+            for l in range(L)]
+    mpo, s_, o_, r_ = models.xxx_model(L, 1.0, g, gamma)
+    m = tjm.Model(L, mpo, s_, o_, r_)
+    m.set_initial_mps(psi0)
+    opt = tjm.default_options(precision=tjm.PREC_FP64, record_bonds=1)
+    res = m.run(N, 0.1, n * 0.1, chi, models.zx_observables(L), seed, opt, traces=True)
+    m.close()
+    Ws = om.xxx_mpo(L, 1.0, g)
+    jumps = om.relax_dephase_jumps(L, gamma, gamma)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    worst = 0.0
+    for t in range(N):
+        rec = {}
+        ref = mps_tjm.run_trajectory(Ws, jumps, psi0, 0.1, n, obs, seed, t, mps_tjm.Options(chi_max=chi), rec)
+        assert list(res['jumps'][t]) == [j for (_, _, j) in rec['jumps']]
+        assert np.array_equal(res['bonds'][t], np.array(rec['bonds']))
+        worst = max(worst, np.abs(res['per_traj'][t] - ref).max())
+    log("  general initial MPS: max |gpu - oracle| =", worst)
+    assert worst < 1e-10
+
+
 @pytest.mark.skip(reason="the transfer-environment jump path (sweep_jumps=0) faulted the device once "
                          "in the mixed L6 chi8 case and its cause is not found yet; it stays off by default")
 @pytest.mark.parametrize("case", [inputs.small_cases()[4], inputs.small_cases()[6]],
