@@ -199,6 +199,7 @@ struct SvdLds {
   int order[128];
   int rotated;
   int k;
+  unsigned long long offmax;   // bits of the largest |w_a^H w_b| / (|w_a| |w_b|) of a sweep
 };
 
 TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
@@ -229,8 +230,12 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   const int ngrp = TJM_NT / tpp;
   const int g = tid / tpp, gl = tid % tpp;
   const double tol = 2.220446049250313e-16 * sqrt((double)p);
+  // convergence is quadratic: a sweep that started with every relative
+  // off-diagonal below 1e-3 sqrt(tol) leaves them far below tol, so no
+  // further sweep is needed to confirm it
+  const double quad = 1e-3 * sqrt(tol);
   for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
-    if (tid == 0) SL.rotated = 0;
+    if (tid == 0) { SL.rotated = 0; SL.offmax = 0ull; }
     tjm_sync();
     for (int rnd = 0; rnd < np - 1; ++rnd) {
       for (int pr = g; pr < npair; pr += ngrp) {
@@ -251,6 +256,10 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
         aa = grp_sum(aa, tpp); bb = grp_sum(bb, tpp);
         cr = grp_sum(cr, tpp); ci = grp_sum(ci, tpp);
         const double ac = hypot(cr, ci);
+        if (aa > zero2 && bb > zero2 && gl == 0) {
+          const double rel = ac / (sqrt(aa) * sqrt(bb));   // >= 0: its bits order like the value
+          atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1.0));
+        }
         if (aa > zero2 && bb > zero2 && ac > tol * sqrt(aa) * sqrt(bb)) {
           const double zeta = (bb - aa) / (2.0 * ac);
           const double az = fabs(zeta);
@@ -268,7 +277,7 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
       }
       tjm_sync();
     }
-    if (SL.rotated == 0) break;
+    if (SL.rotated == 0 || __longlong_as_double((long long)SL.offmax) < quad) break;
     tjm_sync();
   }
   // singular values, descending order (stable in the column index)
