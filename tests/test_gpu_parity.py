@@ -205,3 +205,43 @@ def test_fp64_environment_jump_path_parity(case):
         assert list(res['jumps'][t]) == jl
         assert np.array_equal(res['bonds'][t], bl)
         assert np.abs(res['per_traj'][t] - ref).max() < 1e-10
+
+
+def test_degenerate_runs():
+    """Edge cases of the method and the interface, each against the oracle:
+    no jump operators at all, gamma = 0 (delta p = 0: never a jump), one
+    step, one trajectory, no observables."""
+    L, chi, g = 5, 4, 0.6
+    Ws = om.xxx_mpo(L, 1.0, g)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    sv = om.product_site_vectors(L, inputs.init_bits(L, "neel"))
+    seed = inputs.SEED + 71
+    # no jump operators: the paper's method reduces to TDVP with renormalisation
+    m = tjm.Model(L, models.xxx_mpo(L, 1.0, g), [], [], [])
+    m.set_initial_product(models.neel(L))
+    res = m.run(3, 0.1, 0.4, chi, models.zx_observables(L), seed, tjm.default_options(record_bonds=1), traces=True)
+    m.close()
+    assert np.all(res['jumps'] == -1)
+    for t in range(3):
+        ref = mps_tjm.run_trajectory(Ws, [], mps_tjm.product_mps(sv), 0.1, 4, obs, seed, t, mps_tjm.Options(chi_max=chi))
+        assert np.abs(res['per_traj'][t] - ref).max() < 1e-10
+    # gamma = 0 with jump operators present: identical to the run without them
+    mpo, s_, o_, r_ = models.xxx_model(L, 1.0, g, 0.0)
+    m = tjm.Model(L, mpo, s_, o_, r_)
+    m.set_initial_product(models.neel(L))
+    res0 = m.run(3, 0.1, 0.4, chi, models.zx_observables(L), seed, tjm.default_options(record_bonds=1), traces=True)
+    assert np.all(res0['jumps'] == -1)
+    assert np.abs(res0['per_traj'] - res['per_traj']).max() < 1e-12
+    # one step, one trajectory, and a run without observables
+    res1 = m.run(1, 0.1, 0.1, chi, models.zx_observables(L), seed, tjm.default_options(), traces=True)
+    assert res1['per_traj'].shape == (1, 2, 2 * L)
+    assert np.abs(res1['per_traj'][0] - res0['per_traj'][0][:2]).max() < 1e-12
+    out = m.run(2, 0.1, 0.2, chi, [], seed, tjm.default_options())
+    assert out['mean'].shape == (3, 0)
+    m.close()
+
+
+def test_c4_launch_mixed_sampled_trajectory():
+    # the long chain (L = 1000, chi 16): every trajectory, one step, one
+    # trajectory recomputed by the oracle, properties of all of them
+    _large("C4", 1, tjm.PREC_MIXED, (0,))
