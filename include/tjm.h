@@ -72,7 +72,8 @@ typedef struct {
   int krylov_max;         /* Lanczos iterations per exponential, 1..32;
                              default 30                                       */
   double krylov_tol;      /* stop when beta_j |[exp(-itT)]_{j,0}| <= tol;
-                             <= 0 selects 1e-12 (FP64) or 1e-10 (mixed)       */
+                             <= 0 selects 1e-12 (FP64) or 1e-6 (mixed, the
+                             accuracy of its FP32 contractions)              */
   double deg_tol;         /* multiplet tolerance at the cap, default 1e-12    */
   int workers;            /* resident workgroups; <= 0: automatic             */
   int record_bonds;       /* 1: keep bond dimensions after every U[dt]        */

@@ -272,7 +272,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   if ((double)n_traj * (double)(n + 1) * std::max(n_obs, 1) > 4e9)
     return fail(m, TJM_E_INVAL, "output too large");
   double tol = opt.krylov_tol;
-  if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-10 : 1e-12;
+  if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-6 : 1e-12;   // mixed: at the FP32 contraction accuracy
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(m, TJM_E_DEVICE, "no HIP device");
