@@ -256,17 +256,20 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
         aa = grp_sum(aa, tpp); bb = grp_sum(bb, tpp);
         cr = grp_sum(cr, tpp); ci = grp_sum(ci, tpp);
         const double ac = hypot(cr, ci);
-        if (aa > zero2 && bb > zero2 && gl == 0) {
-          const double rel = ac / (sqrt(aa) * sqrt(bb));   // >= 0: its bits order like the value
+        if (!(aa > zero2 && bb > zero2)) continue;
+        const double sab = sqrt(aa) * sqrt(bb);     // no overflow for large norms
+        if (gl == 0) {
+          const double rel = ac / sab;              // >= 0: its bits order like the value
           atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1.0));
         }
-        if (aa > zero2 && bb > zero2 && ac > tol * sqrt(aa) * sqrt(bb)) {
-          const double zeta = (bb - aa) / (2.0 * ac);
+        if (ac > tol * sab) {
+          const double inv = 1.0 / ac;
+          const double zeta = 0.5 * (bb - aa) * inv;
           const double az = fabs(zeta);
           double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
           if (zeta < 0.0) t = -t;
-          double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          zd eph = cmk(cr / ac, -ci / ac);      // conj(c)/|c|
+          const double cs = rsqrt(1.0 + t * t), sn = cs * t;
+          const zd eph = cmk(cr * inv, -ci * inv);  // conj(c)/|c|
           for (int r = gl; r < p; r += tpp) {
             zd x = wa[r], y = eph * wb[r];
             wa[r] = cs * x - sn * y;
