@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -142,6 +144,60 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
     }
 
 
+def serving(tjm, models, K, precision):
+    """The first K requests of the serving stream, submitted at their arrival
+    times to one tjm_server; latency = submission to completion."""
+    from tests import inputs
+    reqs = inputs.serving_stream(K)
+    prec = tjm.PREC_MIXED if precision == "mixed" else tjm.PREC_FP64
+    built = []
+    for q in reqs:                       # host-side model tables, before the clock starts
+        mpo, s, o, r = models.xxx_model(q["L"], 1.0, q["g"], q["gamma"])
+        m = tjm.Model(q["L"], mpo, s, o, r)
+        m.set_initial_product(models.neel(q["L"]))
+        built.append(m)
+    srv = tjm.Server(0)
+    t0 = time.perf_counter()
+    ids = []
+    for q, m in zip(reqs, built):
+        delay = t0 + q["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(m, q["n_traj"], q["dt"], q["T"], q["chi_max"], models.zx_observables(q["L"]),
+                              q["seed"], tjm.default_options(precision=prec)))
+    reps = []
+    pending = set(range(len(ids)))
+    while pending:                        # progress as jobs finish, in any order
+        for i in sorted(pending):
+            if srv.poll(ids[i]):
+                reps.append((i, srv.wait(ids[i])["report"]))
+                pending.discard(i)
+                print("  request %d done (%d of %d) at %.1fs" % (i, len(reps), len(ids), time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+        time.sleep(0.01)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    for m in built:
+        m.close()
+    reps.sort()
+    lat = np.array([r["latency_s"] for _, r in reps])
+    steps = sum(r["n_traj"] * r["n_steps"] for _, r in reps)
+    flop = sum(8.0 * r["stats"]["cmac_mfma"] for _, r in reps)
+    return {
+        "metric": "p50/p99 latency of the serving stream (first %d requests)" % K,
+        "value": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "unit": "s",
+        "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "c64-mfma+f64" if prec else "f64",
+        "requests": K, "offered_rate_per_s": K / reqs[-1]["t"], "makespan_s": makespan,
+        "mean_queue_s": float(np.mean([r["queue_s"] for _, r in reps])),
+        "mean_run_s": float(np.mean([r["run_s"] for _, r in reps])),
+        "traj_steps_per_s": steps / makespan, "achieved_tflops": flop / makespan / 1e12,
+        "config": {"workload": "serving stream: Poisson arrivals (mean 0.05 s), XXX chains L~U{20..200}, "
+                               "chi_max in {16,32,64}, gamma~U[0.01,0.2], g~U[0,1], N~U{64..512}, "
+                               "T~U[1,5], Neel; numpy default_rng(5); %s" % precision,
+                   "requests": [{k: q[k] for k in ("L", "chi_max", "n_traj", "n_steps")} for q in reqs]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +213,8 @@ def main():
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel used to calibrate the traffic counters")
+    ap.add_argument("--serving", type=int, default=0, metavar="K",
+                    help="instead: latency of the first K requests of the serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -166,6 +224,10 @@ def main():
 
     if args.copy_calibration:
         print(json.dumps(copy_calibration(tjm)), flush=True)
+        return
+
+    if args.serving > 0:
+        print(json.dumps(serving(tjm, models, args.serving, args.precision)), flush=True)
         return
 
     w = dict(WORKLOADS[args.workload])

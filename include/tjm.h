@@ -220,6 +220,89 @@ const char *tjm_last_error(const tjm_model *m);
 /* Releases the model and any run it holds; NULL is ignored. */
 void tjm_destroy(tjm_model *m);
 
+/*
+ * Serving.  A server executes independent jobs, each one whole run as
+ * tjm_run defines it (Sec. "Algorithm"), on one GPU as they are submitted.
+ * Trajectories of different jobs never interact (Eq. TJMExpVal averages
+ * within a job), so up to four admitted jobs run at once, each on a HIP
+ * stream of its own; their results are bit-identical to tjm_run with the
+ * same arguments.  Admission is first come, first served: the oldest waiting
+ * job starts when an executor is free and its device-memory footprint fits
+ * into the budget not held by running jobs; no younger job overtakes it.
+ * The server functions are thread-safe; a model handle passed to
+ * tjm_submit is only read during that call (the server keeps a copy).
+ */
+typedef struct tjm_server tjm_server;
+
+/* Arguments of one job: those of tjm_run.  The server copies them. */
+typedef struct {
+  int n_traj;
+  double dt;
+  double T;
+  int chi_max;
+  int n_obs;
+  const int *obs_site;      /* n_obs sites                                   */
+  const double *obs_op;     /* n_obs complex d x d matrices                  */
+  uint64_t seed;
+  const tjm_options *opt;   /* NULL: defaults; opt->device is replaced by the
+                               server's device, opt->workers is capped so
+                               the job stays within its admitted footprint */
+} tjm_run_args;
+
+/* What tjm_wait reports about a finished job. */
+typedef struct {
+  double latency_s;         /* submission to completion (steady clock)       */
+  double queue_s;           /* submission to start                           */
+  double run_s;             /* start to completion                           */
+  double start_s, end_s;    /* start and completion on the same steady clock
+                               (seconds from an arbitrary origin, comparable
+                               between jobs of one process)                 */
+  int n_traj, n_steps;
+  size_t device_bytes;      /* footprint the job was admitted with           */
+  tjm_stats stats;          /* counters and kernel timings of its run        */
+} tjm_job_report;
+
+/*
+ * Creates a server on HIP device `device` with a device-memory budget
+ * (bytes; 0 selects 85% of the memory free at creation) and starts its
+ * executor threads.  Errors: TJM_E_INVAL (NULL, device ordinal),
+ * TJM_E_DEVICE (no GPU), TJM_E_NOMEM.
+ */
+tjm_status tjm_server_create(tjm_server **out, int device, size_t hbm_budget_bytes);
+
+/*
+ * Queues one job and returns its id in *job without waiting for it.  The
+ * arguments are validated as tjm_run validates them (TJM_E_INVAL,
+ * TJM_E_UNSUPPORTED) and the job is sized; a job larger than the whole
+ * budget is refused with TJM_E_NOMEM.  TJM_E_BUSY once the server is being
+ * destroyed.
+ */
+tjm_status tjm_submit(tjm_server *s, const tjm_model *m, const tjm_run_args *args, uint64_t *job);
+
+/* *done = 1 if the job has finished (successfully or not), else 0.
+ * TJM_E_INVAL for an unknown or already collected job. */
+tjm_status tjm_poll(tjm_server *s, uint64_t job, int *done);
+
+/*
+ * Blocks until the job has finished, then writes its outputs into
+ * caller-allocated buffers (each may be NULL): mean and sem as in tjm_run,
+ * [(n+1)][n_obs] each, and the report.  Returns the job's own status (the
+ * outputs are written only for TJM_OK) and releases the job: its id is
+ * unknown afterwards (TJM_E_INVAL).  TJM_E_BUSY if another call is already
+ * waiting for the same job.
+ */
+tjm_status tjm_wait(tjm_server *s, uint64_t job, double *mean, double *sem, tjm_job_report *report);
+
+/* Message of the last failing server call made by the calling thread. */
+const char *tjm_server_last_error(void);
+
+/*
+ * Stops the server: jobs not yet started are dropped, running jobs are
+ * finished, then every resource is released.  No other call on s may be in
+ * progress or follow.  NULL is ignored.
+ */
+void tjm_server_destroy(tjm_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,7 @@ def build(verbose=False):
     """Compile every HIP source and link libtjm.so; returns its path."""
     objs = []
     procs = []
-    for src in ("tjm_kernels.hip", "tjm_api.cpp"):
+    for src in ("tjm_kernels.hip", "tjm_api.cpp", "tjm_server.cpp"):
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

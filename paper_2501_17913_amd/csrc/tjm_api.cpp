@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -222,7 +223,7 @@ static hipError_t upload(Run* r, const std::vector<T>& h, T** dptr) {
   if (e != hipSuccess) return e;
   r->allocs.push_back(p);
   r->bytes += n;
-  if (!h.empty()) e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (!h.empty()) e = hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, r->stream);
   *dptr = (T*)p;
   return e;
 }
@@ -233,21 +234,34 @@ static hipError_t dalloc(Run* r, size_t n, void** dptr) {
   if (e != hipSuccess) return e;
   r->allocs.push_back(p);
   r->bytes += n;
-  e = hipMemset(p, 0, std::max<size_t>(n, 16));
+  e = hipMemsetAsync(p, 0, std::max<size_t>(n, 16), r->stream);
   *dptr = p;
   return e;
 }
 
 static long align256(long x) { return (x + 255) & ~255L; }
 
-extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double T, int chi_max,
-                                    int n_obs, const int* obs_site, const double* obs_op,
-                                    uint64_t seed, const tjm_options* opt_in) {
-  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
-  if (m->run) return fail(m, TJM_E_BUSY, "a run is already in progress on this model");
-  tjm_options opt;
-  tjm_default_options(&opt);
-  if (opt_in) opt = *opt_in;
+namespace {
+// Everything a run needs that is computed on the host: validated sizes, the
+// kernel parameters except device pointers, the tables to upload and the
+// device-memory layout.  No HIP call is made while it is built.
+struct Plan {
+  TjmParams P;
+  long n = 0;
+  std::vector<MixEnt> ents;
+  std::vector<int> mixL_ptr, mixR_ptr, mix2_ptr, jptr, jidx, optr, oidx, bcap;
+  std::vector<double> Dh, Df, jopd, initd, obsd, init_t;
+  std::vector<long> soff;
+  double per_traj = 0;       // device bytes per trajectory (MPS, logs, outputs)
+};
+}  // namespace
+
+template <typename T>
+static double vec_bytes(const std::vector<T>& v) { return (double)std::max<size_t>(v.size(), 1) * sizeof(T); }
+
+static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                           const int* obs_site, const double* obs_op, uint64_t seed,
+                           const tjm_options& opt, Plan& pl) {
   const int L = m->L, d = m->d;
   if (n_traj < 1) return fail(m, TJM_E_INVAL, "n_traj must be >= 1");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m, TJM_E_INVAL, "dt must be > 0");
@@ -274,43 +288,28 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   double tol = opt.krylov_tol;
   if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-6 : 1e-12;   // mixed: at the FP32 contraction accuracy
 
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(m, TJM_E_DEVICE, "no HIP device");
-  if (opt.device < 0 || opt.device >= ndev) return fail(m, TJM_E_INVAL, "device ordinal out of range");
-  HIPCHK(m, hipSetDevice(opt.device));
 
-  Run* r = new Run();
-  r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = n_obs; r->record_bonds = opt.record_bonds ? 1 : 0;
-  TjmParams& P = r->P;
+  TjmParams& P = pl.P;
   std::memset(&P, 0, sizeof(P));
+  pl.n = n;
   P.L = L; P.d = d;
   P.Dmax = *std::max_element(m->mpoD.begin(), m->mpoD.end());
   P.n_traj = n_traj; P.n_steps = (int)n;
   P.chi_max = chi_max; P.chi_cap = chi_cap; P.krylov_max = opt.krylov_max;
-  P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = r->record_bonds;
+  P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = opt.record_bonds ? 1 : 0;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
   P.sweep_jumps = opt.sweep_jumps ? 1 : 0;
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
   P.seed = seed; P.traj_base = opt.traj_base;
 
-  auto bail = [&](tjm_status st, const std::string& msg) {
-    free_run(r);
-    return fail(m, st, msg);
-  };
-#define RCHK(expr)                                                                              \
-  do {                                                                                          \
-    hipError_t e_ = (expr);                                                                     \
-    if (e_ != hipSuccess)                                                                       \
-      return bail(e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,                      \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
-  } while (0)
-
   // ---- MPO mixing tables -------------------------------------------------
   const int Dm = P.Dmax;
-  std::vector<MixEnt> ents;
-  std::vector<int> mixL_ptr((size_t)L * (Dm * d + 1)), mixR_ptr((size_t)L * (Dm * d + 1));
-  std::vector<int> mix2_ptr((size_t)std::max(L - 1, 1) * (Dm * d * d + 1), 0);
+  auto& ents = pl.ents;
+  auto& mixL_ptr = pl.mixL_ptr; auto& mixR_ptr = pl.mixR_ptr; auto& mix2_ptr = pl.mix2_ptr;
+  mixL_ptr.assign((size_t)L * (Dm * d + 1), 0);
+  mixR_ptr.assign((size_t)L * (Dm * d + 1), 0);
+  mix2_ptr.assign((size_t)std::max(L - 1, 1) * (Dm * d * d + 1), 0);
   auto push = [&](int w, int s, cd v) {
     MixEnt e; e.w = w; e.s = s; e.re = v.real(); e.im = v.imag();
     ents.push_back(e);
@@ -359,7 +358,8 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   }
 
   // ---- dissipators, jumps, observables ------------------------------------
-  std::vector<double> Dh((size_t)L * 8), Df((size_t)L * 8);
+  auto& Dh = pl.Dh; auto& Df = pl.Df;
+  Dh.assign((size_t)L * 8, 0.0); Df.assign((size_t)L * 8, 0.0);
   for (int s = 0; s < L; ++s) {
     cd G[4] = {0, 0, 0, 0};
     for (int j = 0; j < m->n_jump; ++j) {
@@ -377,43 +377,47 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
       Df[(size_t)s * 8 + 2 * e] = f[e].real(); Df[(size_t)s * 8 + 2 * e + 1] = f[e].imag();
     }
   }
-  std::vector<int> jptr(L + 1, 0), jidx;
+  auto& jptr = pl.jptr; auto& jidx = pl.jidx;
+  jptr.assign(L + 1, 0);
   for (int s = 0; s < L; ++s) {
     jptr[s] = (int)jidx.size();
     for (int j = 0; j < m->n_jump; ++j)
       if (m->jsite[j] == s) jidx.push_back(j);
   }
   jptr[L] = (int)jidx.size();
-  std::vector<int> optr(L + 1, 0), oidx;
+  auto& optr = pl.optr; auto& oidx = pl.oidx;
+  optr.assign(L + 1, 0);
   for (int s = 0; s < L; ++s) {
     optr[s] = (int)oidx.size();
     for (int o = 0; o < n_obs; ++o)
       if (obs_site[o] == s) oidx.push_back(o);
   }
   optr[L] = (int)oidx.size();
-  std::vector<double> jopd(m->jop.size() * 2), initd(m->init.size() * 2);
+  auto& jopd = pl.jopd; auto& initd = pl.initd;
+  jopd.assign(m->jop.size() * 2, 0.0); initd.assign(m->init.size() * 2, 0.0);
   for (size_t i = 0; i < m->jop.size(); ++i) { jopd[2 * i] = m->jop[i].real(); jopd[2 * i + 1] = m->jop[i].imag(); }
   for (size_t i = 0; i < m->init.size(); ++i) { initd[2 * i] = m->init[i].real(); initd[2 * i + 1] = m->init[i].imag(); }
-  std::vector<double> obsd(obs_op ? obs_op : (const double*)nullptr,
-                           obs_op ? obs_op + 2L * n_obs * d * d : (const double*)nullptr);
+  pl.obsd.assign(obs_op ? obs_op : (const double*)nullptr, obs_op ? obs_op + 2L * n_obs * d * d : (const double*)nullptr);
 
   // ---- MPS layout: bond b holds at most min(chi_cap, d^b, d^(L-b)) ----------
-  std::vector<int> bcap(L + 1);
+  auto& bcap = pl.bcap;
+  bcap.assign(L + 1, 0);
   for (int b = 0; b <= L; ++b) {
     long c1 = 1, c2 = 1;
     for (int i = 0; i < b && c1 < chi_cap; ++i) c1 *= d;
     for (int i = 0; i < L - b && c2 < chi_cap; ++i) c2 *= d;
     bcap[b] = (int)std::min<long>(chi_cap, std::min(c1, c2));
   }
-  std::vector<long> soff(L + 1, 0);
+  auto& soff = pl.soff;
+  soff.assign(L + 1, 0);
   for (int s = 0; s < L; ++s) soff[s + 1] = soff[s] + (long)bcap[s] * d * bcap[s + 1];
   P.mps_cap = std::max<long>(soff[L], 1);
   // Psi(0) as an MPS: bonds within the caps, tensors to the device layout
-  std::vector<double> init_t;
+  auto& init_t = pl.init_t;
   if (!m->init_bond.empty()) {
     for (int b = 0; b <= L; ++b)
       if (m->init_bond[b] > bcap[b])
-        return bail(TJM_E_INVAL, "initial MPS bond " + std::to_string(b) + " exceeds min(chi_cap, d^l, d^(L-l))");
+        return fail(m, TJM_E_INVAL, "initial MPS bond " + std::to_string(b) + " exceeds min(chi_cap, d^l, d^(L-l))");
     init_t.assign(2 * P.mps_cap, 0.0);
     long off = 0;
     for (int l = 0; l < L; ++l) {
@@ -450,48 +454,132 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   P.off_wts = o; o = align256(o + (long)std::max(m->n_jump, 1) * 8);
   P.scratch_stride = o;
 
-  // ---- worker count --------------------------------------------------------
+  pl.per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_obs * 8.0 + 2.0 * n * 4 +
+                (P.record_bonds ? (double)n * (L + 1) * 4 : 0.0) + TJM_NSTAT * 8 + 4;
+  return TJM_OK;
+}
+
+// Resident workgroups for a plan on a device: blocks per CU times CUs,
+// capped by opt.workers and by the trajectory count.
+static tjm_status plan_workers(tjm_model* m, const Plan& pl, const tjm_options& opt, long* workers) {
   hipDeviceProp_t prop;
-  RCHK(hipGetDeviceProperties(&prop, opt.device));
+  HIPCHK(m, hipGetDeviceProperties(&prop, opt.device));
   int bpc = 1;
-  RCHK(tjm_blocks_per_cu(P.mixed, L, &bpc));
-  if (bpc < 1) return bail(TJM_E_UNSUPPORTED, "kernel does not fit on a compute unit");
-  long workers = (long)bpc * prop.multiProcessorCount;
-  if (opt.workers > 0) workers = std::min<long>(workers, opt.workers);
-  workers = std::min<long>(workers, n_traj);
+  HIPCHK(m, tjm_blocks_per_cu(pl.P.mixed, pl.P.L, &bpc));
+  if (bpc < 1) return fail(m, TJM_E_UNSUPPORTED, "kernel does not fit on a compute unit");
+  long w = (long)bpc * prop.multiProcessorCount;
+  if (opt.workers > 0) w = std::min<long>(w, opt.workers);
+  *workers = std::min<long>(w, pl.P.n_traj);
+  return TJM_OK;
+}
+
+static tjm_status select_device(tjm_model* m, const tjm_options& opt) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(m, TJM_E_DEVICE, "no HIP device");
+  if (opt.device < 0 || opt.device >= ndev) return fail(m, TJM_E_INVAL, "device ordinal out of range");
+  HIPCHK(m, hipSetDevice(opt.device));
+  return TJM_OK;
+}
+
+tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                             const int* obs_site, const double* obs_op, const tjm_options* opt_in,
+                             size_t* bytes, int* workers) {
+  if (!m || !bytes || !workers) return fail(m, TJM_E_INVAL, "NULL argument");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  Plan pl;
+  tjm_status st = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, 0, opt, pl);
+  if (st != TJM_OK) return st;
+  if ((st = select_device(m, opt)) != TJM_OK) return st;
+  long w = 1;
+  if ((st = plan_workers(m, pl, opt, &w)) != TJM_OK) return st;
+  double b = vec_bytes(pl.ents) + vec_bytes(pl.mixL_ptr) + vec_bytes(pl.mixR_ptr) + vec_bytes(pl.mix2_ptr) +
+             vec_bytes(pl.Dh) + vec_bytes(pl.Df) + vec_bytes(pl.jopd) + vec_bytes(m->jrate) +
+             vec_bytes(m->jsite) + vec_bytes(pl.jptr) + vec_bytes(pl.jidx) + vec_bytes(pl.optr) +
+             vec_bytes(pl.oidx) + vec_bytes(pl.obsd) + vec_bytes(pl.initd) + vec_bytes(pl.init_t) +
+             vec_bytes(m->init_bond) + vec_bytes(pl.soff) + vec_bytes(pl.bcap) + vec_bytes(m->mpoD);
+  b += pl.per_traj * n_traj + (double)w * pl.P.scratch_stride + 256;
+  b += 2.0 * 8 * (pl.n + 1) * std::max(n_obs, 1);        // reduction outputs
+  b += 64.0 * 1024 * 64;                                  // allocation granularity, 64 allocations
+  *bytes = (size_t)b;
+  *workers = (int)w;
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double T, int chi_max,
+                                    int n_obs, const int* obs_site, const double* obs_op,
+                                    uint64_t seed, const tjm_options* opt_in) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (m->run) return fail(m, TJM_E_BUSY, "a run is already in progress on this model");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  Plan pl;
+  tjm_status st0 = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt, pl);
+  if (st0 != TJM_OK) return st0;
+  if ((st0 = select_device(m, opt)) != TJM_OK) return st0;
+  const int L = m->L;
+  const long n = pl.n;
+
+  Run* r = new Run();
+  r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = n_obs; r->record_bonds = pl.P.record_bonds;
+  r->P = pl.P;
+  TjmParams& P = r->P;
+  auto bail = [&](tjm_status st, const std::string& msg) {
+    free_run(r);
+    return fail(m, st, msg);
+  };
+#define RCHK(expr)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return bail(e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,                      \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+
+  // ---- worker count --------------------------------------------------------
+  long workers = 1;
+  {
+    tjm_status stw = plan_workers(m, pl, opt, &workers);
+    if (stw != TJM_OK) { free_run(r); return stw; }
+  }
   size_t freeb = 0, totalb = 0;
   RCHK(hipMemGetInfo(&freeb, &totalb));
-  const double per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_obs * 8.0 + 2.0 * n * 4 +
-                          (r->record_bonds ? (double)n * (L + 1) * 4 : 0.0) + TJM_NSTAT * 8 + 4;
-  const double avail = 0.85 * (double)freeb - per_traj * n_traj;
+  const double avail = 0.85 * (double)freeb - pl.per_traj * n_traj;
   if (avail < (double)P.scratch_stride) return bail(TJM_E_NOMEM, "not enough device memory for the run");
   workers = std::min<long>(workers, (long)(avail / (double)P.scratch_stride));
   r->workers = (int)std::max<long>(workers, 1);
-
   // ---- uploads ---------------------------------------------------------------
+  // Every copy and zero fill is ordered on the run's stream, ahead of the
+  // launches, so runs on other streams of the device are not waited for.
+  RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+  RCHK(hipEventCreate(&r->ev0));
+  RCHK(hipEventCreate(&r->ev1));
   RCHK(upload(r, m->mpoD, (int**)&P.mpoD));
   MixEnt* dents = nullptr;
-  RCHK(upload(r, ents, &dents));
+  RCHK(upload(r, pl.ents, &dents));
   P.mixL = dents; P.mixR = dents; P.mix2 = dents;
-  RCHK(upload(r, mixL_ptr, (int**)&P.mixL_ptr));
-  RCHK(upload(r, mixR_ptr, (int**)&P.mixR_ptr));
-  RCHK(upload(r, mix2_ptr, (int**)&P.mix2_ptr));
-  RCHK(upload(r, Dh, (double**)&P.Dhalf));
-  RCHK(upload(r, Df, (double**)&P.Dfull));
-  RCHK(upload(r, jopd, (double**)&P.jump_op));
+  RCHK(upload(r, pl.mixL_ptr, (int**)&P.mixL_ptr));
+  RCHK(upload(r, pl.mixR_ptr, (int**)&P.mixR_ptr));
+  RCHK(upload(r, pl.mix2_ptr, (int**)&P.mix2_ptr));
+  RCHK(upload(r, pl.Dh, (double**)&P.Dhalf));
+  RCHK(upload(r, pl.Df, (double**)&P.Dfull));
+  RCHK(upload(r, pl.jopd, (double**)&P.jump_op));
   RCHK(upload(r, m->jrate, (double**)&P.jump_rate));
   RCHK(upload(r, m->jsite, (int**)&P.jump_site));
-  RCHK(upload(r, jptr, (int**)&P.jptr));
-  RCHK(upload(r, jidx, (int**)&P.jidx));
-  RCHK(upload(r, optr, (int**)&P.optr));
-  RCHK(upload(r, oidx, (int**)&P.oidx));
-  RCHK(upload(r, obsd, (double**)&P.obs_op));
-  RCHK(upload(r, initd, (double**)&P.init_sites));
+  RCHK(upload(r, pl.jptr, (int**)&P.jptr));
+  RCHK(upload(r, pl.jidx, (int**)&P.jidx));
+  RCHK(upload(r, pl.optr, (int**)&P.optr));
+  RCHK(upload(r, pl.oidx, (int**)&P.oidx));
+  RCHK(upload(r, pl.obsd, (double**)&P.obs_op));
+  RCHK(upload(r, pl.initd, (double**)&P.init_sites));
   P.init_mps = m->init_bond.empty() ? 0 : 1;
-  RCHK(upload(r, init_t, (double**)&P.init_tensors));
+  RCHK(upload(r, pl.init_t, (double**)&P.init_tensors));
   RCHK(upload(r, m->init_bond, (int**)&P.init_bonds));
-  RCHK(upload(r, soff, (long**)&P.site_off));
-  RCHK(upload(r, bcap, (int**)&P.bond_cap));
+  RCHK(upload(r, pl.soff, (long**)&P.site_off));
+  RCHK(upload(r, pl.bcap, (int**)&P.bond_cap));
   void* p = nullptr;
   RCHK(dalloc(r, (size_t)n_traj * P.mps_cap * 16, &p)); P.mps = (double*)p;
   RCHK(dalloc(r, (size_t)n_traj * (L + 1) * 4, &p)); P.bonds = (int*)p;
@@ -505,12 +593,8 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
   RCHK(dalloc(r, 256, &p)); P.counter = (int*)p;
 
-  RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
-  RCHK(hipEventCreate(&r->ev0));
-  RCHK(hipEventCreate(&r->ev1));
-  // The zero fills and uploads above run on the null stream, which a
-  // non-blocking stream does not wait for: finish them before any launch.
-  RCHK(hipDeviceSynchronize());
+  // the host tables of the plan must outlive their copies
+  RCHK(hipStreamSynchronize(r->stream));
 
   // ---- F_0 ------------------------------------------------------------------
   RCHK(tjm_launch_reset(P.counter, r->stream));
@@ -655,6 +739,23 @@ extern "C" tjm_status tjm_run(tjm_model* m, int n_traj, double dt, double T, int
 extern "C" const char* tjm_last_error(const tjm_model* m) {
   return m ? m->err.c_str() : g_create_err.c_str();
 }
+
+tjm_model* tjm_model_copy(const tjm_model* m) {
+  if (!m) return nullptr;
+  tjm_model* c = new (std::nothrow) tjm_model();
+  if (!c) return nullptr;
+  try {
+    c->L = m->L; c->d = m->d; c->mpoD = m->mpoD; c->W = m->W;
+    c->n_jump = m->n_jump; c->jsite = m->jsite; c->jop = m->jop; c->jrate = m->jrate;
+    c->init = m->init; c->init_bond = m->init_bond; c->init_mps = m->init_mps;
+  } catch (...) {
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
+int tjm_model_d(const tjm_model* m) { return m ? m->d : 0; }
 
 extern "C" void tjm_destroy(tjm_model* m) {
   if (!m) return;

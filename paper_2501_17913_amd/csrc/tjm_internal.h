@@ -2,6 +2,7 @@
 // (tjm_kernels.hip).  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "tjm.h"
 #include "tjm_params.h"
 
 size_t tjm_dyn_lds_bytes(int L);
@@ -26,3 +27,14 @@ hipError_t tjm_launch_st_expm(int n, const double* H, double* v, double t, int k
 hipError_t tjm_launch_st_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
                                 uint32_t* out);
 hipError_t tjm_launch_st_copy(const void* src, void* dst, long n16, int blocks, hipStream_t s);
+
+// Host-side helpers of tjm_api.cpp used by the server (tjm_server.cpp).
+// A deep copy of a model's inputs (no run state); NULL if out of memory.
+tjm_model* tjm_model_copy(const tjm_model* m);
+int tjm_model_d(const tjm_model* m);
+// Validates a run as tjm_run_begin does and returns the device memory it
+// would hold and the resident workgroups it would use (opt->workers caps
+// them).  Makes opt->device current.  Errors as tjm_run_begin, message on m.
+tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                             const int* obs_site, const double* obs_op, const tjm_options* opt,
+                             size_t* bytes, int* workers);

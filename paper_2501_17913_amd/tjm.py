@@ -25,6 +25,8 @@ EXPORTED = [
     "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_get_stats", "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
+    "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_wait", "tjm_server_last_error",
+    "tjm_server_destroy",
 ]
 
 
@@ -51,6 +53,23 @@ class Stats(C.Structure):
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_s"}
         d["phase_s"] = {k: self.phase_s[i] for i, k in enumerate(self.PHASES)}
+        return d
+
+
+class RunArgs(C.Structure):
+    _fields_ = [("n_traj", C.c_int), ("dt", C.c_double), ("T", C.c_double), ("chi_max", C.c_int),
+                ("n_obs", C.c_int), ("obs_site", C.POINTER(C.c_int)), ("obs_op", C.POINTER(C.c_double)),
+                ("seed", C.c_uint64), ("opt", C.POINTER(Options))]
+
+
+class JobReport(C.Structure):
+    _fields_ = [("latency_s", C.c_double), ("queue_s", C.c_double), ("run_s", C.c_double),
+                ("start_s", C.c_double), ("end_s", C.c_double), ("n_traj", C.c_int), ("n_steps", C.c_int), ("device_bytes", C.c_size_t),
+                ("stats", Stats)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stats"}
+        d["stats"] = self.stats.as_dict()
         return d
 
 
@@ -101,6 +120,18 @@ lib.tjm_selftest_philox.argtypes = [C.c_int, _up, C.c_uint32, C.c_uint32, _up]
 lib.tjm_selftest_philox.restype = C.c_int
 lib.tjm_selftest_copy.argtypes = [C.c_long, C.c_int, _dp]
 lib.tjm_selftest_copy.restype = C.c_int
+lib.tjm_server_create.argtypes = [C.POINTER(_vp), C.c_int, C.c_size_t]
+lib.tjm_server_create.restype = C.c_int
+lib.tjm_submit.argtypes = [_vp, _vp, C.POINTER(RunArgs), C.POINTER(C.c_uint64)]
+lib.tjm_submit.restype = C.c_int
+lib.tjm_poll.argtypes = [_vp, C.c_uint64, _ip]
+lib.tjm_poll.restype = C.c_int
+lib.tjm_wait.argtypes = [_vp, C.c_uint64, _dp, _dp, C.POINTER(JobReport)]
+lib.tjm_wait.restype = C.c_int
+lib.tjm_server_last_error.argtypes = []
+lib.tjm_server_last_error.restype = C.c_char_p
+lib.tjm_server_destroy.argtypes = [_vp]
+lib.tjm_server_destroy.restype = None
 
 
 class TjmError(RuntimeError):
@@ -236,6 +267,56 @@ class Model:
         s = Stats()
         self._check(lib.tjm_get_stats(self.h, C.byref(s)))
         return s.as_dict()
+
+
+class Server:
+    """Serving front end (tjm_server_create / tjm_submit / tjm_poll / tjm_wait)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        h = _vp()
+        self._sc(lib.tjm_server_create(C.byref(h), int(device), C.c_size_t(int(hbm_budget_bytes))))
+        self.h = h
+        self._jobs = {}
+
+    @staticmethod
+    def _sc(st):
+        if st != OK:
+            raise TjmError(st, lib.tjm_server_last_error().decode())
+
+    def submit(self, model, n_traj, dt, T, chi_max, observables, seed, options=None):
+        """Queues one run of `model`; returns the job id."""
+        sites, ops = Model._obs(observables)
+        opsd = ops.view(np.float64)
+        a = RunArgs(n_traj=n_traj, dt=dt, T=T, chi_max=chi_max, n_obs=len(observables),
+                    obs_site=_iptr(sites), obs_op=opsd.ctypes.data_as(_dp), seed=seed,
+                    opt=C.pointer(options) if options is not None else None)
+        job = C.c_uint64()
+        self._sc(lib.tjm_submit(self.h, model.h, C.byref(a), C.byref(job)))
+        n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
+        self._jobs[job.value] = (n, len(observables))
+        return job.value
+
+    def poll(self, job):
+        done = C.c_int()
+        self._sc(lib.tjm_poll(self.h, C.c_uint64(job), C.byref(done)))
+        return bool(done.value)
+
+    def wait(self, job):
+        """Blocks until the job ends; returns dict with mean, sem and report."""
+        n, no = self._jobs.pop(job, (0, 0))
+        mean = np.zeros((n + 1, no))
+        sem = np.zeros((n + 1, no))
+        rep = JobReport()
+        self._sc(lib.tjm_wait(self.h, C.c_uint64(job), _dptr(mean), _dptr(sem), C.byref(rep)))
+        return {"mean": mean, "sem": sem, "report": rep.as_dict()}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tjm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 # ---------------------------------------------------------------------------

@@ -45,3 +45,27 @@ def small_cases():
         (12, 6, "neel", 10, 8, 0.5, 0.1),
         (13, 5, "zero", 8, 8, 0.9, 0.3),
     ]
+
+
+def serving_stream(K, seed=5):
+    """The serving stream: K requests arriving as a Poisson process of mean
+    inter-arrival 0.05 s, each an independent job on the XXX chain (J = 1)
+    with L ~ U{20..200}, chi_max in {16, 32, 64}, one rate gamma ~ U[0.01,
+    0.2] for both jump channels, field g ~ U[0, 1], N ~ U{64..512}
+    trajectories, dt = 0.1, T ~ U[1, 5] rounded to a multiple of dt, Neel
+    initial state.  Returns a list of dicts with arrival time t (s)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(K):
+        t += rng.exponential(0.05)
+        L = int(rng.integers(20, 201))
+        chi = int(rng.choice([16, 32, 64]))
+        gamma = float(rng.uniform(0.01, 0.2))
+        g = float(rng.uniform(0.0, 1.0))
+        N = int(rng.integers(64, 513))
+        n = max(1, int(round(rng.uniform(1.0, 5.0) / 0.1)))
+        out.append(dict(t=t, L=L, chi_max=chi, gamma=gamma, g=g, n_traj=N, dt=0.1, n_steps=n,
+                        T=n * 0.1, seed=SEED + 1000 + i))
+    return out

@@ -187,3 +187,26 @@ def test_package_mpo_matches_oracle_hamiltonian():
             assert np.abs(H - om.xxx_dense(L, J, hx, hz)).max() < 1e-13
     H = om.mpo_to_dense(models.tfim_mpo(3, 1.0, 0.7))
     assert np.abs(H - om.tfim_dense(3, 1.0, 0.7)).max() < 1e-13
+
+
+def test_server_calls_reject_null_arguments():
+    """The serving entry points validate their pointers before any device
+    work."""
+    job = C.c_uint64()
+    assert tjm.lib.tjm_server_create(None, 0, 0) == tjm.E_INVAL
+    assert tjm.lib.tjm_submit(None, None, None, C.byref(job)) == tjm.E_INVAL
+    assert tjm.lib.tjm_server_last_error().decode() == "NULL argument"
+    done = C.c_int()
+    assert tjm.lib.tjm_poll(None, 1, C.byref(done)) == tjm.E_INVAL
+    assert tjm.lib.tjm_wait(None, 1, None, None, None) == tjm.E_INVAL
+    tjm.lib.tjm_server_destroy(None)
+    h = C.c_void_p()
+    assert tjm.lib.tjm_server_create(C.byref(h), -1, 0) in (tjm.E_INVAL, tjm.E_DEVICE)
+    assert not h.value
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_server_without_gpu_reports_device_error():
+    with pytest.raises(tjm.TjmError) as e:
+        tjm.Server(0)
+    assert e.value.status == tjm.E_DEVICE

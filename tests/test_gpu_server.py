@@ -1,0 +1,146 @@
+"""The serving front end (tjm_server_create / tjm_submit / tjm_poll /
+tjm_wait) through the C ABI: jobs of different models, sizes and precisions
+run concurrently on one GPU and return exactly what tjm_run returns for the
+same arguments; a small FP64 job also matches the CPU oracle trajectory by
+trajectory.  Admission: a budget that holds one job at a time still runs
+every job, in submission order; a job above the budget is refused."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2501_17913_amd import models, tjm  # noqa: E402
+from oracle import model as om, mps_tjm  # noqa: E402
+from tests import inputs  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _model(L, g, gamma, init="neel"):
+    mpo, s, o, r = models.xxx_model(L, 1.0, g, gamma)
+    m = tjm.Model(L, mpo, s, o, r)
+    m.set_initial_product(models.product_state(inputs.init_bits(L, init)))
+    return m
+
+
+JOBS = [  # (L, chi_max, n_traj, steps, g, gamma, precision, seed)
+    (6, 8, 40, 6, 0.5, 0.1, tjm.PREC_FP64, inputs.SEED + 81),
+    (12, 16, 300, 4, 0.3, 0.05, tjm.PREC_MIXED, inputs.SEED + 82),
+    (5, 4, 16, 8, 0.6, 0.1, tjm.PREC_FP64, inputs.SEED + 83),
+    (20, 16, 700, 3, 0.8, 0.2, tjm.PREC_MIXED, inputs.SEED + 84),
+    (8, 8, 64, 5, 0.5, 0.1, tjm.PREC_MIXED, inputs.SEED + 85),
+]
+
+
+def _submit_all(srv, jobs):
+    ids = []
+    for (L, chi, N, n, g, gamma, prec, seed) in jobs:
+        m = _model(L, g, gamma)
+        ids.append(srv.submit(m, N, 0.1, n * 0.1, chi, models.zx_observables(L), seed,
+                              tjm.default_options(precision=prec)))
+        m.close()            # the server holds its own copy of the model
+    return ids
+
+
+def _direct(job):
+    (L, chi, N, n, g, gamma, prec, seed) = job
+    m = _model(L, g, gamma)
+    out = m.run(N, 0.1, n * 0.1, chi, models.zx_observables(L), seed, tjm.default_options(precision=prec))
+    m.close()
+    return out
+
+
+def test_server_jobs_equal_direct_runs():
+    log("server: %d concurrent jobs" % len(JOBS))
+    srv = tjm.Server(0)
+    ids = _submit_all(srv, JOBS)
+    res = {}
+    for i in reversed(range(len(ids))):        # collected out of order
+        res[i] = srv.wait(ids[i])
+        with pytest.raises(tjm.TjmError) as e:   # released once collected
+            srv.poll(ids[i])
+        assert e.value.status == tjm.E_INVAL
+    srv.close()
+    for i, job in enumerate(JOBS):
+        ref = _direct(job)
+        r = res[i]
+        log("job", i, job[:4], "latency %.3f s" % r["report"]["latency_s"])
+        assert r["mean"].shape == ref["mean"].shape
+        assert np.array_equal(r["mean"], ref["mean"]) and np.array_equal(r["sem"], ref["sem"])
+        rep = r["report"]
+        assert rep["n_traj"] == job[2] and rep["n_steps"] == job[3]
+        assert 0.0 <= rep["queue_s"] <= rep["latency_s"] and rep["run_s"] > 0.0
+        assert rep["stats"]["steps_done"] == job[3] and rep["stats"]["failed_traj"] == 0
+        assert rep["device_bytes"] >= rep["stats"]["device_bytes"]
+
+
+def test_server_small_fp64_job_matches_oracle():
+    L, chi, N, n, g, gamma, _, seed = JOBS[2]
+    srv = tjm.Server(0)
+    job = srv.submit(_model(L, g, gamma), N, 0.1, n * 0.1, chi, models.zx_observables(L), seed,
+                     tjm.default_options())
+    out = srv.wait(job)
+    srv.close()
+    Ws = om.xxx_mpo(L, 1.0, g)
+    jumps = om.relax_dephase_jumps(L, gamma, gamma)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    sv = om.product_site_vectors(L, inputs.init_bits(L, "neel"))
+    per = np.array([mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, n, obs, seed, t,
+                                           mps_tjm.Options(chi_max=chi)) for t in range(N)])
+    assert np.abs(out["mean"] - per.mean(axis=0)).max() < 1e-10
+    sem = per.std(axis=0, ddof=1) / np.sqrt(N)
+    assert np.abs(out["sem"] - sem).max() < 1e-10
+
+
+def test_server_budget_admits_one_job_at_a_time():
+    jobs = JOBS[:3]
+    sizes = []
+    srv = tjm.Server(0)
+    for job in jobs:       # learn each job's footprint from a first pass
+        sizes.append(srv.wait(_submit_all(srv, [job])[0])["report"]["device_bytes"])
+    srv.close()
+    budget = max(sizes) + min(sizes) // 2      # never room for two jobs at once
+    srv = tjm.Server(0, budget)
+    ids = _submit_all(srv, jobs)
+    reps = [srv.wait(j) for j in ids]
+    srv.close()
+    for job, r in zip(jobs, reps):
+        assert np.array_equal(r["mean"], _direct(job)["mean"])
+    t = [(r["report"]["start_s"], r["report"]["end_s"]) for r in reps]
+    # first come, first served and no overlap: each starts after the previous ended
+    for a, b in zip(t, t[1:]):
+        assert b[0] >= a[1]
+    # a job above the whole budget is refused at submission
+    srv = tjm.Server(0, min(sizes) // 4)
+    with pytest.raises(tjm.TjmError) as e:
+        _submit_all(srv, [jobs[0]])
+    assert e.value.status == tjm.E_NOMEM
+    srv.close()
+
+
+def test_server_rejects_bad_jobs_and_reports_failures():
+    srv = tjm.Server(0)
+    m = _model(6, 0.5, 0.1)
+    with pytest.raises(tjm.TjmError) as e:
+        srv.submit(m, 4, 0.1, 0.25, 8, models.zx_observables(6), 1)      # T/dt not an integer
+    assert e.value.status == tjm.E_INVAL
+    with pytest.raises(tjm.TjmError) as e:
+        srv.submit(m, 4, 0.1, 0.2, 8, models.zx_observables(6), 1, tjm.default_options(chi_cap=128))
+    assert e.value.status == tjm.E_UNSUPPORTED
+    with pytest.raises(tjm.TjmError) as e:
+        srv.wait(12345)
+    assert e.value.status == tjm.E_INVAL
+    job = srv.submit(m, 4, 0.1, 0.2, 8, models.zx_observables(6), 1)
+    while not srv.poll(job):
+        pass
+    assert srv.wait(job)["report"]["n_steps"] == 2
+    # jobs still queued or uncollected at shutdown are released with the server
+    for _ in range(3):
+        srv.submit(m, 64, 0.1, 0.3, 8, models.zx_observables(6), 2)
+    srv.close()
+    m.close()
