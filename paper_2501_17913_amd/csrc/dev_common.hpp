@@ -79,6 +79,23 @@ TJM_DEV double grp_sum(double v, int g) {
   return v;
 }
 
+// The same for two and four values at once: the shuffles of one butterfly
+// step are issued together and wait once.
+TJM_DEV void grp_sum2(double& a, double& b, int g) {
+  for (int m = g / 2; m > 0; m >>= 1) {
+    const double ta = tjm_shfl_xor(a, m), tb = tjm_shfl_xor(b, m);
+    a += ta; b += tb;
+  }
+}
+
+TJM_DEV void grp_sum4(double& a, double& b, double& c, double& d, int g) {
+  for (int m = g / 2; m > 0; m >>= 1) {
+    const double ta = tjm_shfl_xor(a, m), tb = tjm_shfl_xor(b, m);
+    const double tc = tjm_shfl_xor(c, m), td = tjm_shfl_xor(d, m);
+    a += ta; b += tb; c += tc; d += td;
+  }
+}
+
 // --------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
 // (c0,c1,c2,c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),

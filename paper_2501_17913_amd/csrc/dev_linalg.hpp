@@ -36,7 +36,10 @@ struct QrLds {
   double a2next;                        // ||column j+1, rows j+1..||^2
 };
 
-TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) {
+// The elimination: on return X holds the reflectors below the diagonal with
+// their heads v0 on it, the rest of R above it; H holds beta_j (the
+// diagonal of R) and ||v_j||^2.
+TJM_DEV void qr_reduce(int m, int n, zd* X, QrLds& H, BlkScratch& S) {
   const int k = m < n ? m : n;
   const int tid = tjm_tid();
   const int ngrp = TJM_NT / QR_TPC;
@@ -73,7 +76,8 @@ TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) 
         sr += p.re; si += p.im;
       }
       if (vn > 0.0) {
-        const zd sc = cmk(f * grp_sum(sr, QR_TPC), f * grp_sum(si, QR_TPC));
+        grp_sum2(sr, si, QR_TPC);
+        const zd sc = cmk(f * sr, f * si);
 #pragma unroll
         for (int t = 0; t < QR_RPT; ++t) {
           const int i = gl + QR_TPC * t;
@@ -97,6 +101,14 @@ TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) 
     if (tid == 0) X[(long)j * n + j] = v0;        // reflector head, for Q
     tjm_sync();
   }
+}
+
+TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) {
+  const int k = m < n ? m : n;
+  const int tid = tjm_tid();
+  const int ngrp = TJM_NT / QR_TPC;
+  const int g = tid / QR_TPC, gl = tid % QR_TPC;
+  qr_reduce(m, n, X, H, S);
   // R (upper triangle of X, diagonal beta), then the gauge fix
   for (int e = tid; e < k * n; e += TJM_NT) {
     int i = e / n, c = e % n;
@@ -128,7 +140,8 @@ TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) 
         const zd p = cdotc(i < mr ? H.v[i] : cmk(0.0, 0.0), x[t]);
         sr += p.re; si += p.im;
       }
-      const zd sc = cmk(f * grp_sum(sr, QR_TPC), f * grp_sum(si, QR_TPC));
+      grp_sum2(sr, si, QR_TPC);
+      const zd sc = cmk(f * sr, f * si);
 #pragma unroll
       for (int t = 0; t < QR_RPT; ++t) {
         const int i = gl + QR_TPC * t;
@@ -193,6 +206,7 @@ TJM_DEV int trunc_rank(F s, int n, double discard, int cap, double deg_tol) {
 // nc <= 128.
 // --------------------------------------------------------------------------
 constexpr int SVD_LDS_BYTES = 64 * 64 * 16;   // a working matrix of up to 4096 complex doubles
+static_assert(sizeof(QrLds) <= SVD_LDS_BYTES, "the preconditioning QR keeps its reflector in the SVD's LDS");
 
 struct SvdLds {
   double s[128];
@@ -202,20 +216,139 @@ struct SvdLds {
   unsigned long long offmax;   // bits of the largest |w_a^H w_b| / (|w_a| |w_b|) of a sweep
 };
 
+// Round-robin pairing of np (even) players: in round rnd, pair pr meets
+// players a < b; over np - 1 rounds every pair meets once.
+TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
+  if (pr == 0) { a = rnd; b = np - 1; }
+  else { a = (rnd + pr) % (np - 1); b = (rnd - pr + (np - 1)) % (np - 1); }
+  if (a > b) { const int t = a; a = b; b = t; }
+}
+
+// One cyclic sweep of one-sided Jacobi rotations over the ncol columns of W
+// (column-major, p rows, global memory or LDS): every pair once, the pairs
+// of a round in parallel, one thread group per pair.  A pair whose columns
+// are not orthogonal to tol is rotated to orthogonality (complex Jacobi
+// rotation of the 2 x 2 Gram matrix); columns of weight below zero2 are left
+// alone.  SL.rotated records a rotation, SL.offmax the largest relative
+// off-diagonal |w_a^H w_b| / (|w_a| |w_b|) measured.  Ends with a barrier.
+constexpr int JAC_RPT = 8;           // rows per thread a pair keeps in registers
+
+TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, double zero2, double tol, SvdLds& SL) {
+  const int tid = tjm_tid();
+  const int np = (ncol + 1) & ~1;        // players, a dummy if ncol is odd
+  const int npair = np / 2;
+  // as many pairs at once as the workgroup holds, but enough threads per
+  // pair that each keeps at most JAC_RPT rows of the two columns
+  // (a group lies within one wavefront: its sums are lane shuffles)
+  int tpp = TJM_WAVE < 64 ? TJM_WAVE : 64;
+  while (tpp > 1 && tpp * npair > TJM_NT) tpp >>= 1;
+  while (tpp < 64 && tpp < TJM_WAVE && tpp < TJM_NT && tpp * JAC_RPT < p) tpp <<= 1;
+  const int span = JAC_RPT * tpp;         // rows one pass over the registers covers
+  const int ngrp = TJM_NT / tpp;
+  const int g = tid / tpp, gl = tid % tpp;
+  for (int rnd = 0; rnd < np - 1; ++rnd) {
+    for (int pr = g; pr < npair; pr += ngrp) {
+      int a, b;
+      rr_pair(np, rnd, pr, a, b);
+      if (b >= ncol) continue;
+      zd* wa = W + (long)a * p;
+      zd* wb = W + (long)b * p;
+      // rows r0 + gl + tpp t of both columns, in registers; one pass when
+      // p <= span, and then the rotation reuses them
+      zd x[JAC_RPT], y[JAC_RPT];
+      double aa = 0.0, bb = 0.0, cr = 0.0, ci = 0.0;
+      for (int r0 = 0; r0 < p; r0 += span) {
+#pragma unroll
+        for (int t = 0; t < JAC_RPT; ++t) {
+          const int r = r0 + gl + tpp * t;
+          x[t] = r < p ? wa[r] : cmk(0.0, 0.0);
+          y[t] = r < p ? wb[r] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < JAC_RPT; ++t) {
+          aa += abs2(x[t]); bb += abs2(y[t]);
+          const zd c = cdotc(x[t], y[t]);
+          cr += c.re; ci += c.im;
+        }
+      }
+      grp_sum4(aa, bb, cr, ci, tpp);
+      const double ac = hypot(cr, ci);
+      if (!(aa > zero2 && bb > zero2)) continue;
+      const double sab = sqrt(aa) * sqrt(bb);     // no overflow for large norms
+      if (gl == 0) {
+        const double rel = ac / sab;              // >= 0: its bits order like the value
+        atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1.0));
+      }
+      if (ac > tol * sab) {
+        const double inv = 1.0 / ac;
+        const double zeta = 0.5 * (bb - aa) * inv;
+        const double az = fabs(zeta);
+        double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
+        if (zeta < 0.0) t = -t;
+        const double cs = rsqrt(1.0 + t * t), sn = cs * t;
+        const zd eph = cmk(cr * inv, -ci * inv);  // conj(c)/|c|
+        for (int r0 = 0; r0 < p; r0 += span) {
+          if (p > span) {
+#pragma unroll
+            for (int t = 0; t < JAC_RPT; ++t) {
+              const int r = r0 + gl + tpp * t;
+              x[t] = r < p ? wa[r] : cmk(0.0, 0.0);
+              y[t] = r < p ? wb[r] : cmk(0.0, 0.0);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < JAC_RPT; ++q) {
+            const int r = r0 + gl + tpp * q;
+            if (r < p) {
+              const zd yy = eph * y[q];
+              wa[r] = cs * x[q] - sn * yy;
+              wb[r] = sn * x[q] + cs * yy;
+            }
+          }
+        }
+        if (gl == 0) atomicOr(&SL.rotated, 1);
+      }
+    }
+    tjm_sync();
+  }
+}
+
 TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
                     double discard, int cap, double deg_tol,
                     zd* Wc, zd* Uc, zd* Tg, SvdLds& SL, BlkScratch& S, void* glds) {
   const int tid = tjm_tid();
   const bool tr = absorb_left;           // rotate the columns of G^H (-> V)
   const int p = tr ? n : m;              // rows of the working matrix
-  const int nc = tr ? m : n;             // columns of the working matrix
+  // Preconditioning: the rotated matrix is R^H from a Householder QR of
+  // G (tr) or of G^H, X = Q R.  It has the Gram matrix R^H R = X^H X of the
+  // matrix it replaces, hence the same singular values and rotated-side
+  // singular vectors, only r = min(m, n) columns, and a graded,
+  // near-triangular form on which the sweeps converge in far fewer rounds
+  // than on G itself when the spectrum decays (Drmac and Veselic, SIAM J.
+  // Matrix Anal. Appl. 29 (2008)).
+  const int xr = tr ? m : n;             // rows of X (columns of X = p)
+  const bool pre = xr <= QR_MROWS;
+  const int nc = pre ? (m < n ? m : n) : (tr ? m : n);   // columns of the working matrix
   // the working matrix is rotated in LDS (glds, SVD_LDS_BYTES) when it fits,
   // else in the global array Wc; glds is free until the final product
-  if ((long)p * nc * 16 <= SVD_LDS_BYTES) Wc = (zd*)glds;
   double f2 = 0.0;
+  if (pre) {
+    for (int e = tid; e < xr * p; e += TJM_NT) {
+      const int i = e / p, c = e % p;    // X[i][c]
+      Tg[e] = tr ? G[(long)i * n + c] : conjg(G[(long)c * n + i]);
+    }
+    tjm_sync();
+    QrLds& H = *(QrLds*)glds;
+    qr_reduce(xr, p, Tg, H, S);
+    for (int j = tid; j < nc; j += TJM_NT) Tg[(long)j * p + j] = cmk(H.bre[j], H.bim[j]);
+    tjm_sync();                          // H (in glds) is dead from here
+  }
+  if ((long)p * nc * 16 <= SVD_LDS_BYTES) Wc = (zd*)glds;
   for (int e = tid; e < p * nc; e += TJM_NT) {
     int c = e / p, r = e % p;            // Wc[c][r] = Gw[r][c]
-    zd x = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
+    zd x;
+    if (pre) x = r < c ? cmk(0.0, 0.0) : conjg(Tg[(long)c * p + r]);   // (R^H)[r][c]
+    else x = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
     Wc[e] = x;
     f2 += abs2(x);
   }
@@ -223,62 +356,48 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   // below any truncation threshold: they are not rotated (rotating them only
   // stirs rounding noise and never converges)
   const double zero2 = 1e-28 * blk_sum(f2, S);
-  const int np = (nc + 1) & ~1;          // players, a dummy if nc is odd
-  const int npair = np / 2;
-  int tpp = 64;
-  while (tpp > 1 && tpp * npair > TJM_NT) tpp >>= 1;
-  const int ngrp = TJM_NT / tpp;
-  const int g = tid / tpp, gl = tid % tpp;
   const double tol = 2.220446049250313e-16 * sqrt((double)p);
   // convergence is quadratic: a sweep that started with every relative
   // off-diagonal below 1e-3 sqrt(tol) leaves them far below tol, so no
   // further sweep is needed to confirm it
   const double quad = 1e-3 * sqrt(tol);
-  for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
+  // A working matrix too large for LDS is swept in column blocks: two blocks
+  // of bw columns at a time are staged in LDS and every pair among their
+  // columns is rotated there, the block pairs following the same round-robin
+  // as single columns (block one-sided Jacobi).  Each sweep then reads and
+  // writes the matrix nb - 1 times instead of once per column pair.
+  const bool in_lds = (long)p * nc * 16 <= SVD_LDS_BYTES;
+  const int bw = in_lds ? nc : SVD_LDS_BYTES / (32 * p);
+  const bool blocked = !in_lds && bw >= 2;
+  const int nb = blocked ? (nc + bw - 1) / bw : 1;
+  const int nbp = (nb + 1) & ~1;
+  zd* Lc = (zd*)glds;
+  for (int sweep = 0; sweep < 40 && nc >= 2; ++sweep) {
     if (tid == 0) { SL.rotated = 0; SL.offmax = 0ull; }
     tjm_sync();
-    for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int pr = g; pr < npair; pr += ngrp) {
-        int a, b;
-        if (pr == 0) { a = rnd; b = np - 1; }
-        else { a = (rnd + pr) % (np - 1); b = (rnd - pr + (np - 1)) % (np - 1); }
-        if (a > b) { int t = a; a = b; b = t; }
-        if (b >= nc) continue;
-        zd* wa = Wc + (long)a * p;
-        zd* wb = Wc + (long)b * p;
-        double aa = 0.0, bb = 0.0, cr = 0.0, ci = 0.0;
-        for (int r = gl; r < p; r += tpp) {
-          zd x = wa[r], y = wb[r];
-          aa += abs2(x); bb += abs2(y);
-          zd c = cdotc(x, y);
-          cr += c.re; ci += c.im;
-        }
-        aa = grp_sum(aa, tpp); bb = grp_sum(bb, tpp);
-        cr = grp_sum(cr, tpp); ci = grp_sum(ci, tpp);
-        const double ac = hypot(cr, ci);
-        if (!(aa > zero2 && bb > zero2)) continue;
-        const double sab = sqrt(aa) * sqrt(bb);     // no overflow for large norms
-        if (gl == 0) {
-          const double rel = ac / sab;              // >= 0: its bits order like the value
-          atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1.0));
-        }
-        if (ac > tol * sab) {
-          const double inv = 1.0 / ac;
-          const double zeta = 0.5 * (bb - aa) * inv;
-          const double az = fabs(zeta);
-          double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
-          if (zeta < 0.0) t = -t;
-          const double cs = rsqrt(1.0 + t * t), sn = cs * t;
-          const zd eph = cmk(cr * inv, -ci * inv);  // conj(c)/|c|
-          for (int r = gl; r < p; r += tpp) {
-            zd x = wa[r], y = eph * wb[r];
-            wa[r] = cs * x - sn * y;
-            wb[r] = sn * x + cs * y;
+    if (!blocked) {
+      jacobi_sweep(Wc, p, nc, zero2, tol, SL);
+    } else {
+      for (int rnd = 0; rnd < nbp - 1; ++rnd)
+        for (int pr = 0; pr < nbp / 2; ++pr) {
+          int I, J;
+          rr_pair(nbp, rnd, pr, I, J);
+          if (J >= nb) continue;
+          const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
+          const int c1 = J * bw, cJ = nc - c1 < bw ? nc - c1 : bw;
+          const int ncl = cI + cJ;
+          for (int e = tid; e < ncl * p; e += TJM_NT) {
+            const int c = e / p, r = e % p;
+            Lc[e] = Wc[(long)(c < cI ? c0 + c : c1 + c - cI) * p + r];
           }
-          if (gl == 0) atomicOr(&SL.rotated, 1);
+          tjm_sync();
+          jacobi_sweep(Lc, p, ncl, zero2, tol, SL);
+          for (int e = tid; e < ncl * p; e += TJM_NT) {
+            const int c = e / p, r = e % p;
+            Wc[(long)(c < cI ? c0 + c : c1 + c - cI) * p + r] = Lc[e];
+          }
+          tjm_sync();
         }
-      }
-      tjm_sync();
     }
     if (SL.rotated == 0 || __longlong_as_double((long long)SL.offmax) < quad) break;
     tjm_sync();
