@@ -83,6 +83,11 @@ def _svd_cases():
     for (m, n, r) in [(8, 6, 6), (6, 8, 6), (12, 8, 4), (128, 128, 128), (128, 64, 64), (64, 128, 40), (1, 5, 1)]:
         cases.append(("random", m, n, r))
     cases += [("zero_rows", 8, 6, 0), ("zero_cols", 6, 8, 0), ("graded", 20, 20, 0), ("degenerate", 16, 16, 0)]
+    # working matrices above 64x64 swept in column blocks: ragged last blocks
+    # (72 = 4 x 16 + 8 columns), a dummy block (100 columns in blocks of 20),
+    # and the exponentially decaying spectra of MPS bonds
+    cases += [("random", 128, 72, 72), ("random", 100, 128, 100), ("expdecay", 128, 128, 0),
+              ("expdecay", 100, 128, 0)]
     return cases
 
 
@@ -101,6 +106,11 @@ def test_svd(kind, m, n, r, absorb):
         U0, _ = np.linalg.qr(cr(m, m))
         V0, _ = np.linalg.qr(cr(n, n))
         G = (U0 * np.logspace(0, -10, m)) @ V0.conj().T
+    elif kind == "expdecay":
+        k0 = min(m, n)
+        U0, _ = np.linalg.qr(cr(m, k0))
+        V0, _ = np.linalg.qr(cr(n, k0))
+        G = (U0 * np.exp(-np.arange(k0) / 6.0)) @ V0.conj().T
     else:
         U0, _ = np.linalg.qr(cr(m, m))
         V0, _ = np.linalg.qr(cr(n, n))
