@@ -210,3 +210,18 @@ def test_server_without_gpu_reports_device_error():
     with pytest.raises(tjm.TjmError) as e:
         tjm.Server(0)
     assert e.value.status == tjm.E_DEVICE
+
+
+def test_serving_stream_recipe():
+    """The serving stream's requests follow the stated recipe and are
+    reproducible: every parameter in range, T an exact multiple of dt."""
+    from tests import inputs
+    a = inputs.serving_stream(200)
+    assert a == inputs.serving_stream(200)
+    t = np.array([q["t"] for q in a])
+    assert np.all(np.diff(t) > 0) and 0.03 < t[-1] / len(a) < 0.07
+    for q in a:
+        assert 20 <= q["L"] <= 200 and q["chi_max"] in (16, 32, 64) and 64 <= q["n_traj"] <= 512
+        assert 0.01 <= q["gamma"] <= 0.2 and 0.0 <= q["g"] <= 1.0
+        assert 10 <= q["n_steps"] <= 50 and abs(q["T"] / q["dt"] - q["n_steps"]) < 1e-9
+    assert len({q["seed"] for q in a}) == len(a)
