@@ -226,17 +226,22 @@ TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
 
 // One cyclic sweep of one-sided Jacobi rotations over the ncol columns of W
 // (column-major, p rows, global memory or LDS): every pair once, the pairs
-// of a round in parallel, one thread group per pair.  A pair whose columns
+// of a round in parallel, one thread group per pair.  With n1 > 0 only the
+// pairs between the first n1 columns and the others are visited: in round
+// r, column i meets column n1 + (i + r) mod max(n1, ncol - n1).  A pair whose columns
 // are not orthogonal to tol is rotated to orthogonality (complex Jacobi
 // rotation of the 2 x 2 Gram matrix); columns of weight below zero2 are left
 // alone.  SL.rotated records a rotation, SL.offmax the largest relative
 // off-diagonal |w_a^H w_b| / (|w_a| |w_b|) measured.  Ends with a barrier.
 constexpr int JAC_RPT = 8;           // rows per thread a pair keeps in registers
 
-TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, double zero2, double tol, SvdLds& SL) {
+TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double tol, SvdLds& SL) {
   const int tid = tjm_tid();
   const int np = (ncol + 1) & ~1;        // players, a dummy if ncol is odd
-  const int npair = np / 2;
+  const int n2 = ncol - n1;
+  const int mx = n1 > n2 ? n1 : n2;
+  const int npair = n1 > 0 ? mx : np / 2;
+  const int nrnd = n1 > 0 ? mx : np - 1;
   // as many pairs at once as the workgroup holds, but enough threads per
   // pair that each keeps at most JAC_RPT rows of the two columns
   // (a group lies within one wavefront: its sums are lane shuffles)
@@ -246,11 +251,17 @@ TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, double zero2, double tol, Sv
   const int span = JAC_RPT * tpp;         // rows one pass over the registers covers
   const int ngrp = TJM_NT / tpp;
   const int g = tid / tpp, gl = tid % tpp;
-  for (int rnd = 0; rnd < np - 1; ++rnd) {
+  for (int rnd = 0; rnd < nrnd; ++rnd) {
     for (int pr = g; pr < npair; pr += ngrp) {
       int a, b;
-      rr_pair(np, rnd, pr, a, b);
-      if (b >= ncol) continue;
+      if (n1 > 0) {
+        const int j = (pr + rnd) % mx;
+        if (pr >= n1 || j >= n2) continue;
+        a = pr; b = n1 + j;
+      } else {
+        rr_pair(np, rnd, pr, a, b);
+        if (b >= ncol) continue;
+      }
       zd* wa = W + (long)a * p;
       zd* wb = W + (long)b * p;
       // rows r0 + gl + tpp t of both columns, in registers; one pass when
@@ -361,11 +372,12 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
   // off-diagonal below 1e-3 sqrt(tol) leaves them far below tol, so no
   // further sweep is needed to confirm it
   const double quad = 1e-3 * sqrt(tol);
-  // A working matrix too large for LDS is swept in column blocks: two blocks
-  // of bw columns at a time are staged in LDS and every pair among their
-  // columns is rotated there, the block pairs following the same round-robin
-  // as single columns (block one-sided Jacobi).  Each sweep then reads and
-  // writes the matrix nb - 1 times instead of once per column pair.
+  // A working matrix too large for LDS is swept in column blocks of bw
+  // columns (block one-sided Jacobi): each block is staged in LDS alone for
+  // the pairs within it, then two blocks at a time, the block pairs in the
+  // same round-robin as single columns, for the pairs across them.  Every
+  // column pair is visited once per sweep, and the matrix is read and
+  // written nb times per sweep instead of once per column pair.
   const bool in_lds = (long)p * nc * 16 <= SVD_LDS_BYTES;
   const int bw = in_lds ? nc : SVD_LDS_BYTES / (32 * p);
   const bool blocked = !in_lds && bw >= 2;
@@ -376,8 +388,23 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
     if (tid == 0) { SL.rotated = 0; SL.offmax = 0ull; }
     tjm_sync();
     if (!blocked) {
-      jacobi_sweep(Wc, p, nc, zero2, tol, SL);
+      jacobi_sweep(Wc, p, nc, 0, zero2, tol, SL);
     } else {
+      // stage columns [c0, c0 + cI) and [c1, c1 + cJ) in Lc, or write them back
+      auto move = [&](bool in, int c0, int cI, int c1, int cJ) {
+        for (int e = tid; e < (cI + cJ) * p; e += TJM_NT) {
+          const int c = e / p, r = e % p;
+          zd* w = Wc + (long)(c < cI ? c0 + c : c1 + c - cI) * p + r;
+          if (in) Lc[e] = *w; else *w = Lc[e];
+        }
+        tjm_sync();
+      };
+      for (int I = 0; I < nb; ++I) {
+        const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
+        move(true, c0, cI, 0, 0);
+        jacobi_sweep(Lc, p, cI, 0, zero2, tol, SL);
+        move(false, c0, cI, 0, 0);
+      }
       for (int rnd = 0; rnd < nbp - 1; ++rnd)
         for (int pr = 0; pr < nbp / 2; ++pr) {
           int I, J;
@@ -385,18 +412,9 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
           if (J >= nb) continue;
           const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
           const int c1 = J * bw, cJ = nc - c1 < bw ? nc - c1 : bw;
-          const int ncl = cI + cJ;
-          for (int e = tid; e < ncl * p; e += TJM_NT) {
-            const int c = e / p, r = e % p;
-            Lc[e] = Wc[(long)(c < cI ? c0 + c : c1 + c - cI) * p + r];
-          }
-          tjm_sync();
-          jacobi_sweep(Lc, p, ncl, zero2, tol, SL);
-          for (int e = tid; e < ncl * p; e += TJM_NT) {
-            const int c = e / p, r = e % p;
-            Wc[(long)(c < cI ? c0 + c : c1 + c - cI) * p + r] = Lc[e];
-          }
-          tjm_sync();
+          move(true, c0, cI, c1, cJ);
+          jacobi_sweep(Lc, p, cI + cJ, cI, zero2, tol, SL);
+          move(false, c0, cI, c1, cJ);
         }
     }
     if (SL.rotated == 0 || __longlong_as_double((long long)SL.offmax) < quad) break;
