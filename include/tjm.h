@@ -85,17 +85,11 @@ typedef struct {
                              other gauge), SVD otherwise; 0 = SVD at every
                              bond; < 0 (default) = 1 for TJM_PREC_MIXED and 0
                              for TJM_PREC_FP64                                */
-  int sweep_jumps;        /* 1 (default): run the jump process with the
-                             sweeps in the printed order (QR sweep for delta p,
-                             LQ sweep for the weights, QR moves to the jump
-                             site); 0: take delta p, the weights and sampled
-                             observables from FP64 transfer-matrix
-                             environments and factorise only where the state
-                             must be canonical (same decisions, bond
-                             dimensions and states up to rounding; the sweep
-                             order is used anyway where a bond violates
-                             b_{l+1} <= d b_l or b_l <= d b_{l+1}).  0 is
-                             experimental: not validated on the device       */
+  int sweep_jumps;        /* must be 1 (the default): the jump process runs
+                             its sweeps in the printed order (QR sweep for
+                             delta p, LQ sweep for the weights, QR moves to
+                             the jump site); any other value is rejected
+                             with TJM_E_UNSUPPORTED                           */
 } tjm_options;
 
 typedef struct {
@@ -111,15 +105,14 @@ typedef struct {
   size_t device_bytes;            /* device memory held by the run            */
   /* workgroup-seconds summed over trajectories, by phase: [0] whole step
    * functions, [1] contractions (effective Hamiltonians, environments),
-   * [2] transfer-matrix environment sweeps of the jump process, [3] SVDs,
+   * [2] unused (0), [3] SVDs,
    * [4] QR/LQ, [5] Lanczos exponentials including their contractions,
    * [6] bond-matrix absorption and two-site products, [7] unused            */
   double phase_s[8];
   int failed_traj;                /* trajectories flagged with a non-finite
                                      norm so far (tjm_run_end then returns
                                      TJM_E_NUMERIC)                           */
-  unsigned long long cmac_env;    /* complex MACs of the jump-process
-                                     environment sweeps (FP64 matrix cores)   */
+  unsigned long long cmac_env;    /* unused (0)                               */
 } tjm_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -30,11 +30,15 @@ def build(verbose=False):
     """Compile every HIP source and link libtjm.so; returns its path."""
     objs = []
     procs = []
-    for src in ("tjm_kernels.hip", "tjm_api.cpp", "tjm_server.cpp"):
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    # the step kernels are one source compiled once per contraction precision
+    units = [("tjm_step.hip", "tjm_step_f32", ["-DTJM_TC=float"]),
+             ("tjm_step.hip", "tjm_step_f64", ["-DTJM_TC=double"]),
+             ("tjm_kernels.hip", "tjm_kernels", []),
+             ("tjm_api.cpp", "tjm_api", ["-x", "hip"]),
+             ("tjm_server.cpp", "tjm_server", ["-x", "hip"])]
+    for src, name, extra in units:
+        obj = os.path.join(CSRC, name + ".o")
+        cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     for cmd, p in procs:

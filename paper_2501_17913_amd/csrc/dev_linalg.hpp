@@ -8,9 +8,7 @@
 //                 the small tridiagonal exponential by scaled Taylor series.
 // All matrices are row-major complex<double> in global scratch memory.
 #pragma once
-#include <dev_gemm.hpp>
-
-#define TJM_KMAX 32                 // largest Krylov dimension supported
+#include <dev_lds.hpp>
 
 // --------------------------------------------------------------------------
 // Householder QR.  X (m x n, ld n, m <= 128) is destroyed.  On return Q
@@ -25,17 +23,6 @@
 // product and the update; the group that updates column j+1 also returns
 // its norm below the diagonal for the next step.
 // --------------------------------------------------------------------------
-constexpr int QR_MROWS = 128;
-constexpr int QR_TPC = TJM_NT >= 16 ? 16 : 1;                   // threads per column
-constexpr int QR_RPT = (QR_MROWS + QR_TPC - 1) / QR_TPC;        // rows per thread
-
-struct QrLds {
-  double vnorm2[QR_MROWS];
-  double bre[QR_MROWS], bim[QR_MROWS];  // diagonal of R before the gauge fix
-  zd v[QR_MROWS];                       // reflector of the current step
-  double a2next;                        // ||column j+1, rows j+1..||^2
-};
-
 // The elimination: on return X holds the reflectors below the diagonal with
 // their heads v0 on it, the rest of R above it; H holds beta_j (the
 // diagonal of R) and ||v_j||^2.
@@ -103,7 +90,9 @@ TJM_DEV void qr_reduce(int m, int n, zd* X, QrLds& H, BlkScratch& S) {
   }
 }
 
-TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, QrLds& H, BlkScratch& S) {
+TJM_DEVNI void blk_qr(int m, int n, zd* X, zd* Q, zd* R) {
+  QrLds& H = tjm_lds.qr;
+  BlkScratch& S = tjm_lds.S;
   const int k = m < n ? m : n;
   const int tid = tjm_tid();
   const int ngrp = TJM_NT / QR_TPC;
@@ -205,17 +194,6 @@ TJM_DEV int trunc_rank(F s, int n, double discard, int cap, double deg_tol) {
 // (m x n), with p, nc the row and column counts of the rotated matrix;
 // nc <= 128.
 // --------------------------------------------------------------------------
-constexpr int SVD_LDS_BYTES = 64 * 64 * 16;   // a working matrix of up to 4096 complex doubles
-static_assert(sizeof(QrLds) <= SVD_LDS_BYTES, "the preconditioning QR keeps its reflector in the SVD's LDS");
-
-struct SvdLds {
-  double s[128];
-  int order[128];
-  int rotated;
-  int k;
-  unsigned long long offmax;   // bits of the largest |w_a^H w_b| / (|w_a| |w_b|) of a sweep
-};
-
 // Round-robin pairing of np (even) players: in round rnd, pair pr meets
 // players a < b; over np - 1 rounds every pair meets once.
 TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
@@ -235,7 +213,8 @@ TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
 // off-diagonal |w_a^H w_b| / (|w_a| |w_b|) measured.  Ends with a barrier.
 constexpr int JAC_RPT = 8;           // rows per thread a pair keeps in registers
 
-TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double tol, SvdLds& SL) {
+TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double tol) {
+  SvdLds& SL = tjm_lds.sv;
   const int tid = tjm_tid();
   const int np = (ncol + 1) & ~1;        // players, a dummy if ncol is odd
   const int n2 = ncol - n1;
@@ -324,9 +303,11 @@ TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double
   }
 }
 
-TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
-                    double discard, int cap, double deg_tol,
-                    zd* Wc, zd* Uc, zd* Tg, SvdLds& SL, BlkScratch& S, void* glds) {
+TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
+                      double discard, int cap, double deg_tol, zd* Wc, zd* Uc, zd* Tg) {
+  SvdLds& SL = tjm_lds.sv;
+  BlkScratch& S = tjm_lds.S;
+  void* glds = tjm_lds.gemm;
   const int tid = tjm_tid();
   const bool tr = absorb_left;           // rotate the columns of G^H (-> V)
   const int p = tr ? n : m;              // rows of the working matrix
@@ -388,7 +369,7 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
     if (tid == 0) { SL.rotated = 0; SL.offmax = 0ull; }
     tjm_sync();
     if (!blocked) {
-      jacobi_sweep(Wc, p, nc, 0, zero2, tol, SL);
+      jacobi_sweep(Wc, p, nc, 0, zero2, tol);
     } else {
       // stage columns [c0, c0 + cI) and [c1, c1 + cJ) in Lc, or write them back
       auto move = [&](bool in, int c0, int cI, int c1, int cJ) {
@@ -402,7 +383,7 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
       for (int I = 0; I < nb; ++I) {
         const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
         move(true, c0, cI, 0, 0);
-        jacobi_sweep(Lc, p, cI, 0, zero2, tol, SL);
+        jacobi_sweep(Lc, p, cI, 0, zero2, tol);
         move(false, c0, cI, 0, 0);
       }
       for (int rnd = 0; rnd < nbp - 1; ++rnd)
@@ -413,7 +394,7 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
           const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
           const int c1 = J * bw, cJ = nc - c1 < bw ? nc - c1 : bw;
           move(true, c0, cI, c1, cJ);
-          jacobi_sweep(Lc, p, cI + cJ, cI, zero2, tol, SL);
+          jacobi_sweep(Lc, p, cI + cJ, cI, zero2, tol);
           move(false, c0, cI, c1, cJ);
         }
     }
@@ -486,15 +467,6 @@ TJM_DEV int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_
 // leaves w complete for all threads).  Q holds up to m_max basis vectors of
 // length n, w is an n-vector of scratch.  Returns the Krylov dimension used.
 // --------------------------------------------------------------------------
-struct LanczosLds {
-  double alpha[TJM_KMAX], beta[TJM_KMAX];
-  double cre[TJM_KMAX], cim[TJM_KMAX];
-  double hre[TJM_KMAX], him[TJM_KMAX];
-  double red[TJM_NWAVE][2 * TJM_KMAX];
-  double ur[TJM_KMAX], ui[TJM_KMAX], tr[TJM_KMAX], ti[TJM_KMAX];
-  int done;
-};
-
 // exp(-i t T) e_0 for the symmetric tridiagonal T = tridiag(beta, alpha, beta)
 // of size m <= 32: shift by alpha_0, split t into s pieces with
 // |t/s| * ||T - alpha_0||_inf <= 1/2 (Gershgorin) and sum 18 Taylor terms per
@@ -574,8 +546,9 @@ TJM_DEV void tridiag_exp_e0(int m, double t, LanczosLds& Lz) {
 }
 
 template <class Op>
-TJM_DEV int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol,
-                     zd* Q, zd* w, LanczosLds& Lz, BlkScratch& S) {
+TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd* Q, zd* w) {
+  LanczosLds& Lz = tjm_lds.lz;
+  BlkScratch& S = tjm_lds.S;
   const int tid = tjm_tid();
   double b0 = 0.0;
   for (int e = tid; e < n; e += TJM_NT) b0 += abs2(v[e]);

@@ -22,24 +22,9 @@
 #include <dev_linalg.hpp>
 #include "tjm_params.h"
 
-constexpr int LDS_WORK_BYTES = GEMM_LDS_BYTES > SVD_LDS_BYTES ? GEMM_LDS_BYTES : SVD_LDS_BYTES;
-
-struct Lds {
-  alignas(16) char gemm[LDS_WORK_BYTES];   // GEMM staging, or the SVD working matrix
-  BlkScratch S;
-  QrLds qr;
-  SvdLds sv;
-  LanczosLds lz;
-  unsigned long long st[TJM_NSTAT];
-  int item;
-  int pick;
-  double rho[4];
-};
-
 template <typename Tc> struct Tjm {
   typedef cplx<Tc> zc;
   const TjmParams& P;
-  Lds& sh;
   int* slot;          // LDS [L+2]: env slot of each bond; slot[L+1] is the spare
   int* bA;            // LDS [L+1]: bonds of the sampling MPS
   int* bB;            // LDS [L+1]: bonds of the sampling-layer copy
@@ -47,7 +32,7 @@ template <typename Tc> struct Tjm {
   zc* env; zd* smps; zd* Q; zd* w; zd* v; zc* T1; zd* X; zd* Y; zd* Z; zd* Cb; double* wts;
   int d, L;
 
-  TJM_DEV Tjm(const TjmParams& p, Lds& s, int* dyn, int worker) : P(p), sh(s) {
+  TJM_DEV Tjm(const TjmParams& p, int* dyn, int worker) : P(p) {
     L = P.L; d = P.d;
     slot = dyn;
     bA = dyn + (L + 2);
@@ -71,8 +56,8 @@ template <typename Tc> struct Tjm {
 
   TJM_DEV zc* envp(int bond) { return env + (long)slot[bond] * P.env_cap; }
   TJM_DEV zc* spare() { return env + (long)slot[L + 1] * P.env_cap; }
-  TJM_DEV void count(int i, unsigned long long n) { if (tjm_tid() == 0) sh.st[i] += n; }
-  TJM_DEV void since(int i, unsigned long long t0) { if (tjm_tid() == 0) sh.st[i] += tjm_clock() - t0; }
+  TJM_DEV void count(int i, unsigned long long n) { if (tjm_tid() == 0) tjm_lds.st[i] += n; }
+  TJM_DEV void since(int i, unsigned long long t0) { if (tjm_tid() == 0) tjm_lds.st[i] += tjm_clock() - t0; }
   TJM_DEV static zd* site(zd* mps, const TjmParams& P, int s) { return mps + P.site_off[s]; }
 
   TJM_DEV unsigned long long mix_nnz(int Dout, int dph, const int* rp) {
@@ -87,16 +72,16 @@ template <typename Tc> struct Tjm {
   }
 
   // L_{s+1}[w'][b'][b] = sum L_s[w][a'][a] conj(A[a'][s'][b']) W[w][w'][s'][s] A[a][s][b]
-  TJM_DEV void lupdate(int s, const zd* A, int chl, int chr, const zc* Lold, zc* Lnew) {
+  TJM_DEVNI void lupdate(int s, const zd* A, int chl, int chr, const zc* Lold, zc* Lnew) {
     const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
     blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
-                  T1, d * chr, (long)chl * d * chr, false, sh.gemm);
+                  T1, d * chr, (long)chl * d * chr, false, tjm_lds.gemm);
     tjm_sync();
     blk_cgemm<Tc>(chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
                   mix_rows((const zc*)T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
-                  Lnew, chr, (long)chr * chr, false, sh.gemm);
+                  Lnew, chr, (long)chr * chr, false, tjm_lds.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chr * chr * chl * d);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dr, d, rp) * chl * chr);
@@ -104,16 +89,16 @@ template <typename Tc> struct Tjm {
   }
 
   // R_{s-1}[w][a][a'] = sum B[a][s][b] R_s[w'][b][b'] W[w][w'][s'][s] conj(B[a'][s'][b'])
-  TJM_DEV void rupdate(int s, const zd* B, int chl, int chr, const zc* Rold, zc* Rnew) {
+  TJM_DEVNI void rupdate(int s, const zd* B, int chl, int chr, const zc* Rold, zc* Rnew) {
     const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixR_ptr + (long)s * (P.Dmax * d + 1);
     blk_cgemm<Tc>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
-                  T1, chr, (long)chl * d * chr, false, sh.gemm);
+                  T1, chr, (long)chl * d * chr, false, tjm_lds.gemm);
     tjm_sync();
     blk_cgemm<Tc>(chl, chl, d * chr, Dl, false,
                   mix_cols((const zc*)T1, rp, P.mixR, d, chr, (long)chl * d * chr, (long)d * chr, (long)chr),
-                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, sh.gemm);
+                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, tjm_lds.gemm);
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dl, d, rp) * chl * chr);
@@ -125,17 +110,17 @@ template <typename Tc> struct Tjm {
   // ------------------------------------------------------------------
   struct H1 {            // site s: degree-6 network
     Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
-    TJM_DEV void apply(const zd* q, zd* y) {
+    TJM_DEVNI void apply(const zd* q, zd* y) {
       const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
       const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
       blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
-                    t->T1, d * chr, (long)chl * d * chr, false, t->sh.gemm);
+                    t->T1, d * chr, (long)chl * d * chr, false, tjm_lds.gemm);
       tjm_sync();
       blk_cgemm<Tc>(chl * d, chr, chr, Dr, true,
                     mix_rows((const zc*)t->T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
-                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, tjm_lds.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chl * d * chr * chr);
       t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d, rp) * chl * chr);
@@ -145,17 +130,17 @@ template <typename Tc> struct Tjm {
 
   struct H2 {            // sites s, s+1: degree-8 network
     Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
-    TJM_DEV void apply(const zd* q, zd* y) {
+    TJM_DEVNI void apply(const zd* q, zd* y) {
       const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, d2 = d * d, Dl = P.mpoD[s], Dr = P.mpoD[s + 2];
       const int* rp = P.mix2_ptr + (long)s * (P.Dmax * d2 + 1);
       blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
-                    t->T1, d2 * chr, (long)chl * d2 * chr, false, t->sh.gemm);
+                    t->T1, d2 * chr, (long)chl * d2 * chr, false, tjm_lds.gemm);
       tjm_sync();
       blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true,
                     mix_rows((const zc*)t->T1, rp, P.mix2, d2, (long)chl * d2 * chr, (long)d2 * chr, (long)chr),
-                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, t->sh.gemm);
+                    cmat(Re, chr, (long)chr * chr), y, chr, 0, false, tjm_lds.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d2 * chr + (unsigned long long)Dr * chl * d2 * chr * chr);
       t->count(TJM_ST_CMAC_MIX, t->mix_nnz(Dr, d2, rp) * chl * chr);
@@ -165,13 +150,13 @@ template <typename Tc> struct Tjm {
 
   struct H0 {            // bond b: degree-4 network, C is kl x kr
     Tjm* t; int D, kl, kr; const zc* Le; const zc* Re;
-    TJM_DEV void apply(const zd* q, zd* y) {
+    TJM_DEVNI void apply(const zd* q, zd* y) {
       const unsigned long long t0 = tjm_clock();
       blk_cgemm<Tc>(kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
-                    t->T1, kr, (long)kl * kr, false, t->sh.gemm);
+                    t->T1, kr, (long)kl * kr, false, tjm_lds.gemm);
       tjm_sync();
       blk_cgemm<Tc>(kl, kr, kr, D, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
-                    cmat(Re, kr, (long)kr * kr), y, kr, 0, false, t->sh.gemm);
+                    cmat(Re, kr, (long)kr * kr), y, kr, 0, false, tjm_lds.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)D * kl * kl * kr + (unsigned long long)D * kl * kr * kr);
       t->since(TJM_ST_T_CONTRACT, t0);
@@ -180,7 +165,7 @@ template <typename Tc> struct Tjm {
 
   template <class Op> TJM_DEV void expm(Op& op, zd* vec, int n, double t) {
     const unsigned long long t0 = tjm_clock();
-    int it = blk_expm(op, vec, n, t, P.krylov_max, P.krylov_tol, Q, w, sh.lz, sh.S);
+    int it = blk_expm(op, vec, n, t, P.krylov_max, P.krylov_tol, Q, w);
     count(TJM_ST_KRYLOV, (unsigned long long)it);
     count(TJM_ST_EXPM, 1ull);
     since(TJM_ST_T_EXPM, t0);
@@ -194,18 +179,18 @@ template <typename Tc> struct Tjm {
   }
 
   // next (k x d x c) = C (k x m) . next (m x d x c), via v
-  TJM_DEV void absorb_right(zd* next, int k, int m, int c) {
+  TJM_DEVNI void absorb_right(zd* next, int k, int m, int c) {
     const unsigned long long t0 = tjm_clock();
-    blk_cgemm<double>(k, d * c, m, 1, true, cmat((const zd*)Cb, m), cmat((const zd*)next, d * c), v, d * c, 0, false, sh.gemm);
+    blk_cgemm<double>(k, d * c, m, 1, true, cmat((const zd*)Cb, m), cmat((const zd*)next, d * c), v, d * c, 0, false, tjm_lds.gemm);
     tjm_sync();
     copy(next, v, (long)k * d * c);
     tjm_sync();
     since(TJM_ST_T_ABSORB, t0);
   }
   // prev (p x d x k) = prev (p x d x m) . C (m x k), via v
-  TJM_DEV void absorb_left(zd* prev, int p, int m, int k) {
+  TJM_DEVNI void absorb_left(zd* prev, int p, int m, int k) {
     const unsigned long long t0 = tjm_clock();
-    blk_cgemm<double>(p * d, k, m, 1, true, cmat((const zd*)prev, m), cmat((const zd*)Cb, k), v, k, 0, false, sh.gemm);
+    blk_cgemm<double>(p * d, k, m, 1, true, cmat((const zd*)prev, m), cmat((const zd*)Cb, k), v, k, 0, false, tjm_lds.gemm);
     tjm_sync();
     copy(prev, v, (long)p * d * k);
     tjm_sync();
@@ -213,12 +198,12 @@ template <typename Tc> struct Tjm {
   }
 
   // QR of M_s as (chl d) x chr: M_s <- Q, Cb <- R (k x chr); returns k
-  TJM_DEV int qr_site(zd* Ms, int chl, int chr) {
+  TJM_DEVNI int qr_site(zd* Ms, int chl, int chr) {
     const unsigned long long t0 = tjm_clock();
     const int m = chl * d;
     copy(X, Ms, (long)m * chr);
     tjm_sync();
-    blk_qr(m, chr, X, Ms, Cb, sh.qr, sh.S);
+    blk_qr(m, chr, X, Ms, Cb);
     count(TJM_ST_FACT, 1ull);
     since(TJM_ST_T_QR, t0);
     return m < chr ? m : chr;
@@ -226,7 +211,7 @@ template <typename Tc> struct Tjm {
 
   // LQ of M_s as chl x (d chr): M_s <- B (k x d chr, orthonormal rows),
   // Cb <- C (chl x k); returns k
-  TJM_DEV int lq_site(zd* Ms, int chl, int chr) {
+  TJM_DEVNI int lq_site(zd* Ms, int chl, int chr) {
     const unsigned long long t0 = tjm_clock();
     const int n = d * chr;
     for (long e = tjm_tid(); e < (long)n * chl; e += TJM_NT) {      // X = M^H (n x chl)
@@ -234,7 +219,7 @@ template <typename Tc> struct Tjm {
       X[e] = conjg(Ms[(long)j * n + i]);
     }
     tjm_sync();
-    blk_qr(n, chl, X, Y, Z, sh.qr, sh.S);                           // Y: n x k, Z: k x chl
+    blk_qr(n, chl, X, Y, Z);                           // Y: n x k, Z: k x chl
     const int k = n < chl ? n : chl;
     for (long e = tjm_tid(); e < (long)k * n; e += TJM_NT) {        // M = Y^H
       int i = (int)(e / n), j = (int)(e % n);
@@ -250,7 +235,7 @@ template <typename Tc> struct Tjm {
     return k;
   }
 
-  TJM_DEV void qr_move_right(zd* mps, int* bd, int s) {
+  TJM_DEVNI void qr_move_right(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
     const int k = qr_site(Ms, chl, chr);
@@ -259,7 +244,7 @@ template <typename Tc> struct Tjm {
     tjm_sync();
   }
 
-  TJM_DEV void lq_move_left(zd* mps, int* bd, int s) {
+  TJM_DEVNI void lq_move_left(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
     const int k = lq_site(Ms, chl, chr);
@@ -272,7 +257,7 @@ template <typename Tc> struct Tjm {
   // of R (row-major, ld) provably exceeds sqrt(2 thr): sigma_min(R) >=
   // 1 / ||R^{-1}||_F, with R^{-1} by back substitution (thread c builds
   // column c in Y).  For a wide R [R1 R2], sigma_min >= sigma_min(R1).
-  TJM_DEV bool sv_floor_certified(const zd* R, int n, int ld, double thr) {
+  TJM_DEVNI bool sv_floor_certified(const zd* R, int n, int ld, double thr) {
     double acc = 0.0;
     int bad = 0;
     for (int c = tjm_tid(); c < n; c += TJM_NT) {
@@ -289,7 +274,7 @@ template <typename Tc> struct Tjm {
       }
     }
     double b2 = (double)bad;
-    blk_sum2(acc, b2, sh.S);
+    blk_sum2(acc, b2, tjm_lds.S);
     return b2 == 0.0 && acc * 2.0 * thr < 1.0;
   }
 
@@ -297,13 +282,13 @@ template <typename Tc> struct Tjm {
   // jump): M_s = Q R; if R's singular values certifiably all survive the
   // discard threshold the QR move is the result, otherwise R = U S V^H is
   // truncated, M_s = Q U, next <- S V^H next.
-  TJM_DEV void svd_move_right(zd* mps, int* bd, int s) {
+  TJM_DEVNI void svd_move_right(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cn = bd[s + 2];
     const int m = chl * d;
     if (!P.certify) {                                 // SVD of M_s itself
       const unsigned long long ts_ = tjm_clock();
-      const int k = blk_svd(m, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      const int k = blk_svd(m, chr, Ms, Ms, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
       count(TJM_ST_FACT, 1ull);
       since(TJM_ST_T_SVD, ts_);
       absorb_right(site(mps, P, s + 1), k, chr, cn);
@@ -316,9 +301,9 @@ template <typename Tc> struct Tjm {
     const double tot = norm2_site(Cb, (long)k0 * chr);
     int k = k0;
     if (!sv_floor_certified(Cb, k0, chr, P.svd_discard * tot)) {
-      k = blk_svd(k0, chr, Cb, w, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      k = blk_svd(k0, chr, Cb, w, Cb, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
       count(TJM_ST_FACT, 1ull);
-      blk_cgemm<double>(m, k, k0, 1, true, cmat((const zd*)Ms, k0), cmat((const zd*)w, k), v, k, 0, false, sh.gemm);
+      blk_cgemm<double>(m, k, k0, 1, true, cmat((const zd*)Ms, k0), cmat((const zd*)w, k), v, k, 0, false, tjm_lds.gemm);
       tjm_sync();
       copy(Ms, v, (long)m * k);
       tjm_sync();
@@ -331,13 +316,13 @@ template <typename Tc> struct Tjm {
 
   // Mirror image: M_s = C B (LQ); C's singular values certified, or
   // C = U S V^H truncated, M_s <- V^H B, prev <- prev U S.
-  TJM_DEV void svd_move_left(zd* mps, int* bd, int s) {
+  TJM_DEVNI void svd_move_left(zd* mps, int* bd, int s) {
     zd* Ms = site(mps, P, s);
     const int chl = bd[s], chr = bd[s + 1], cp = bd[s - 1];
     const int n = d * chr;
     if (!P.certify) {                                 // SVD of M_s itself
       const unsigned long long ts_ = tjm_clock();
-      const int k = blk_svd(chl, n, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      const int k = blk_svd(chl, n, Ms, Cb, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
       count(TJM_ST_FACT, 1ull);
       since(TJM_ST_T_SVD, ts_);
       absorb_left(site(mps, P, s - 1), cp, chl, k);
@@ -350,9 +335,9 @@ template <typename Tc> struct Tjm {
     const double tot = norm2_site(Cb, (long)chl * k0);
     int k = k0;
     if (!sv_floor_certified(Z, k0, chl, P.svd_discard * tot)) {
-      k = blk_svd(chl, k0, Cb, Cb, w, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+      k = blk_svd(chl, k0, Cb, Cb, w, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
       count(TJM_ST_FACT, 1ull);
-      blk_cgemm<double>(k, n, k0, 1, true, cmat((const zd*)w, k0), cmat((const zd*)Ms, n), v, n, 0, false, sh.gemm);
+      blk_cgemm<double>(k, n, k0, 1, true, cmat((const zd*)w, k0), cmat((const zd*)Ms, n), v, n, 0, false, tjm_lds.gemm);
       tjm_sync();
       copy(Ms, v, (long)k * n);
       tjm_sync();
@@ -369,7 +354,7 @@ template <typename Tc> struct Tjm {
   // sweep reaches it, else 1TDVP; the turning unit is evolved again.
   // Precondition: centre at site 0, other sites right-canonical.
   // ------------------------------------------------------------------
-  TJM_DEV void tdvp(zd* mps, int* bd) {
+  TJM_DEVNI void tdvp(zd* mps, int* bd) {
     const double tau = 0.5 * P.dt;
     if (tjm_tid() == 0)
       for (int b = 0; b < L + 2; ++b) slot[b] = b;
@@ -390,13 +375,13 @@ template <typename Tc> struct Tjm {
         count(TJM_ST_TWO_SITE, 1ull);
         const unsigned long long tt_ = tjm_clock();
         blk_cgemm<double>(chl * d, d * chr, chm, 1, true, cmat((const zd*)Ms, chm), cmat((const zd*)Mn, d * chr),
-                          v, d * chr, 0, false, sh.gemm);
+                          v, d * chr, 0, false, tjm_lds.gemm);
         tjm_sync();
         since(TJM_ST_T_ABSORB, tt_);
         H2 op{this, s, chl, chr, envp(s), envp(s + 2)};
         expm(op, v, chl * d * d * chr, tau);
         const unsigned long long ts_ = tjm_clock();
-    const int k = blk_svd(chl * d, d * chr, v, Ms, Mn, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+    const int k = blk_svd(chl * d, d * chr, v, Ms, Mn, false, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
         count(TJM_ST_FACT, 1ull);
         since(TJM_ST_T_SVD, ts_);
         if (tjm_tid() == 0) bd[s + 1] = k;
@@ -438,13 +423,13 @@ template <typename Tc> struct Tjm {
         count(TJM_ST_TWO_SITE, 1ull);
         const unsigned long long tt_ = tjm_clock();
         blk_cgemm<double>(chp * d, d * chr, chl, 1, true, cmat((const zd*)Mp, chl), cmat((const zd*)Ms, d * chr),
-                          v, d * chr, 0, false, sh.gemm);
+                          v, d * chr, 0, false, tjm_lds.gemm);
         tjm_sync();
         since(TJM_ST_T_ABSORB, tt_);
         H2 op{this, s - 1, chp, chr, envp(s - 1), envp(s + 1)};
         expm(op, v, chp * d * d * chr, tau);
         const unsigned long long ts_ = tjm_clock();
-    const int k = blk_svd(chp * d, d * chr, v, Mp, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z, sh.sv, sh.S, sh.gemm);
+    const int k = blk_svd(chp * d, d * chr, v, Mp, Ms, true, P.svd_discard, P.chi_cap, P.deg_tol, X, Y, Z);
         count(TJM_ST_FACT, 1ull);
         since(TJM_ST_T_SVD, ts_);
         if (tjm_tid() == 0) bd[s] = k;
@@ -482,7 +467,7 @@ template <typename Tc> struct Tjm {
   // Dissipative contraction (Eq. DissipativeMPO): M_l <- D_l M_l on the
   // physical index of every site; bond dimensions unchanged.
   // ------------------------------------------------------------------
-  TJM_DEV void dissipate(zd* mps, const int* bd, const double* Dtab) {
+  TJM_DEVNI void dissipate(zd* mps, const int* bd, const double* Dtab) {
     for (int s = 0; s < L; ++s) {
       zd* M = site(mps, P, s);
       const zd* D = (const zd*)Dtab + (long)s * d * d;
@@ -498,8 +483,8 @@ template <typename Tc> struct Tjm {
   }
 
   // rho[s][s'] = sum_{a,b} M[a][s][b] conj(M[a][s'][b]) at the centre
-  // (d = 2): sh.rho = (rho00, rho11, Re rho01, Im rho01)
-  TJM_DEV void site_rho(const zd* M, int chl, int chr) {
+  // (d = 2): tjm_lds.rho = (rho00, rho11, Re rho01, Im rho01)
+  TJM_DEVNI void site_rho(const zd* M, int chl, int chr) {
     double r00 = 0, r11 = 0, rr = 0, ri = 0;
     for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
       int a = (int)(e / chr), b = (int)(e % chr);
@@ -508,21 +493,21 @@ template <typename Tc> struct Tjm {
       zd c = cdotc(x1, x0);      // x0 conj(x1)
       rr += c.re; ri += c.im;
     }
-    blk_sum4(r00, r11, rr, ri, sh.S);
-    if (tjm_tid() == 0) { sh.rho[0] = r00; sh.rho[1] = r11; sh.rho[2] = rr; sh.rho[3] = ri; }
+    blk_sum4(r00, r11, rr, ri, tjm_lds.S);
+    if (tjm_tid() == 0) { tjm_lds.rho[0] = r00; tjm_lds.rho[1] = r11; tjm_lds.rho[2] = rr; tjm_lds.rho[3] = ri; }
     tjm_sync();
   }
 
   // sum_{s,s'} O[s'][s] rho[s][s'] (real part), for a 2x2 operator O
   TJM_DEV double tr_op_rho(const zd* O) {
-    zd r01 = cmk(sh.rho[2], sh.rho[3]);
-    zd v = O[0] * cmk(sh.rho[0], 0.0) + O[3] * cmk(sh.rho[1], 0.0) + O[2] * r01 + O[1] * conjg(r01);
+    zd r01 = cmk(tjm_lds.rho[2], tjm_lds.rho[3]);
+    zd v = O[0] * cmk(tjm_lds.rho[0], 0.0) + O[3] * cmk(tjm_lds.rho[1], 0.0) + O[2] * r01 + O[1] * conjg(r01);
     return v.re;
   }
 
   // Tr(L rho L^dag) for a 2x2 L
   TJM_DEV double tr_l_rho_ld(const zd* Lop) {
-    zd rho[4] = {cmk(sh.rho[0], 0.0), cmk(sh.rho[2], sh.rho[3]), cmk(sh.rho[2], -sh.rho[3]), cmk(sh.rho[1], 0.0)};
+    zd rho[4] = {cmk(tjm_lds.rho[0], 0.0), cmk(tjm_lds.rho[2], tjm_lds.rho[3]), cmk(tjm_lds.rho[2], -tjm_lds.rho[3]), cmk(tjm_lds.rho[1], 0.0)};
     double acc = 0.0;
     for (int a = 0; a < 2; ++a) {
       zd x = cmk(0.0, 0.0);
@@ -533,10 +518,10 @@ template <typename Tc> struct Tjm {
     return acc;
   }
 
-  // measure every observable of site s with the centre at s (rho in sh.rho)
+  // measure every observable of site s with the centre at s (rho in tjm_lds.rho)
   TJM_DEV void measure(int s, double* out) {
     if (tjm_tid() == 0) {
-      const double tr = sh.rho[0] + sh.rho[1];
+      const double tr = tjm_lds.rho[0] + tjm_lds.rho[1];
       for (int q = P.optr[s]; q < P.optr[s + 1]; ++q) {
         int o = P.oidx[q];
         out[o] = tr_op_rho((const zd*)P.obs_op + (long)o * 4) / tr;
@@ -547,7 +532,7 @@ template <typename Tc> struct Tjm {
   TJM_DEV double norm2_site(const zd* M, long n) {
     double a = 0.0;
     for (long e = tjm_tid(); e < n; e += TJM_NT) a += abs2(M[e]);
-    return blk_sum(a, sh.S);
+    return blk_sum(a, tjm_lds.S);
   }
 
   TJM_DEV void scale_site(zd* M, long n, double f) {
@@ -555,91 +540,10 @@ template <typename Tc> struct Tjm {
     tjm_sync();
   }
 
-  // ------------------------------------------------------------------
-  // Transfer-matrix environments of an MPS in any gauge (FP64):
-  //   right R_s = sum_sig M_s^sig R_{s+1} M_s^sig^H  (b_s x b_s, R_L = 1),
-  //   left  F_{s+1} = sum_sig M_s^sig^H F_s M_s^sig   (F_0 = 1),
-  // and rho_s[sig][sig'] = Tr(F_s M_s^sig R_{s+1} M_s^sig'^H), the
-  // (unnormalised) reduced density matrix of site s; <psi|psi> = R_0.
-  // R_s lives in environment slot s (free during the jump process).
-  // ------------------------------------------------------------------
-  TJM_DEV zd* renv(int s) { return (zd*)envp(s); }
-
-  TJM_DEV double envs_right(const zd* mps, const int* bd) {
-    const unsigned long long t0 = tjm_clock();
-    zd* RL = renv(L);
-    if (tjm_tid() == 0) RL[0] = cmk(1.0, 0.0);
-    tjm_sync();
-    for (int s = L - 1; s >= 0; --s) {
-      const zd* M = site((zd*)mps, P, s);
-      const int chl = bd[s], chr = bd[s + 1];
-      blk_cgemm<double>(chl * d, chr, chr, 1, true, cmat(M, chr), cmat((const zd*)renv(s + 1), chr), X, chr, 0,
-                        false, sh.gemm);
-      tjm_sync();
-      blk_cgemm<double>(chl, chl, d * chr, 1, true, cmat((const zd*)X, d * chr), cmat(M, d * chr, 0, true, true),
-                        renv(s), chl, 0, false, sh.gemm);
-      tjm_sync();
-      count(TJM_ST_CMAC_FP64, 2ull * chl * d * chr * chr);
-    }
-    since(TJM_ST_T_ENV, t0);
-    return renv(0)[0].re;
-  }
-
-  // Left sweep of F with rho_s at every site: jump weights (wts) and/or the
-  // site observables (obs_out, normalised by Tr rho).  Needs envs_right.
-  TJM_DEV void envs_left_rho(const zd* mps, const int* bd, bool weights, double* obs_out) {
-    const unsigned long long t0 = tjm_clock();
-    zd* F = Y;
-    zd* Fn = Z;
-    if (tjm_tid() == 0) F[0] = cmk(1.0, 0.0);
-    tjm_sync();
-    for (int s = 0; s < L; ++s) {
-      const zd* M = site((zd*)mps, P, s);
-      const int chl = bd[s], chr = bd[s + 1];
-      // V = F M  (chl x d chr),  U = V R_{s+1}  ((chl d) x chr)
-      blk_cgemm<double>(chl, d * chr, chl, 1, true, cmat((const zd*)F, chl), cmat(M, d * chr), X, d * chr, 0,
-                        false, sh.gemm);
-      tjm_sync();
-      blk_cgemm<double>(chl * d, chr, chr, 1, true, cmat((const zd*)X, chr), cmat((const zd*)renv(s + 1), chr),
-                        Cb, chr, 0, false, sh.gemm);
-      tjm_sync();
-      double r00 = 0, r11 = 0, rr = 0, ri = 0;
-      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
-        const int a = (int)(e / chr), b = (int)(e % chr);
-        const zd u0 = Cb[((long)a * 2 + 0) * chr + b], u1 = Cb[((long)a * 2 + 1) * chr + b];
-        const zd m0 = M[((long)a * 2 + 0) * chr + b], m1 = M[((long)a * 2 + 1) * chr + b];
-        r00 += cdotc(m0, u0).re;
-        r11 += cdotc(m1, u1).re;
-        const zd c = cdotc(m1, u0);                 // U^0 conj(M^1)
-        rr += c.re; ri += c.im;
-      }
-      blk_sum4(r00, r11, rr, ri, sh.S);
-      if (tjm_tid() == 0) {
-        sh.rho[0] = r00; sh.rho[1] = r11; sh.rho[2] = rr; sh.rho[3] = ri;
-        if (weights)
-          for (int q = P.jptr[s]; q < P.jptr[s + 1]; ++q) {
-            const int j = P.jidx[q];
-            wts[j] = P.jump_rate[j] * tr_l_rho_ld((const zd*)P.jump_op + (long)j * 4);
-          }
-      }
-      tjm_sync();
-      if (obs_out) measure(s, obs_out);
-      if (s + 1 < L) {                               // F_{s+1} = M^H V over (a, sig)
-        blk_cgemm<double>(chr, chr, chl * d, 1, true, cmat(M, chr, 0, true, true), cmat((const zd*)X, chr), Fn, chr,
-                          0, false, sh.gemm);
-        tjm_sync();
-        zd* t = F; F = Fn; Fn = t;
-      }
-      count(TJM_ST_CMAC_FP64, (unsigned long long)chl * chl * d * chr + (unsigned long long)chl * d * chr * chr +
-                                  (s + 1 < L ? (unsigned long long)chr * chr * chl * d : 0ull));
-    }
-    since(TJM_ST_T_ENV, t0);
-  }
-
   // pick the jump from wts (rule of Sec. "Stochastic jump process" with the
   // weights normalised by their sum): first index whose running sum exceeds
   // r W; -1 if W <= 1e-300
-  TJM_DEV int pick_jump(double r) {
+  TJM_DEVNI int pick_jump(double r) {
     if (tjm_tid() == 0) {
       double tot = 0.0;
       for (int j = 0; j < P.n_jump; ++j) tot += wts[j];
@@ -655,15 +559,15 @@ template <typename Tc> struct Tjm {
           for (int j = P.n_jump - 1; j >= 0; --j)
             if (wts[j] > 0.0) { m = j; break; }
       }
-      sh.pick = m;
+      tjm_lds.pick = m;
     }
     tjm_sync();
-    return sh.pick;
+    return tjm_lds.pick;
   }
 
   // apply jump m at its site (centre there), normalise, then the
   // normalisation sweeps through successive SVDs: site -> right end -> 0
-  TJM_DEV void apply_jump(zd* mps, int* bd, int m, double* obs_out) {
+  TJM_DEVNI void apply_jump(zd* mps, int* bd, int m, double* obs_out) {
     const int sj = P.jump_site[m];
     zd* M = site(mps, P, sj);
     const zd* Op = (const zd*)P.jump_op + (long)m * 4;
@@ -688,60 +592,25 @@ template <typename Tc> struct Tjm {
   }
 
   // ------------------------------------------------------------------
-  // Jump process J_eps (Sec. "Stochastic jump process").  Entry: centre at
-  // site 0, the other sites right-canonical.  Exit (if keep): normalised,
-  // centre at site 0, other sites right-canonical.  If obs_out is non-null,
-  // the site observables of the resulting state are written there; a state
-  // that is not kept is only measured.
+  // Jump process J_eps (Sec. "Stochastic jump process") applied to D[tau]
+  // of the MPS.  Entry: centre at site 0, the other sites right-canonical.
+  // Exit: normalised, centre at site 0, other sites right-canonical.  If
+  // obs_out is non-null, the site observables of the resulting state are
+  // written there (measured at each centre of the final sweep).
   // Returns the applied jump index, -1 for none, -2 on a non-finite norm.
-  //
-  // The decisions are those of the sweep order of the paper (QR sweep to the
-  // right end for delta p, LQ sweep back for the weights, QR moves to the
-  // jump site): delta p = 1 - <psi|psi> and the weights are gauge-invariant
-  // traces, taken here from transfer-matrix environments, and the QR / LQ
-  // moves change no bond dimension when b_{s+1} <= d b_s and b_s <= d b_{s+1}
-  // for every bond; otherwise (or with P.sweep_jumps) the sweeps are run as
-  // printed.
   // ------------------------------------------------------------------
-  TJM_DEV int jump_process(zd* mps, int* bd, const double* Dtab, uint32_t step, uint32_t branch,
-                           double* obs_out, bool keep) {
+  TJM_DEVNI int jump_process(zd* mps, int* bd, const double* Dtab, uint32_t step, uint32_t branch,
+                             double* obs_out) {
     dissipate(mps, bd, Dtab);
-    if (tjm_tid() == 0) {
-      int ok = P.sweep_jumps ? 0 : 1;
-      for (int b = 0; b < L && ok; ++b)
-        if (bd[b + 1] > d * bd[b] || bd[b] > d * bd[b + 1]) ok = 0;
-      sh.pick = ok;
-    }
-    tjm_sync();
-    if (!sh.pick) return jump_process_sweeps(mps, bd, step, branch, obs_out);
-    const double nrm2 = envs_right(mps, bd);
-    if (!(nrm2 == nrm2) || nrm2 > 1e300) return -2;
-    const double dp = nrm2 < 1.0 ? 1.0 - nrm2 : 0.0;
-    double eps, r;
-    tjm_draws(P.seed, P.traj_base + (uint32_t)traj_id, step, branch, eps, r);
-    int m = -1;
-    if (eps < dp) {
-      envs_left_rho(mps, bd, true, obs_out);
-      m = pick_jump(r);
-    } else if (obs_out) {
-      envs_left_rho(mps, bd, false, obs_out);
-    }
-    if (m < 0) {                                        // no jump: normalise
-      if (keep) {
-        for (int s = L - 1; s >= 1; --s) lq_move_left(mps, bd, s);
-        finish(mps, bd, nullptr);
-      }
-      return -1;
-    }
-    const int sj = P.jump_site[m];
-    for (int s = L - 1; s > sj; --s) lq_move_left(mps, bd, s);
-    for (int s = 0; s < sj; ++s) qr_move_right(mps, bd, s);
-    apply_jump(mps, bd, m, obs_out);
-    return m;
+    return jump_sweeps(mps, bd, step, branch, obs_out);
   }
 
-  // The jump process with the sweeps in the printed order (entry after D).
-  TJM_DEV int jump_process_sweeps(zd* mps, int* bd, uint32_t step, uint32_t branch, double* obs_out) {
+  // The jump process proper, entry after D: QR sweep to the right end for
+  // delta p = 1 - ||M_L||^2; no jump (eps >= delta p): normalise and LQ
+  // sweep back; otherwise LQ sweep back with the weights at every centre,
+  // pick, QR moves to the jump site, apply and normalise through the SVD
+  // sweeps.
+  TJM_DEVNI int jump_sweeps(zd* mps, int* bd, uint32_t step, uint32_t branch, double* obs_out) {
     for (int s = 0; s < L - 1; ++s) qr_move_right(mps, bd, s);
     const long nlast = (long)bd[L - 1] * d * bd[L];
     const double nrm2 = norm2_site(site(mps, P, L - 1), nlast);
@@ -781,7 +650,7 @@ template <typename Tc> struct Tjm {
   }
 
   // centre at site 0: measure it and normalise
-  TJM_DEV void finish(zd* mps, int* bd, double* obs_out) {
+  TJM_DEVNI void finish(zd* mps, int* bd, double* obs_out) {
     zd* M0 = site(mps, P, 0);
     const long n = (long)bd[0] * d * bd[1];
     if (obs_out) { site_rho(M0, bd[0], bd[1]); measure(0, obs_out); }
@@ -804,20 +673,20 @@ template <typename Tc> struct Tjm {
     tjm_sync();
   }
   TJM_DEV void stats_begin() {
-    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) sh.st[i] = 0ull;
+    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) tjm_lds.st[i] = 0ull;
     tjm_sync();
     if (tjm_tid() == 0) t_begin = tjm_clock();
     tjm_sync();
   }
   TJM_DEV void stats_end(int traj) {
     tjm_sync();
-    if (tjm_tid() == 0) sh.st[TJM_ST_T_TOTAL] += tjm_clock() - t_begin;
+    if (tjm_tid() == 0) tjm_lds.st[TJM_ST_T_TOTAL] += tjm_clock() - t_begin;
     tjm_sync();
-    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) P.tstats[(long)traj * TJM_NSTAT + i] += sh.st[i];
+    for (int i = tjm_tid(); i < TJM_NSTAT; i += TJM_NT) P.tstats[(long)traj * TJM_NSTAT + i] += tjm_lds.st[i];
   }
 
   // Psi(0): product state, canonicalised; t = 0 observables; Phi = F_0 Psi(0)
-  TJM_DEV void traj_init(int traj) {
+  TJM_DEVNI void traj_init(int traj) {
     traj_id = traj;
     stats_begin();
     zd* mps = (zd*)P.mps + (long)traj * P.mps_cap;
@@ -856,7 +725,7 @@ template <typename Tc> struct Tjm {
       }
       finish(mps, bA, o0);
     }
-    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr, true);
+    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
     if (tjm_tid() == 0) {
       P.jlog[(long)traj * 2 * P.n_steps] = m;
       if (m == -2) P.tflags[traj] = 1;
@@ -867,7 +736,7 @@ template <typename Tc> struct Tjm {
 
   // F_k for k = 1..n: X = U Phi; Psi_k = J D[dt/2] X (measured);
   // Phi = J D[dt] X for k < n
-  TJM_DEV void traj_step(int traj, int k) {
+  TJM_DEVNI void traj_step(int traj, int k) {
     traj_id = traj;
     stats_begin();
     if (P.tflags[traj]) {            // already non-finite: no further work
@@ -882,9 +751,9 @@ template <typename Tc> struct Tjm {
     for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
     tjm_sync();
     double* ok = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
-    int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok, false);
+    int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok);
     int mm = -1;
-    if (k < P.n_steps && ms != -2) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr, true);
+    if (k < P.n_steps && ms != -2) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr);
     if (tjm_tid() == 0) {
       int* jl = P.jlog + (long)traj * 2 * P.n_steps;
       jl[2 * k - 1] = ms;

@@ -277,6 +277,8 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   const int chi_cap = opt.chi_cap > 0 ? opt.chi_cap : chi_max;
   if (chi_cap > 64) return fail(m, TJM_E_UNSUPPORTED, "chi_cap above 64 is not supported");
   if (opt.krylov_max < 1 || opt.krylov_max > 32) return fail(m, TJM_E_INVAL, "krylov_max must be in 1..32");
+  if (opt.sweep_jumps != 1)
+    return fail(m, TJM_E_UNSUPPORTED, "only the jump process with the printed sweeps (sweep_jumps = 1) is implemented");
   if (!std::isfinite(opt.svd_discard) || !std::isfinite(opt.deg_tol) || opt.deg_tol < 0)
     return fail(m, TJM_E_INVAL, "svd_discard / deg_tol must be finite");
   if (n_obs < 0 || (n_obs > 0 && (!obs_site || !obs_op))) return fail(m, TJM_E_INVAL, "bad observables");
@@ -285,6 +287,7 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   if (n_obs > 0 && !finite_arr(obs_op, 2L * n_obs * d * d)) return fail(m, TJM_E_INVAL, "observable not finite");
   if ((double)n_traj * (double)(n + 1) * std::max(n_obs, 1) > 4e9)
     return fail(m, TJM_E_INVAL, "output too large");
+  if ((double)(n + 1) * std::max(n_obs, 1) > 2e9) return fail(m, TJM_E_INVAL, "too many output entries per trajectory");
   double tol = opt.krylov_tol;
   if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-6 : 1e-12;   // mixed: at the FP32 contraction accuracy
 
@@ -299,7 +302,6 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = opt.record_bonds ? 1 : 0;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
-  P.sweep_jumps = opt.sweep_jumps ? 1 : 0;
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
   P.seed = seed; P.traj_base = opt.traj_base;
 
@@ -671,7 +673,7 @@ extern "C" tjm_status tjm_run_end(tjm_model* m, double* mean, double* sem, doubl
   if (!r) return fail(m, TJM_E_BUSY, "no run in progress");
   tjm_status st = TJM_OK;
   std::string msg;
-  const int entries = (r->n_steps + 1) * r->n_obs;
+  const long entries = (long)(r->n_steps + 1) * r->n_obs;
   auto chk = [&](hipError_t e, const char* what) {
     if (e != hipSuccess && st == TJM_OK) {
       st = TJM_E_DEVICE;
@@ -681,13 +683,13 @@ extern "C" tjm_status tjm_run_end(tjm_model* m, double* mean, double* sem, doubl
   if (r->steps_done != r->n_steps) { st = TJM_E_BUSY; msg = "run ended before its last step"; }
   if (st == TJM_OK && entries > 0 && (mean || sem)) {
     double *dm = nullptr, *ds = nullptr;
-    chk(hipMalloc((void**)&dm, entries * 8), "hipMalloc");
-    chk(hipMalloc((void**)&ds, entries * 8), "hipMalloc");
+    chk(hipMalloc((void**)&dm, (size_t)entries * 8), "hipMalloc");
+    chk(hipMalloc((void**)&ds, (size_t)entries * 8), "hipMalloc");
     if (st == TJM_OK) {
       chk(tjm_launch_reduce(r->d_obs, r->n_traj, entries, dm, ds, r->stream), "reduce");
       chk(hipStreamSynchronize(r->stream), "sync");
-      if (mean) chk(hipMemcpy(mean, dm, entries * 8, hipMemcpyDeviceToHost), "copy mean");
-      if (sem) chk(hipMemcpy(sem, ds, entries * 8, hipMemcpyDeviceToHost), "copy sem");
+      if (mean) chk(hipMemcpy(mean, dm, (size_t)entries * 8, hipMemcpyDeviceToHost), "copy mean");
+      if (sem) chk(hipMemcpy(sem, ds, (size_t)entries * 8, hipMemcpyDeviceToHost), "copy sem");
     }
     if (dm) (void)hipFree(dm);
     if (ds) (void)hipFree(ds);

@@ -10,8 +10,13 @@ hipError_t tjm_blocks_per_cu(int mixed, int L, int* blocks);
 hipError_t tjm_launch_reset(int* counter, hipStream_t s);
 // k = 0: F_0 and t = 0 observables; k >= 1: step function k
 hipError_t tjm_launch_step(const TjmParams& P, int k, int workers, hipStream_t s);
+// the same per contraction precision (tjm_step.hip, compiled once for each)
+hipError_t tjm_blocks_per_cu_float(int L, int* blocks);
+hipError_t tjm_blocks_per_cu_double(int L, int* blocks);
+hipError_t tjm_launch_step_float(const TjmParams& P, int k, int workers, hipStream_t s);
+hipError_t tjm_launch_step_double(const TjmParams& P, int k, int workers, hipStream_t s);
 // mean / standard error over trajectories of obs[n_traj][entries], fixed order
-hipError_t tjm_launch_reduce(const double* obs, int n_traj, int entries, double* mean,
+hipError_t tjm_launch_reduce(const double* obs, int n_traj, long entries, double* mean,
                              double* sem, hipStream_t s);
 
 hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_batches,

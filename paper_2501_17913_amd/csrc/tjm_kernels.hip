@@ -1,52 +1,16 @@
-// TJM kernels for CDNA4 (gfx950).
-//
-// tjm_step_kernel is persistent: a grid of resident workgroups pulls
-// trajectory indices from a device work counter, so trajectories with more
-// work (jumps, larger bonds, more Lanczos iterations) do not stall the
-// others.  One launch applies one step function to every trajectory; the
-// per-trajectory MPS lives in HBM between launches, the environments,
-// Krylov basis and factorisation workspaces are per-workgroup scratch.
+// Small TJM kernels for CDNA4 (gfx950): work-queue reset, the trajectory
+// average, the precision dispatch of the step kernels (tjm_step.hip), and
+// the self-test kernels that run one building block as one workgroup.
 #include <dev_tjm.hpp>
 #include "tjm_internal.h"
-
-template <typename Tc>
-__global__ __launch_bounds__(TJM_NT, 2) void tjm_step_kernel(TjmParams P, int k) {
-  __shared__ Lds sh;
-  extern __shared__ int dyn[];
-  Tjm<Tc> t(P, sh, dyn, (int)blockIdx.x);
-  for (;;) {
-    if (threadIdx.x == 0) sh.item = atomicAdd(P.counter, 1);
-    __syncthreads();
-    const int item = sh.item;
-    __syncthreads();
-    if (item >= P.n_traj) break;
-    t.traj_step(item, k);
-  }
-}
-
-// Psi(0) -> t = 0 observables and Phi = F_0 Psi(0), same work queue
-template <typename Tc>
-__global__ __launch_bounds__(TJM_NT, 2) void tjm_init_kernel(TjmParams P) {
-  __shared__ Lds sh;
-  extern __shared__ int dyn[];
-  Tjm<Tc> t(P, sh, dyn, (int)blockIdx.x);
-  for (;;) {
-    if (threadIdx.x == 0) sh.item = atomicAdd(P.counter, 1);
-    __syncthreads();
-    const int item = sh.item;
-    __syncthreads();
-    if (item >= P.n_traj) break;
-    t.traj_init(item);
-  }
-}
 
 __global__ void tjm_reset_kernel(int* c) { *c = 0; }
 
 // Trajectory average (Eq. TJMExpVal) and its standard error, one thread per
 // (time, observable) entry, trajectories summed in index order.
-__global__ void tjm_reduce_kernel(const double* obs, int n_traj, int entries, double* mean,
+__global__ void tjm_reduce_kernel(const double* obs, int n_traj, long entries, double* mean,
                                   double* sem) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= entries) return;
   double s = 0.0;
   for (int t = 0; t < n_traj; ++t) s += obs[(long)t * entries + e];
@@ -63,11 +27,7 @@ __global__ void tjm_reduce_kernel(const double* obs, int n_traj, int entries, do
 size_t tjm_dyn_lds_bytes(int L) { return sizeof(int) * (size_t)(3 * L + 4); }
 
 hipError_t tjm_blocks_per_cu(int mixed, int L, int* blocks) {
-  if (mixed)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, tjm_step_kernel<float>, TJM_NT,
-                                                        tjm_dyn_lds_bytes(L));
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, tjm_step_kernel<double>, TJM_NT,
-                                                      tjm_dyn_lds_bytes(L));
+  return mixed ? tjm_blocks_per_cu_float(L, blocks) : tjm_blocks_per_cu_double(L, blocks);
 }
 
 hipError_t tjm_launch_reset(int* counter, hipStream_t s) {
@@ -76,21 +36,10 @@ hipError_t tjm_launch_reset(int* counter, hipStream_t s) {
 }
 
 hipError_t tjm_launch_step(const TjmParams& P, int k, int workers, hipStream_t s) {
-  const size_t dyn = tjm_dyn_lds_bytes(P.L);
-  if (k == 0) {
-    if (P.mixed)
-      hipLaunchKernelGGL(tjm_init_kernel<float>, dim3(workers), dim3(TJM_NT), dyn, s, P);
-    else
-      hipLaunchKernelGGL(tjm_init_kernel<double>, dim3(workers), dim3(TJM_NT), dyn, s, P);
-  } else if (P.mixed) {
-    hipLaunchKernelGGL(tjm_step_kernel<float>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
-  } else {
-    hipLaunchKernelGGL(tjm_step_kernel<double>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
-  }
-  return hipGetLastError();
+  return P.mixed ? tjm_launch_step_float(P, k, workers, s) : tjm_launch_step_double(P, k, workers, s);
 }
 
-hipError_t tjm_launch_reduce(const double* obs, int n_traj, int entries, double* mean,
+hipError_t tjm_launch_reduce(const double* obs, int n_traj, long entries, double* mean,
                              double* sem, hipStream_t s) {
   const int bs = 256;
   hipLaunchKernelGGL(tjm_reduce_kernel, dim3((entries + bs - 1) / bs), dim3(bs), 0, s, obs, n_traj,
@@ -105,44 +54,34 @@ template <typename T>
 __global__ __launch_bounds__(TJM_NT) void st_cgemm_kernel(int M, int N, int K, int nb, int sum,
     const zd* A, int lda, long bsA, int tA, int cA, const zd* B, int ldb, long bsB, int tB, int cB,
     zd* C, int ldc, long cs, int acc) {
-  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
   blk_cgemm<T>(M, N, K, nb, sum != 0, cmat(A, lda, bsA, tA != 0, cA != 0),
-               cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, gl);
+               cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, tjm_lds.gemm);
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* Q, zd* R) {
-  __shared__ BlkScratch S;
-  __shared__ QrLds H;
-  blk_qr(m, n, X, Q, R, H, S);
+  blk_qr(m, n, X, Q, R);
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_svd_kernel(int m, int n, const zd* G, double discard,
     int cap, double deg_tol, int absorb, zd* left, zd* right, double* Sout, int* kout, zd* Wc, zd* Uc, zd* Tg) {
-  __shared__ BlkScratch S;
-  __shared__ SvdLds SL;
-  __shared__ alignas(16) char gl[SVD_LDS_BYTES > GEMM_LDS_BYTES ? SVD_LDS_BYTES : GEMM_LDS_BYTES];
-  int k = blk_svd(m, n, G, left, right, absorb != 0, discard, cap, deg_tol, Wc, Uc, Tg, SL, S, gl);
+  int k = blk_svd(m, n, G, left, right, absorb != 0, discard, cap, deg_tol, Wc, Uc, Tg);
   if (threadIdx.x == 0) *kout = k;
-  for (int j = threadIdx.x; j < k; j += TJM_NT) Sout[j] = SL.s[SL.order[j]];
+  for (int j = threadIdx.x; j < k; j += TJM_NT) Sout[j] = tjm_lds.sv.s[tjm_lds.sv.order[j]];
 }
 
 struct DenseOp {
   const zd* H;
   int n;
-  void* gl;
-  TJM_DEV void apply(const zd* q, zd* y) {
-    blk_cgemm<double>(n, 1, n, 1, true, cmat(H, n), cmat(q, 1), y, 1, 0, false, gl);
+  TJM_DEVNI void apply(const zd* q, zd* y) {
+    blk_cgemm<double>(n, 1, n, 1, true, cmat(H, n), cmat(q, 1), y, 1, 0, false, tjm_lds.gemm);
     tjm_sync();
   }
 };
 
 __global__ __launch_bounds__(TJM_NT) void st_expm_kernel(int n, const zd* H, zd* v, double t,
     int kmax, double tol, zd* Q, zd* w, int* iters) {
-  __shared__ BlkScratch S;
-  __shared__ LanczosLds Lz;
-  __shared__ alignas(16) char gl[GEMM_LDS_BYTES];
-  DenseOp op{H, n, gl};
-  int it = blk_expm(op, v, n, t, kmax, tol, Q, w, Lz, S);
+  DenseOp op{H, n};
+  int it = blk_expm(op, v, n, t, kmax, tol, Q, w);
   if (threadIdx.x == 0) *iters = it;
 }
 

@@ -22,7 +22,6 @@ struct TjmParams {
   int record_bonds;
   int mixed;                         // 1: complex-FP32 contractions
   int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
-  int sweep_jumps;                   // 1: jump process with the sweeps in the printed order
   double dt, krylov_tol, svd_discard, deg_tol;
   uint64_t seed;
   uint32_t traj_base;                // global id of trajectory 0 of this run
@@ -91,11 +90,11 @@ enum {
   // device-clock ticks (100 MHz) spent by the trajectory's workgroup in:
   TJM_ST_T_TOTAL = 8,     //   the whole step function
   TJM_ST_T_CONTRACT = 9,  //   effective-Hamiltonian and environment contractions
-  TJM_ST_T_ENV = 10,      //   transfer-matrix environment sweeps of the jump process
+  TJM_ST_T_ENV = 10,      //   (unused)
   TJM_ST_T_SVD = 11,      //   SVD factorisations
   TJM_ST_T_QR = 12,       //   QR / LQ factorisations
   TJM_ST_T_EXPM = 13,     //   Lanczos exponentials (including their contractions)
   TJM_ST_T_ABSORB = 14,   //   bond-matrix absorption and two-site products
-  TJM_ST_CMAC_FP64 = 15,  // complex multiply-adds of those environment sweeps (FP64)
+  TJM_ST_CMAC_FP64 = 15,  // (unused)
   TJM_NSTAT = 16
 };

@@ -1,0 +1,66 @@
+// The persistent TJM kernels of one contraction precision.
+//
+// This file is compiled twice, with TJM_TC = float (complex-FP32 matrix-core
+// contractions, the mixed path) and TJM_TC = double (the FP64 path); each
+// object defines the launchers of its own precision.
+//
+// tjm_step_kernel is persistent: a grid of resident workgroups pulls
+// trajectory indices from a device work counter, so trajectories with more
+// work (jumps, larger bonds, more Lanczos iterations) do not stall the
+// others.  One launch applies one step function to every trajectory; the
+// per-trajectory MPS lives in HBM between launches, the environments,
+// Krylov basis and factorisation workspaces are per-workgroup scratch.
+#include <dev_tjm.hpp>
+#include "tjm_internal.h"
+
+#ifndef TJM_TC
+#error "compile with -DTJM_TC=float or -DTJM_TC=double"
+#endif
+
+typedef TJM_TC Tc;
+
+template <typename T>
+__global__ __launch_bounds__(TJM_NT, 2) void tjm_step_kernel(TjmParams P, int k) {
+  extern __shared__ int dyn[];
+  Tjm<T> t(P, dyn, (int)blockIdx.x);
+  for (;;) {
+    if (threadIdx.x == 0) tjm_lds.item = atomicAdd(P.counter, 1);
+    __syncthreads();
+    const int item = tjm_lds.item;
+    __syncthreads();
+    if (item >= P.n_traj) break;
+    t.traj_step(item, k);
+  }
+}
+
+// Psi(0) -> t = 0 observables and Phi = F_0 Psi(0), same work queue
+template <typename T>
+__global__ __launch_bounds__(TJM_NT, 2) void tjm_init_kernel(TjmParams P) {
+  extern __shared__ int dyn[];
+  Tjm<T> t(P, dyn, (int)blockIdx.x);
+  for (;;) {
+    if (threadIdx.x == 0) tjm_lds.item = atomicAdd(P.counter, 1);
+    __syncthreads();
+    const int item = tjm_lds.item;
+    __syncthreads();
+    if (item >= P.n_traj) break;
+    t.traj_init(item);
+  }
+}
+
+#define TJM_CAT2(a, b) a##b
+#define TJM_CAT(a, b) TJM_CAT2(a, b)
+#define TJM_SUFFIX TJM_CAT(_, TJM_TC)
+
+hipError_t TJM_CAT(tjm_blocks_per_cu, TJM_SUFFIX)(int L, int* blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, tjm_step_kernel<Tc>, TJM_NT, tjm_dyn_lds_bytes(L));
+}
+
+hipError_t TJM_CAT(tjm_launch_step, TJM_SUFFIX)(const TjmParams& P, int k, int workers, hipStream_t s) {
+  const size_t dyn = tjm_dyn_lds_bytes(P.L);
+  if (k == 0)
+    hipLaunchKernelGGL(tjm_init_kernel<Tc>, dim3(workers), dim3(TJM_NT), dyn, s, P);
+  else
+    hipLaunchKernelGGL(tjm_step_kernel<Tc>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
+  return hipGetLastError();
+}

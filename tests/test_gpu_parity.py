@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 from paper_2501_17913_amd import models, tjm  # noqa: E402
 from oracle import lindblad, model as om, mps_tjm  # noqa: E402
 from tests import inputs  # noqa: E402
+from tests.oracle_pool import oracle_trajectories  # noqa: E402
 
 
 def log(*a):
@@ -142,15 +143,22 @@ def _large(name, steps, prec, sample):
     assert np.all(res['bonds'][:, :, -1] == 1)
     assert np.all((res['jumps'] >= -1) & (res['jumps'] < 2 * L))
     tol = 1e-10 if prec == tjm.PREC_FP64 else 2e-4
+    t1 = time.time()
+    ref = oracle_trajectories(L, w["chi_max"], w["init"], steps, w["g"], w["gamma"], w["seed"], sample)
+    log("  oracle: %d sampled trajectories in %.1fs" % (len(sample), time.time() - t1))
+    flips, worst = 0, 0.0
     for t in sample:
-        t1 = time.time()
-        ref, jl, bl = oracle_traj(L, w["chi_max"], w["init"], steps, w["g"], w["gamma"], w["seed"], t)
-        log("  oracle trajectory %d in %.1fs" % (t, time.time() - t1))
+        out, jl, bl = ref[t]
         if prec == tjm.PREC_FP64:
             assert list(res['jumps'][t]) == jl
             assert np.array_equal(res['bonds'][t], bl)
-        if list(res['jumps'][t]) == jl:
-            assert np.abs(per[t] - ref).max() < tol
+        if list(res['jumps'][t]) != jl:
+            flips += 1                    # mixed path: a decision within the FP32 error of its threshold
+            continue
+        worst = max(worst, float(np.abs(per[t] - out).max()))
+    log("  sampled: max |gpu - oracle| = %.3e, %d of %d flipped" % (worst, flips, len(sample)))
+    assert flips <= max(1, len(sample) // 8)
+    assert worst < tol
 
 
 def test_c2_launch_fp64_sampled_trajectories():
@@ -158,7 +166,7 @@ def test_c2_launch_fp64_sampled_trajectories():
 
 
 def test_c3_launch_mixed_sampled_trajectories():
-    _large("C3", 2, tjm.PREC_MIXED, (0, 4095))
+    _large("C3", 2, tjm.PREC_MIXED, (0, 1, 2, 3, 1024, 2047, 3000, 4095))
 
 
 def test_fp64_general_initial_mps_parity():
@@ -191,7 +199,8 @@ def test_fp64_general_initial_mps_parity():
 
 
 @pytest.mark.skip(reason="the transfer-environment jump path (sweep_jumps=0) faulted the device once "
-                         "in the mixed L6 chi8 case and its cause is not found yet; it stays off by default")
+                         "in the mixed L6 chi8 case and its cause was never found; the path has been removed "
+                         "and sweep_jumps=0 is rejected with TJM_E_UNSUPPORTED")
 @pytest.mark.parametrize("case", [inputs.small_cases()[4], inputs.small_cases()[6]],
                          ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
 def test_fp64_environment_jump_path_parity(case):
