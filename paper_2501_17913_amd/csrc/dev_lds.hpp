@@ -23,6 +23,14 @@ struct QrLds {
   double a2next;                        // ||column j+1, rows j+1..||^2
 };
 
+// Register-resident QR (m <= 128, n <= 64): the reflector of the current
+// step (two buffers) and per column beta and ||v||^2.
+constexpr int QRF_ROWS = 128, QRF_COLS = 64, QRF_RPT = QRF_ROWS / 4;
+struct QrfLds {
+  zd v[2][QRF_ROWS];
+  double bre[QRF_COLS], bim[QRF_COLS], vn[QRF_COLS];
+};
+
 // Jacobi SVD: singular values, their order, convergence flags.
 constexpr int SVD_LDS_BYTES = 64 * 64 * 16;   // a working matrix of up to 4096 complex doubles
 static_assert(sizeof(QrLds) <= SVD_LDS_BYTES, "the preconditioning QR keeps its reflector in the SVD's LDS");
@@ -51,7 +59,7 @@ constexpr int LDS_WORK_BYTES = GEMM_LDS_BYTES > SVD_LDS_BYTES ? GEMM_LDS_BYTES :
 struct Lds {
   alignas(16) char gemm[LDS_WORK_BYTES];   // GEMM staging, or the SVD working matrix
   BlkScratch S;
-  QrLds qr;
+  union { QrLds qr; QrfLds qrf; };
   SvdLds sv;
   LanczosLds lz;
   unsigned long long st[TJM_NSTAT];

@@ -90,7 +90,7 @@ TJM_DEV void qr_reduce(int m, int n, zd* X, QrLds& H, BlkScratch& S) {
   }
 }
 
-TJM_DEVNI void blk_qr(int m, int n, zd* X, zd* Q, zd* R) {
+TJM_DEVNI void blk_qr_global(int m, int n, zd* X, zd* Q, zd* R) {
   QrLds& H = tjm_lds.qr;
   BlkScratch& S = tjm_lds.S;
   const int k = m < n ? m : n;
@@ -151,6 +151,166 @@ TJM_DEVNI void blk_qr(int m, int n, zd* X, zd* Q, zd* R) {
     if (ab > 0.0) Q[e] = cmk(br / ab, bi / ab) * Q[e];
   }
   tjm_sync();
+}
+
+// --------------------------------------------------------------------------
+// The same Householder QR with the matrix held in registers, for m <= 128
+// rows and n <= 64 columns (every site tensor of a bond of at most 64).
+// Thread t owns column c = t / 4 and the rows g + 4 i (g = t % 4,
+// i < 32) of it; the four threads of a column are neighbouring lanes of one
+// wavefront, so a column's sums are two lane shuffles.  Step j: the owners
+// of column j form its reflector and publish it in LDS, one barrier, and
+// every later column is updated in registers against it; the next step's
+// owners start at once (the reflector buffer alternates, so one barrier per
+// column suffices).  The reflectors also go to V (m x k, global scratch)
+// for the formation of Q, which runs the same way backwards over them on
+// [I; 0] held in the same registers.  Same reflectors, signs and gauge as
+// blk_qr_global (which serves larger shapes).  X may alias Q or R.
+// With adj the matrix factorised is A = X^H for X of n x m (ld m), and the
+// factors are written adjoint: Q^H (k x m, ld m) to Q and R^H (n x k, ld k)
+// to R, plus R itself (k x n) to Rk if it is non-null; this is the LQ
+// X = R^H Q^H of a site tensor without transposed copies.
+// --------------------------------------------------------------------------
+static_assert(TJM_NT == 4 * QRF_COLS, "one column per four threads");
+
+TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool adj, zd* Rk) {
+  QrfLds& H = tjm_lds.qrf;
+  const int tid = tjm_tid();
+  const int c = tid >> 2, g = tid & 3;
+  const int k = m < n ? m : n;
+  const bool live = c < n;
+  zd x[QRF_RPT];
+#pragma unroll
+  for (int i = 0; i < QRF_RPT; ++i) {
+    const int r = g + 4 * i;
+    x[i] = (live && r < m) ? (adj ? conjg(X[(long)c * m + r]) : X[(long)r * n + c]) : cmk(0.0, 0.0);
+  }
+  tjm_sync();                                     // X is read before Q or R may overwrite it
+  for (int j = 0; j < k; ++j) {
+    zd* vb = H.v[j & 1];
+    if (c == j) {
+      // reflector of column j: x0 = X[j][j], beta = -(x0/|x0|) ||x||,
+      // v = x with v0 = x0 - beta, ||v||^2 = 2 ||x|| (||x|| + |x0|)
+      double a2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < QRF_RPT; ++i) {
+        const int r = g + 4 * i;
+        if (r >= j && r < m) { a2 += abs2(x[i]); vb[r] = x[i]; }
+      }
+      a2 += tjm_shfl_xor(a2, 1);
+      a2 += tjm_shfl_xor(a2, 2);
+      __builtin_amdgcn_wave_barrier();
+      const zd x0 = vb[j];                        // written by a lane of this wavefront
+      const double ax0 = sqrt(abs2(x0)), al = sqrt(a2);
+      zd beta = cmk(0.0, 0.0), v0 = x0;
+      double vn = 0.0;
+      if (al > 0.0) {
+        const zd ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+        beta = cmk(-ph.re * al, -ph.im * al);
+        v0 = x0 - beta;
+        vn = 2.0 * al * (al + ax0);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (g == 0) { vb[j] = v0; H.bre[j] = beta.re; H.bim[j] = beta.im; H.vn[j] = vn; }
+#pragma unroll
+      for (int i = 0; i < QRF_RPT; ++i) {
+        const int r = g + 4 * i;
+        if (r >= j && r < m) V[(long)j * m + r] = r == j ? v0 : x[i];
+      }
+    }
+    tjm_sync();
+    if (live && c > j) {
+      const double vn = H.vn[j];
+      if (vn > 0.0) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < QRF_RPT; ++i) {
+          const int r = g + 4 * i;
+          if (r >= j && r < m) { const zd p = cdotc(vb[r], x[i]); sr += p.re; si += p.im; }
+        }
+        sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
+        sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
+        const double f = 2.0 / vn;
+        const zd sc = cmk(f * sr, f * si);
+#pragma unroll
+        for (int i = 0; i < QRF_RPT; ++i) {
+          const int r = g + 4 * i;
+          if (r >= j && r < m) x[i] = x[i] - sc * vb[r];
+        }
+      }
+    }
+  }
+  tjm_sync();                                     // every reflector read; H.v free
+  // R: row r of the upper triangle times conj(ph_r), diagonal |beta_r|
+#pragma unroll
+  for (int i = 0; i < QRF_RPT; ++i) {
+    const int r = g + 4 * i;
+    if (live && r < k) {
+      const double br = H.bre[r], bi = H.bim[r], ab = sqrt(br * br + bi * bi);
+      zd val = cmk(0.0, 0.0);
+      if (r < c) val = ab > 0.0 ? cmk(br / ab, -bi / ab) * x[i] : x[i];
+      else if (r == c) val = ab > 0.0 ? cmk(ab, 0.0) : cmk(br, bi);
+      if (adj) {
+        R[(long)c * k + r] = conjg(val);
+        if (Rk) Rk[(long)r * n + c] = val;
+      } else {
+        R[(long)r * n + c] = val;
+      }
+    }
+  }
+  // Q = H_0 ... H_{k-1} [I; 0], reflectors staged in LDS one step ahead
+  const bool qlive = c < k;
+  zd* q = x;
+#pragma unroll
+  for (int i = 0; i < QRF_RPT; ++i) q[i] = cmk((qlive && g + 4 * i == c) ? 1.0 : 0.0, 0.0);
+  if (k > 0 && tid < m) H.v[(k - 1) & 1][tid] = tid >= k - 1 ? V[(long)(k - 1) * m + tid] : cmk(0.0, 0.0);
+  tjm_sync();
+  for (int j = k - 1; j >= 0; --j) {
+    const zd* vb = H.v[j & 1];
+    zd nxt = cmk(0.0, 0.0);
+    if (j > 0 && tid < m && tid >= j - 1) nxt = V[(long)(j - 1) * m + tid];
+    const double vn = H.vn[j];
+    if (qlive && c >= j && vn > 0.0) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int i = 0; i < QRF_RPT; ++i) {
+        const int r = g + 4 * i;
+        if (r >= j && r < m) { const zd p = cdotc(vb[r], q[i]); sr += p.re; si += p.im; }
+      }
+      sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
+      sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
+      const double f = 2.0 / vn;
+      const zd sc = cmk(f * sr, f * si);
+#pragma unroll
+      for (int i = 0; i < QRF_RPT; ++i) {
+        const int r = g + 4 * i;
+        if (r >= j && r < m) q[i] = q[i] - sc * vb[r];
+      }
+    }
+    if (j > 0 && tid < m) H.v[(j - 1) & 1][tid] = nxt;
+    tjm_sync();
+  }
+  // column c of Q times ph_c
+  if (qlive) {
+    const double br = H.bre[c], bi = H.bim[c], ab = sqrt(br * br + bi * bi);
+    const zd ph = ab > 0.0 ? cmk(br / ab, bi / ab) : cmk(1.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < QRF_RPT; ++i) {
+      const int r = g + 4 * i;
+      if (r < m) {
+        if (adj) Q[(long)c * m + r] = conjg(ph * q[i]);
+        else Q[(long)r * k + c] = ph * q[i];
+      }
+    }
+  }
+  tjm_sync();
+}
+
+// Thin QR X = Q R (k = min(m, n), diag(R) real >= 0) of an m x n matrix,
+// m <= 128; V is m x k scratch.  X is destroyed.
+TJM_DEV void blk_qr(int m, int n, zd* X, zd* Q, zd* R, zd* V) {
+  if (m <= QRF_ROWS && n <= QRF_COLS) blk_qr_regs(m, n, X, Q, R, V, false, nullptr);
+  else blk_qr_global(m, n, X, Q, R);
 }
 
 // --------------------------------------------------------------------------

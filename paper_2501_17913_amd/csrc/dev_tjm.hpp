@@ -201,35 +201,43 @@ template <typename Tc> struct Tjm {
   TJM_DEVNI int qr_site(zd* Ms, int chl, int chr) {
     const unsigned long long t0 = tjm_clock();
     const int m = chl * d;
-    copy(X, Ms, (long)m * chr);
-    tjm_sync();
-    blk_qr(m, chr, X, Ms, Cb);
+    if (m <= QRF_ROWS && chr <= QRF_COLS) {
+      blk_qr_regs(m, chr, Ms, Ms, Cb, Y, false, nullptr);
+    } else {
+      copy(X, Ms, (long)m * chr);
+      tjm_sync();
+      blk_qr_global(m, chr, X, Ms, Cb);
+    }
     count(TJM_ST_FACT, 1ull);
     since(TJM_ST_T_QR, t0);
     return m < chr ? m : chr;
   }
 
   // LQ of M_s as chl x (d chr): M_s <- B (k x d chr, orthonormal rows),
-  // Cb <- C (chl x k); returns k
+  // Cb <- C (chl x k), Z <- C^H (k x chl); returns k
   TJM_DEVNI int lq_site(zd* Ms, int chl, int chr) {
     const unsigned long long t0 = tjm_clock();
     const int n = d * chr;
-    for (long e = tjm_tid(); e < (long)n * chl; e += TJM_NT) {      // X = M^H (n x chl)
-      int i = (int)(e / chl), j = (int)(e % chl);
-      X[e] = conjg(Ms[(long)j * n + i]);
-    }
-    tjm_sync();
-    blk_qr(n, chl, X, Y, Z);                           // Y: n x k, Z: k x chl
     const int k = n < chl ? n : chl;
-    for (long e = tjm_tid(); e < (long)k * n; e += TJM_NT) {        // M = Y^H
-      int i = (int)(e / n), j = (int)(e % n);
-      Ms[e] = conjg(Y[(long)j * k + i]);
+    if (n <= QRF_ROWS && chl <= QRF_COLS) {
+      blk_qr_regs(n, chl, Ms, Ms, Cb, Y, true, Z);                  // QR of M^H, written adjoint
+    } else {
+      for (long e = tjm_tid(); e < (long)n * chl; e += TJM_NT) {    // X = M^H (n x chl)
+        int i = (int)(e / chl), j = (int)(e % chl);
+        X[e] = conjg(Ms[(long)j * n + i]);
+      }
+      tjm_sync();
+      blk_qr_global(n, chl, X, Y, Z);                               // Y: n x k, Z: k x chl
+      for (long e = tjm_tid(); e < (long)k * n; e += TJM_NT) {      // M = Y^H
+        int i = (int)(e / n), j = (int)(e % n);
+        Ms[e] = conjg(Y[(long)j * k + i]);
+      }
+      for (long e = tjm_tid(); e < (long)chl * k; e += TJM_NT) {    // C = Z^H
+        int i = (int)(e / k), j = (int)(e % k);
+        Cb[e] = conjg(Z[(long)j * chl + i]);
+      }
+      tjm_sync();
     }
-    for (long e = tjm_tid(); e < (long)chl * k; e += TJM_NT) {      // C = Z^H
-      int i = (int)(e / k), j = (int)(e % k);
-      Cb[e] = conjg(Z[(long)j * chl + i]);
-    }
-    tjm_sync();
     count(TJM_ST_FACT, 1ull);
     since(TJM_ST_T_QR, t0);
     return k;

@@ -824,11 +824,12 @@ extern "C" tjm_status tjm_selftest_qr(int m, int n, const double* X, double* Q, 
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, TJM_E_DEVICE, "no HIP device");
   const int k = std::min(m, n);
   DevScope ds;
-  double *dX, *dQ, *dR;
+  double *dX, *dQ, *dR, *dV;
   STCHK(ds.put(X, 2L * m * n, &dX));
   STCHK(ds.put((const double*)nullptr, 2L * m * k, &dQ));
   STCHK(ds.put((const double*)nullptr, 2L * k * n, &dR));
-  STCHK(tjm_launch_st_qr(m, n, dX, dQ, dR));
+  STCHK(ds.put((const double*)nullptr, 2L * m * k, &dV));
+  STCHK(tjm_launch_st_qr(m, n, dX, dQ, dR, dV));
   STCHK(hipDeviceSynchronize());
   STCHK(hipMemcpy(Q, dQ, 2L * m * k * 8, hipMemcpyDeviceToHost));
   STCHK(hipMemcpy(R, dR, 2L * k * n * 8, hipMemcpyDeviceToHost));

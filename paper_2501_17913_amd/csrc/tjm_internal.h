@@ -23,7 +23,7 @@ hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_b
                                const double* A, int lda, long bsA, int transA, int conjA,
                                const double* B, int ldb, long bsB, int transB, int conjB,
                                double* C, int ldc, long csC, int accumulate);
-hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R);
+hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R, double* V);
 hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                              int absorb_left, double* left, double* right, double* S, int* k,
                              double* Wc, double* Uc, double* Tg);

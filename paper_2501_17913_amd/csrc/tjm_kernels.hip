@@ -58,8 +58,8 @@ __global__ __launch_bounds__(TJM_NT) void st_cgemm_kernel(int M, int N, int K, i
                cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, tjm_lds.gemm);
 }
 
-__global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* Q, zd* R) {
-  blk_qr(m, n, X, Q, R);
+__global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* Q, zd* R, zd* V) {
+  blk_qr(m, n, X, Q, R, V);
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_svd_kernel(int m, int n, const zd* G, double discard,
@@ -120,8 +120,8 @@ hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_b
   return hipGetLastError();
 }
 
-hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R) {
-  hipLaunchKernelGGL(st_qr_kernel, dim3(1), dim3(TJM_NT), 0, 0, m, n, (zd*)X, (zd*)Q, (zd*)R);
+hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R, double* V) {
+  hipLaunchKernelGGL(st_qr_kernel, dim3(1), dim3(TJM_NT), 0, 0, m, n, (zd*)X, (zd*)Q, (zd*)R, (zd*)V);
   return hipGetLastError();
 }
 

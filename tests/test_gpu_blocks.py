@@ -66,7 +66,8 @@ def test_cgemm_batched_and_accumulate(prec, sum_batches):
 
 
 @pytest.mark.parametrize("m,n,r", [(2, 1, 1), (8, 6, 6), (12, 6, 3), (6, 8, 6), (128, 64, 64),
-                                   (64, 128, 64), (128, 64, 20), (1, 1, 1)])
+                                   (64, 128, 64), (128, 64, 20), (1, 1, 1), (128, 64, 0), (100, 50, 50),
+                                   (3, 64, 3), (128, 1, 1), (127, 63, 63), (128, 128, 100)])
 def test_qr(m, n, r):
     X = cr(m, r) @ cr(r, n)
     Q, R = tjm.selftest_qr(X)
