@@ -90,6 +90,13 @@ typedef struct {
                              delta p, LQ sweep for the weights, QR moves to
                              the jump site); any other value is rejected
                              with TJM_E_UNSUPPORTED                           */
+  int generic_heff;       /* 0 (default): effective Hamiltonians of
+                             nearest-neighbour MPOs as two single products
+                             (left and right environment) plus a local term,
+                             using the identity channels of canonical
+                             environments; 1: always the generic contraction
+                             L x W x M x R through a (D chi d chi)
+                             intermediate.  Same operator, other rounding.  */
 } tjm_options;
 
 typedef struct {

@@ -23,6 +23,13 @@ template <typename T, typename S> TJM_DEV cplx<T> ccast(cplx<S> a) { return cmk(
 typedef cplx<double> zd;
 typedef cplx<float> zf;
 
+// c ? a : b on complex values, as two scalar selects (a conditional on
+// struct lvalues becomes a select of addresses, which keeps a register
+// array in scratch memory)
+template <typename T> TJM_DEV cplx<T> csel(bool c, cplx<T> a, cplx<T> b) {
+  return cmk(c ? a.re : b.re, c ? a.im : b.im);
+}
+
 // LDS scratch every workgroup routine may use for reductions and broadcasts.
 struct BlkScratch {
   double red[TJM_NWAVE * 4];

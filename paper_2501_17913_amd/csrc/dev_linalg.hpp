@@ -173,6 +173,43 @@ TJM_DEVNI void blk_qr_global(int m, int n, zd* X, zd* Q, zd* R) {
 // --------------------------------------------------------------------------
 static_assert(TJM_NT == 4 * QRF_COLS, "one column per four threads");
 
+// One reflector application to a column held in registers (rows g + 4 i,
+// i < QRF_RPT): x <- x - (2/vn) (v^H x) v over the rows r >= j, r < m; the
+// four threads of the column reduce the product by two shuffles.  Branch
+// free: every row's v is read (the buffer has 128 rows; rows outside
+// [j, m) may hold stale values) and masked by a select; the reads are taken
+// in chunks of eight rows with a scheduling barrier between chunks, so that
+// at most eight of them are live next to the 32 register-resident entries.
+TJM_DEV void qrf_reflect(zd* x, const zd* vb, int j, int m, int g, double vn) {
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
+#pragma unroll
+    for (int i = i0; i < i0 + 8; ++i) {
+      const int r = g + 4 * i;
+      const bool on = r >= j && r < m;
+      const zd p = cdotc(vb[r], x[i]);
+      sr += on ? p.re : 0.0;
+      si += on ? p.im : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
+  sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
+  const double f = 2.0 / vn;
+  const zd sc = cmk(f * sr, f * si);
+#pragma unroll
+  for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
+#pragma unroll
+    for (int i = i0; i < i0 + 8; ++i) {
+      const int r = g + 4 * i;
+      const bool on = r >= j && r < m;
+      x[i] = csel(on, x[i] - sc * vb[r], x[i]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool adj, zd* Rk) {
   QrfLds& H = tjm_lds.qrf;
   const int tid = tjm_tid();
@@ -183,7 +220,9 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
 #pragma unroll
   for (int i = 0; i < QRF_RPT; ++i) {
     const int r = g + 4 * i;
-    x[i] = (live && r < m) ? (adj ? conjg(X[(long)c * m + r]) : X[(long)r * n + c]) : cmk(0.0, 0.0);
+    zd e = cmk(0.0, 0.0);
+    if (live && r < m) e = adj ? conjg(X[(long)c * m + r]) : X[(long)r * n + c];
+    x[i] = e;
   }
   tjm_sync();                                     // X is read before Q or R may overwrite it
   for (int j = 0; j < k; ++j) {
@@ -191,11 +230,14 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     if (c == j) {
       // reflector of column j: x0 = X[j][j], beta = -(x0/|x0|) ||x||,
       // v = x with v0 = x0 - beta, ||v||^2 = 2 ||x|| (||x|| + |x0|)
+      // the whole column goes to the buffer (rows above j hold finished R
+      // entries and rows from m on zeros; the readers mask rows < j)
       double a2 = 0.0;
 #pragma unroll
       for (int i = 0; i < QRF_RPT; ++i) {
         const int r = g + 4 * i;
-        if (r >= j && r < m) { a2 += abs2(x[i]); vb[r] = x[i]; }
+        a2 += r >= j ? abs2(x[i]) : 0.0;
+        vb[r] = x[i];
       }
       a2 += tjm_shfl_xor(a2, 1);
       a2 += tjm_shfl_xor(a2, 2);
@@ -215,29 +257,13 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
 #pragma unroll
       for (int i = 0; i < QRF_RPT; ++i) {
         const int r = g + 4 * i;
-        if (r >= j && r < m) V[(long)j * m + r] = r == j ? v0 : x[i];
+        if (r >= j && r < m) V[(long)j * m + r] = csel(r == j, v0, x[i]);
       }
     }
     tjm_sync();
     if (live && c > j) {
       const double vn = H.vn[j];
-      if (vn > 0.0) {
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int i = 0; i < QRF_RPT; ++i) {
-          const int r = g + 4 * i;
-          if (r >= j && r < m) { const zd p = cdotc(vb[r], x[i]); sr += p.re; si += p.im; }
-        }
-        sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
-        sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
-        const double f = 2.0 / vn;
-        const zd sc = cmk(f * sr, f * si);
-#pragma unroll
-        for (int i = 0; i < QRF_RPT; ++i) {
-          const int r = g + 4 * i;
-          if (r >= j && r < m) x[i] = x[i] - sc * vb[r];
-        }
-      }
+      if (vn > 0.0) qrf_reflect(x, vb, j, m, g, vn);
     }
   }
   tjm_sync();                                     // every reflector read; H.v free
@@ -247,9 +273,9 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     const int r = g + 4 * i;
     if (live && r < k) {
       const double br = H.bre[r], bi = H.bim[r], ab = sqrt(br * br + bi * bi);
-      zd val = cmk(0.0, 0.0);
-      if (r < c) val = ab > 0.0 ? cmk(br / ab, -bi / ab) * x[i] : x[i];
-      else if (r == c) val = ab > 0.0 ? cmk(ab, 0.0) : cmk(br, bi);
+      const zd ph = ab > 0.0 ? cmk(br / ab, -bi / ab) : cmk(1.0, 0.0);
+      const zd dg = ab > 0.0 ? cmk(ab, 0.0) : cmk(br, bi);
+      const zd val = csel(r < c, ph * x[i], csel(r == c, dg, cmk(0.0, 0.0)));
       if (adj) {
         R[(long)c * k + r] = conjg(val);
         if (Rk) Rk[(long)r * n + c] = val;
@@ -270,23 +296,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     zd nxt = cmk(0.0, 0.0);
     if (j > 0 && tid < m && tid >= j - 1) nxt = V[(long)(j - 1) * m + tid];
     const double vn = H.vn[j];
-    if (qlive && c >= j && vn > 0.0) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int i = 0; i < QRF_RPT; ++i) {
-        const int r = g + 4 * i;
-        if (r >= j && r < m) { const zd p = cdotc(vb[r], q[i]); sr += p.re; si += p.im; }
-      }
-      sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
-      sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
-      const double f = 2.0 / vn;
-      const zd sc = cmk(f * sr, f * si);
-#pragma unroll
-      for (int i = 0; i < QRF_RPT; ++i) {
-        const int r = g + 4 * i;
-        if (r >= j && r < m) q[i] = q[i] - sc * vb[r];
-      }
-    }
+    if (qlive && c >= j && vn > 0.0) qrf_reflect(q, vb, j, m, g, vn);
     if (j > 0 && tid < m) H.v[(j - 1) & 1][tid] = nxt;
     tjm_sync();
   }

@@ -40,6 +40,34 @@ template <typename S> TJM_DEV CMat<S> cmat(const cplx<S>* p, int ld, long bs = 0
   CMat<S> m; m.p = p; m.ld = ld; m.bs = bs; m.trans = trans; m.conj = conj; return m;
 }
 
+// A stack of row-major matrices (ld, consecutive matrices cs elements
+// apart) of which batch b takes matrix chan[b]: the channels of an
+// environment that one class of effective-Hamiltonian terms uses.
+template <typename S> struct ChanMat {
+  const cplx<S>* p;
+  int ld;
+  long cs;
+  const int* chan;
+  bool trans;
+  template <typename T> TJM_DEV cplx<T> get(int b, int i, int k) const {
+    const cplx<S> v = p[(long)chan[b] * cs + (long)i * ld + k];
+    return cmk((T)v.re, (T)v.im);
+  }
+  template <typename T, int NE>
+  TJM_DEV void gather(int b, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+    const cplx<S>* base = p + (long)chan[b] * cs;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const cplx<S> v = ok[u] ? base[(long)ii[u] * ld + kk[u]] : cmk((S)0, (S)0);
+      out[u] = cmk((T)v.re, (T)v.im);
+    }
+  }
+};
+
+template <typename S> TJM_DEV ChanMat<S> chan_mat(const cplx<S>* p, int ld, long cs, const int* chan) {
+  ChanMat<S> m; m.p = p; m.ld = ld; m.cs = cs; m.chan = chan; m.trans = false; return m;
+}
+
 // sum over the nonzeros (wi, si, v) of one mixing row of v * x(wi, si)
 template <typename T, typename S>
 TJM_DEV cplx<T> mix_row(const int* rp, const MixEnt* ent, int row, const cplx<S>* base, long sw, long ss) {

@@ -108,12 +108,60 @@ template <typename Tc> struct Tjm {
   // ------------------------------------------------------------------
   // Effective Hamiltonians as matrix-free products (Fig. TDVP)
   // ------------------------------------------------------------------
+  // Structured products (nearest-neighbour MPO, canonical environments):
+  //   y = sum_{b<nL} L[chanL_b] (O_b M) + sum_{b<nR} (O'_b M) R[chanR_b] + Oloc M
+  // with M = q[a][s][c] (s < dp), the physical mixings O of each class as
+  // CSR rows (see TjmParams), Oloc the local term.  The identity channels
+  // of L and R are never read.
+  TJM_DEV void heff_struct(const zd* q, zd* y, int chl, int chr, int dp, const zc* Le, const zc* Re,
+                           const int* ptrL, const int* ptrR, const int* chanL, const int* chanR, int nL, int nR,
+                           const double* loc) {
+    const int Dm = P.Dmax;
+    bool acc = false;
+    if (nL > 0) {      // left class: (chl x chl) . (chl x dp chr), summed over channels
+      blk_cgemm<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
+                    mix_cols(q, ptrL, P.mixL, dp, chr, 0L, (long)dp * chr, (long)chr), y, dp * chr, 0, false,
+                    tjm_lds.gemm);
+      acc = true;
+    }
+    if (nR > 0) {      // right class: (chl dp x chr) . (chr x chr), summed over channels
+      blk_cgemm<Tc>(chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
+                    chan_mat(Re, chr, (long)chr * chr, chanR), y, chr, 0, acc, tjm_lds.gemm);
+      acc = true;
+    }
+    // local term in FP64: y[a][s'][c] += sum_s Oloc[s'][s] q[a][s][c]
+    const zd* O = (const zd*)loc;
+    const long n = (long)chl * chr;
+    for (long e = tjm_tid(); e < n; e += TJM_NT) {
+      const int a = (int)(e / chr), c = (int)(e % chr);
+      zd in[4];
+      for (int s = 0; s < dp; ++s) in[s] = q[((long)a * dp + s) * chr + c];
+      for (int so = 0; so < dp; ++so) {
+        zd v = acc ? y[((long)a * dp + so) * chr + c] : cmk(0.0, 0.0);
+        for (int s = 0; s < dp; ++s) v = v + O[so * dp + s] * in[s];
+        y[((long)a * dp + so) * chr + c] = v;
+      }
+    }
+    tjm_sync();
+    count(TJM_ST_CMAC_MFMA, (unsigned long long)nL * chl * chl * dp * chr + (unsigned long long)nR * chl * dp * chr * chr);
+    count(TJM_ST_CMAC_MIX, (unsigned long long)(ptrL[Dm * dp] - ptrL[0] + ptrR[Dm * dp] - ptrR[0]) * chl * chr);
+  }
+
   struct H1 {            // site s: degree-6 network
     Tjm* t; int s, chl, chr; const zc* Le; const zc* Re;
     TJM_DEVNI void apply(const zd* q, zd* y) {
       const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
+      if (P.structured) {
+        const int Dm = P.Dmax;
+        const int* rp = P.s1_ptr + (long)s * 2 * (Dm * d + 1);
+        t->heff_struct(q, y, chl, chr, d, Le, Re, rp, rp + (Dm * d + 1), P.s1_chan + (long)s * 2 * Dm,
+                       P.s1_chan + ((long)s * 2 + 1) * Dm, P.s1_n[2 * s], P.s1_n[2 * s + 1],
+                       P.s1_loc + (long)s * d * d * 2);
+        t->since(TJM_ST_T_CONTRACT, t0);
+        return;
+      }
       const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
       blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
                     t->T1, d * chr, (long)chl * d * chr, false, tjm_lds.gemm);
@@ -134,6 +182,15 @@ template <typename Tc> struct Tjm {
       const unsigned long long t0 = tjm_clock();
       const TjmParams& P = t->P;
       const int d = t->d, d2 = d * d, Dl = P.mpoD[s], Dr = P.mpoD[s + 2];
+      if (P.structured) {
+        const int Dm = P.Dmax;
+        const int* rp = P.s2_ptr + (long)s * 2 * (Dm * d2 + 1);
+        t->heff_struct(q, y, chl, chr, d2, Le, Re, rp, rp + (Dm * d2 + 1), P.s2_chan + (long)s * 2 * Dm,
+                       P.s2_chan + ((long)s * 2 + 1) * Dm, P.s2_n[2 * s], P.s2_n[2 * s + 1],
+                       P.s2_loc + (long)s * d2 * d2 * 2);
+        t->since(TJM_ST_T_CONTRACT, t0);
+        return;
+      }
       const int* rp = P.mix2_ptr + (long)s * (P.Dmax * d2 + 1);
       blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
                     t->T1, d2 * chr, (long)chl * d2 * chr, false, tjm_lds.gemm);
@@ -149,9 +206,31 @@ template <typename Tc> struct Tjm {
   };
 
   struct H0 {            // bond b: degree-4 network, C is kl x kr
-    Tjm* t; int D, kl, kr; const zc* Le; const zc* Re;
+    Tjm* t; int b, kl, kr; const zc* Le; const zc* Re;
     TJM_DEVNI void apply(const zd* q, zd* y) {
       const unsigned long long t0 = tjm_clock();
+      const TjmParams& P = t->P;
+      const int D = P.mpoD[b];
+      if (P.structured) {
+        // y = C R[st] + L[en] C + sum_{other w} (L[w] C) R[w]
+        const int st = P.env_st[b], en = P.env_en[b], nlr = P.lr_n[b];
+        const int* lr = P.lr_chan + (long)b * P.Dmax;
+        blk_cgemm<Tc>(kl, kr, kr, 1, true, cmat(q, kr), cmat(Re + (long)st * kr * kr, kr), y, kr, 0, false,
+                      tjm_lds.gemm);
+        blk_cgemm<Tc>(kl, kr, kl, 1, true, cmat(Le + (long)en * kl * kl, kl), cmat(q, kr), y, kr, 0, true,
+                      tjm_lds.gemm);
+        if (nlr > 0) {
+          blk_cgemm<Tc>(kl, kr, kl, nlr, false, chan_mat(Le, kl, (long)kl * kl, lr), cmat(q, kr),
+                        t->T1, kr, (long)kl * kr, false, tjm_lds.gemm);
+          tjm_sync();
+          blk_cgemm<Tc>(kl, kr, kr, nlr, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
+                        chan_mat(Re, kr, (long)kr * kr, lr), y, kr, 0, true, tjm_lds.gemm);
+        }
+        tjm_sync();
+        t->count(TJM_ST_CMAC_MFMA, (unsigned long long)(1 + nlr) * kl * kr * (kl + kr));
+        t->since(TJM_ST_T_CONTRACT, t0);
+        return;
+      }
       blk_cgemm<Tc>(kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
                     t->T1, kr, (long)kl * kr, false, tjm_lds.gemm);
       tjm_sync();
@@ -406,7 +485,7 @@ template <typename Tc> struct Tjm {
         expm(op, Ms, chl * d * chm, tau);
         const int k = qr_site(Ms, chl, chm);
         lupdate(s, Ms, chl, k, envp(s), spare());
-        H0 op0{this, P.mpoD[s + 1], k, chm, spare(), envp(s + 1)};
+        H0 op0{this, s + 1, k, chm, spare(), envp(s + 1)};
         expm(op0, Cb, k * chm, -tau);
         if (tjm_tid() == 0) {
           int t = slot[s + 1]; slot[s + 1] = slot[L + 1]; slot[L + 1] = t;
@@ -454,7 +533,7 @@ template <typename Tc> struct Tjm {
         expm(op, Ms, chl * d * chr, tau);
         const int k = lq_site(Ms, chl, chr);
         rupdate(s, Ms, k, chr, envp(s + 1), spare());
-        H0 op0{this, P.mpoD[s], chl, k, envp(s), spare()};
+        H0 op0{this, s, chl, k, envp(s), spare()};
         expm(op0, Cb, chl * k, -tau);
         if (tjm_tid() == 0) {
           int t = slot[s]; slot[s] = slot[L + 1]; slot[L + 1] = t;

@@ -90,6 +90,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->device = 0;
   o->certify_sweeps = -1;
   o->sweep_jumps = 1;
+  o->generic_heff = 0;
 }
 
 extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
@@ -250,6 +251,9 @@ struct Plan {
   long n = 0;
   std::vector<MixEnt> ents;
   std::vector<int> mixL_ptr, mixR_ptr, mix2_ptr, jptr, jidx, optr, oidx, bcap;
+  // structured effective Hamiltonians (see the structure section of plan_run)
+  std::vector<int> sptr1, schan1, sn1, sptr2, schan2, sn2, env_st, env_en, lr_chan, lr_n;
+  std::vector<double> sloc1, sloc2;
   std::vector<double> Dh, Df, jopd, initd, obsd, init_t;
   std::vector<long> soff;
   double per_traj = 0;       // device bytes per trajectory (MPS, logs, outputs)
@@ -357,6 +361,155 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
             if (v != cd(0, 0)) push(wl, s1 * d + s2, v);
           }
     }
+  }
+
+  // ---- structure of the effective Hamiltonians -------------------------------
+  // With the sites left of bond b left-canonical, the left environment L_b
+  // has a channel st[b] that is exactly the identity (the channel that has
+  // only carried W's identity blocks from the left boundary); with the sites
+  // right of b right-canonical, R_b has such a channel en[b].  Every block
+  // O = W[wl][wr] of a one- or two-site operator then falls in one class:
+  //   wl = st, wr = en : O M                        (local)
+  //   wl = st          : (O M) R[wr]                (right class)
+  //   wr = en          : L[wl] (O M)                (left class)
+  //   otherwise        : L[wl] (O M) R[wr]          (two-sided)
+  // A nearest-neighbour Hamiltonian has no two-sided block, so H^eff M is
+  // two single products, L-side and R-side, plus a local term: no
+  // intermediate tensor of D chi d chi elements.  The bond operator keeps
+  // its two-sided channels (L[w] C R[w]).  If a site has a two-sided block
+  // or an environment has no identity channel, the generic three-stage
+  // contraction is used everywhere (structured = 0).
+  {
+    auto& st = pl.env_st; auto& en = pl.env_en;
+    st.assign(L + 1, -1); en.assign(L + 1, -1);
+    auto blk = [&](int s, int wl, int wr, int so, int si) {
+      const int Dr = m->mpoD[s + 1];
+      return m->W[s][(((long)wl * Dr + wr) * d + so) * d + si];
+    };
+    auto is_id = [&](int s, int wl, int wr) {
+      for (int so = 0; so < d; ++so)
+        for (int si = 0; si < d; ++si)
+          if (blk(s, wl, wr, so, si) != (so == si ? cd(1, 0) : cd(0, 0))) return false;
+      return true;
+    };
+    auto is_zero = [&](int s, int wl, int wr) {
+      for (int so = 0; so < d; ++so)
+        for (int si = 0; si < d; ++si)
+          if (blk(s, wl, wr, so, si) != cd(0, 0)) return false;
+      return true;
+    };
+    st[0] = 0;
+    for (int s = 0; s < L && st[s] >= 0; ++s) {
+      const int Dl = m->mpoD[s], Dr = m->mpoD[s + 1];
+      for (int wr = 0; wr < Dr && st[s + 1] < 0; ++wr) {
+        bool ok = is_id(s, st[s], wr);
+        for (int wl = 0; wl < Dl && ok; ++wl) ok = wl == st[s] || is_zero(s, wl, wr);
+        if (ok) st[s + 1] = wr;
+      }
+    }
+    en[L] = 0;
+    for (int s = L - 1; s >= 0 && en[s + 1] >= 0; --s) {
+      const int Dl = m->mpoD[s], Dr = m->mpoD[s + 1];
+      for (int wl = 0; wl < Dl && en[s] < 0; ++wl) {
+        bool ok = is_id(s, wl, en[s + 1]);
+        for (int wr = 0; wr < Dr && ok; ++wr) ok = wr == en[s + 1] || is_zero(s, wl, wr);
+        if (ok) en[s] = wl;
+      }
+    }
+    bool structured = true;
+    // one (dp = d) and two (dp = d^2) site operators: per site a left-class
+    // and a right-class list of channels with the physical mixing of each,
+    // as CSR rows (batch b, s_out) -> (0, s_in, value), and the local term
+    auto classify = [&](int nsite, int s, std::vector<int>& ptr, std::vector<int>& chan, std::vector<int>& cnt,
+                        std::vector<double>& loc) {
+      const int dp = nsite == 1 ? d : d * d;
+      const int Dl = m->mpoD[s], Dr = m->mpoD[s + nsite];
+      const int sl = st[s], er = en[s + nsite];
+      if (sl < 0 || er < 0) { structured = false; return; }
+      // the dp x dp block (wl, wr) of the operator
+      auto op = [&](int wl, int wr, int so, int si) {
+        if (nsite == 1) return blk(s, wl, wr, so, si);
+        cd v = 0;
+        const int s1o = so / d, s2o = so % d, s1 = si / d, s2 = si % d;
+        for (int u = 0; u < m->mpoD[s + 1]; ++u) {
+          const int Du = m->mpoD[s + 1];
+          v += m->W[s][(((long)wl * Du + u) * d + s1o) * d + s1] *
+               m->W[s + 1][(((long)u * Dr + wr) * d + s2o) * d + s2];
+        }
+        return v;
+      };
+      auto nonzero = [&](int wl, int wr) {
+        for (int so = 0; so < dp; ++so)
+          for (int si = 0; si < dp; ++si)
+            if (op(wl, wr, so, si) != cd(0, 0)) return true;
+        return false;
+      };
+      double* lo = &loc[(size_t)s * dp * dp * 2];
+      int* pL = &ptr[((size_t)s * 2 + 0) * (Dm * dp + 1)];
+      int* pR = &ptr[((size_t)s * 2 + 1) * (Dm * dp + 1)];
+      int* cL = &chan[((size_t)s * 2 + 0) * Dm];
+      int* cR = &chan[((size_t)s * 2 + 1) * Dm];
+      int nL = 0, nR = 0;
+      std::vector<int> wls, wrs;
+      for (int wl = 0; wl < Dl; ++wl)
+        for (int wr = 0; wr < Dr; ++wr) {
+          if (!nonzero(wl, wr)) continue;
+          if (wl == sl && wr == er) {
+            for (int so = 0; so < dp; ++so)
+              for (int si = 0; si < dp; ++si) {
+                lo[2 * (so * dp + si)] += op(wl, wr, so, si).real();
+                lo[2 * (so * dp + si) + 1] += op(wl, wr, so, si).imag();
+              }
+          } else if (wl == sl) {
+            wrs.push_back(wr);
+          } else if (wr == er) {
+            wls.push_back(wl);
+          } else {
+            structured = false;
+          }
+        }
+      // left class: batch b is channel wls[b] of L, mixing W[wls[b]][er]
+      for (int b = 0; b < (int)wls.size(); ++b) cL[nL++] = wls[b];
+      for (int row = 0; row <= Dm * dp; ++row) {
+        pL[row] = (int)ents.size();
+        if (row == Dm * dp || row / dp >= nL) continue;
+        const int wl = cL[row / dp], so = row % dp;
+        for (int si = 0; si < dp; ++si)
+          if (op(wl, er, so, si) != cd(0, 0)) push(0, si, op(wl, er, so, si));
+      }
+      for (int b = 0; b < (int)wrs.size(); ++b) cR[nR++] = wrs[b];
+      for (int row = 0; row <= Dm * dp; ++row) {
+        pR[row] = (int)ents.size();
+        if (row == Dm * dp || row / dp >= nR) continue;
+        const int wr = cR[row / dp], so = row % dp;
+        for (int si = 0; si < dp; ++si)
+          if (op(sl, wr, so, si) != cd(0, 0)) push(0, si, op(sl, wr, so, si));
+      }
+      cnt[(size_t)s * 2 + 0] = nL;
+      cnt[(size_t)s * 2 + 1] = nR;
+    };
+    const int L2 = std::max(L - 1, 1);
+    pl.sptr1.assign((size_t)L * 2 * (Dm * d + 1), 0);
+    pl.schan1.assign((size_t)L * 2 * Dm, 0);
+    pl.sn1.assign((size_t)L * 2, 0);
+    pl.sloc1.assign((size_t)L * d * d * 2, 0.0);
+    pl.sptr2.assign((size_t)L2 * 2 * (Dm * d * d + 1), 0);
+    pl.schan2.assign((size_t)L2 * 2 * Dm, 0);
+    pl.sn2.assign((size_t)L2 * 2, 0);
+    pl.sloc2.assign((size_t)L2 * d * d * d * d * 2, 0.0);
+    for (int s = 0; s < L && structured; ++s) classify(1, s, pl.sptr1, pl.schan1, pl.sn1, pl.sloc1);
+    for (int s = 0; s + 1 < L && structured; ++s) classify(2, s, pl.sptr2, pl.schan2, pl.sn2, pl.sloc2);
+    // bond operators: the channels of bond b other than st[b] and en[b]
+    pl.lr_chan.assign((size_t)(L + 1) * Dm, 0);
+    pl.lr_n.assign(L + 1, 0);
+    for (int b = 1; b < L && structured; ++b) {
+      if (st[b] < 0 || en[b] < 0) { structured = false; break; }
+      int n2 = 0;
+      for (int w = 0; w < m->mpoD[b]; ++w)
+        if (w != st[b] && w != en[b]) pl.lr_chan[(size_t)b * Dm + n2++] = w;
+      pl.lr_n[b] = n2;
+    }
+    P.structured = structured && !opt.generic_heff ? 1 : 0;
   }
 
   // ---- dissipators, jumps, observables ------------------------------------
@@ -497,6 +650,9 @@ tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int 
   long w = 1;
   if ((st = plan_workers(m, pl, opt, &w)) != TJM_OK) return st;
   double b = vec_bytes(pl.ents) + vec_bytes(pl.mixL_ptr) + vec_bytes(pl.mixR_ptr) + vec_bytes(pl.mix2_ptr) +
+             vec_bytes(pl.sptr1) + vec_bytes(pl.schan1) + vec_bytes(pl.sn1) + vec_bytes(pl.sloc1) +
+             vec_bytes(pl.sptr2) + vec_bytes(pl.schan2) + vec_bytes(pl.sn2) + vec_bytes(pl.sloc2) +
+             vec_bytes(pl.env_st) + vec_bytes(pl.env_en) + vec_bytes(pl.lr_chan) + vec_bytes(pl.lr_n) +
              vec_bytes(pl.Dh) + vec_bytes(pl.Df) + vec_bytes(pl.jopd) + vec_bytes(m->jrate) +
              vec_bytes(m->jsite) + vec_bytes(pl.jptr) + vec_bytes(pl.jidx) + vec_bytes(pl.optr) +
              vec_bytes(pl.oidx) + vec_bytes(pl.obsd) + vec_bytes(pl.initd) + vec_bytes(pl.init_t) +
@@ -566,6 +722,18 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   RCHK(upload(r, pl.mixL_ptr, (int**)&P.mixL_ptr));
   RCHK(upload(r, pl.mixR_ptr, (int**)&P.mixR_ptr));
   RCHK(upload(r, pl.mix2_ptr, (int**)&P.mix2_ptr));
+  RCHK(upload(r, pl.sptr1, (int**)&P.s1_ptr));
+  RCHK(upload(r, pl.schan1, (int**)&P.s1_chan));
+  RCHK(upload(r, pl.sn1, (int**)&P.s1_n));
+  RCHK(upload(r, pl.sloc1, (double**)&P.s1_loc));
+  RCHK(upload(r, pl.sptr2, (int**)&P.s2_ptr));
+  RCHK(upload(r, pl.schan2, (int**)&P.s2_chan));
+  RCHK(upload(r, pl.sn2, (int**)&P.s2_n));
+  RCHK(upload(r, pl.sloc2, (double**)&P.s2_loc));
+  RCHK(upload(r, pl.env_st, (int**)&P.env_st));
+  RCHK(upload(r, pl.env_en, (int**)&P.env_en));
+  RCHK(upload(r, pl.lr_chan, (int**)&P.lr_chan));
+  RCHK(upload(r, pl.lr_n, (int**)&P.lr_n));
   RCHK(upload(r, pl.Dh, (double**)&P.Dhalf));
   RCHK(upload(r, pl.Df, (double**)&P.Dfull));
   RCHK(upload(r, pl.jopd, (double**)&P.jump_op));

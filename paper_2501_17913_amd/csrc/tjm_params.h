@@ -34,6 +34,22 @@ struct TjmParams {
   const MixEnt* mixR;
   const int* mix2_ptr;               // [L-1][Dmax*d*d+1]  rows w''*d*d+s1'*d+s2' -> (w, s1*d+s2)
   const MixEnt* mix2;
+  // structured effective Hamiltonians (structured = 1): per site s and class
+  // c (0 = left, 1 = right) the channels of that class and the CSR mixing
+  // rows (batch b, s_out) -> (0, s_in, value); local terms [s][dp][dp]
+  int structured;
+  const int* s1_ptr;                 // [L][2][Dmax*d+1]
+  const int* s1_chan;                // [L][2][Dmax]
+  const int* s1_n;                   // [L][2]
+  const double* s1_loc;              // [L][d][d] complex
+  const int* s2_ptr;                 // [L-1][2][Dmax*d*d+1]
+  const int* s2_chan;                // [L-1][2][Dmax]
+  const int* s2_n;                   // [L-1][2]
+  const double* s2_loc;              // [L-1][d*d][d*d] complex
+  const int* env_st;                 // [L+1] identity channel of L_b (left-canonical left part)
+  const int* env_en;                 // [L+1] identity channel of R_b (right-canonical right part)
+  const int* lr_chan;                // [L+1][Dmax] the other channels of bond b
+  const int* lr_n;                   // [L+1]
   const double* Dhalf;               // [L][d][d] complex: D_l[dt/2]
   const double* Dfull;               // [L][d][d] complex: D_l[dt]
   const double* jump_op;             // [n_jump][d][d] complex

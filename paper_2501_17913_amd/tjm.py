@@ -34,7 +34,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("chi_cap", C.c_int), ("svd_discard", C.c_double),
                 ("krylov_max", C.c_int), ("krylov_tol", C.c_double), ("deg_tol", C.c_double),
                 ("workers", C.c_int), ("record_bonds", C.c_int), ("traj_base", C.c_uint32),
-                ("device", C.c_int), ("certify_sweeps", C.c_int), ("sweep_jumps", C.c_int)]
+                ("device", C.c_int), ("certify_sweeps", C.c_int), ("sweep_jumps", C.c_int),
+                ("generic_heff", C.c_int)]
 
 
 class Stats(C.Structure):

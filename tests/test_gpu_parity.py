@@ -88,6 +88,30 @@ def test_fp64_certified_sweeps_parity(case):
     assert worst < 1e-8
 
 
+@pytest.mark.parametrize("prec", [tjm.PREC_FP64, tjm.PREC_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("case", [inputs.small_cases()[2], inputs.small_cases()[5]],
+                         ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
+def test_generic_effective_hamiltonian_parity(case, prec):
+    # the generic three-stage contraction L x W x M x R (any MPO), which the
+    # nearest-neighbour XXX chain otherwise replaces by the structured products
+    L, chi, init, n, N, g, gamma = case
+    seed = inputs.SEED + L
+    res = gpu_run(L, chi, init, n, N, g, gamma, seed, prec=prec, generic_heff=1)
+    worst, flips = 0.0, 0
+    for t in range(N):
+        ref, jl, bl = oracle_traj(L, chi, init, n, g, gamma, seed, t)
+        if prec == tjm.PREC_FP64:
+            assert list(res['jumps'][t]) == jl
+            assert np.array_equal(res['bonds'][t], bl)
+        if list(res['jumps'][t]) != jl:
+            flips += 1
+            continue
+        worst = max(worst, np.abs(res['per_traj'][t] - ref).max())
+    log("  generic contraction: max |gpu - oracle| =", worst, "flipped", flips)
+    assert flips <= max(1, N // 8)
+    assert worst < (1e-10 if prec == tjm.PREC_FP64 else 2e-4)
+
+
 @pytest.mark.parametrize("case", [inputs.small_cases()[3], inputs.small_cases()[5]],
                          ids=lambda c: "L%d_chi%d" % (c[0], c[1]))
 def test_mixed_precision_per_trajectory_parity(case):
