@@ -9,8 +9,12 @@ mixed precision (complex-FP32 matrix-core contractions, FP64 factorisations).
 
 Timed region: the K steps that follow W untimed warmup steps of the same run
 (F_0 and uploads happen before; inputs are resident in HBM).  value =
-trajectories x K / wall seconds.  The FP64 path is timed on the same steps
-for trajectory ids 0..511 (fp64_path).
+trajectories x K / wall seconds.  The default window (W=5, K=20: steps
+6..25) is where the bulk bonds reach chi_max=64 and stay there.  The FP64
+path is timed on the same steps for trajectory ids 0..511 (fp64_path), and
+the observables of those ids on both paths are compared step by step
+(error_vs_fp64: largest difference over trajectories whose jump logs agree,
+and the number whose jump logs differ).
 
 roofline.traffic (HBM bytes per launch of the step kernel) comes from the
 FETCH_SIZE / WRITE_SIZE counter summary in profiles/, scaled by the same
@@ -69,35 +73,102 @@ def traffic_per_launch(workload, precision, W, K):
     return 1024.0 * (fetch + write)
 
 
-def _oracle_worker(args):
-    L, chi, steps, traj = args
+def _oracle_sample(args):
+    """One process of the CPU baseline: the oracle's own routines timed on a
+    random right-canonical MPS of the workload's chain with every bond at
+    min(2^b, 2^(L-b), chi_max) (the saturated regime of the timed steps)."""
+    L, chi, budget, seed = args
+    import numpy as np
     from oracle import model as om, mps_tjm
+    rng = np.random.default_rng(seed)
+    bonds = [min(2 ** b, 2 ** (L - b), chi) for b in range(L + 1)]
+    psi = [rng.normal(size=(2, bonds[l], bonds[l + 1])) + 1j * rng.normal(size=(2, bonds[l], bonds[l + 1]))
+           for l in range(L)]
+    mps_tjm.canonicalize(psi)
     Ws = om.xxx_mpo(L, 1.0, 0.5)
     jumps = om.relax_dephase_jumps(L, 0.1, 0.1)
     obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
-    sv = om.product_site_vectors(L, [l % 2 for l in range(L)])
-    t0 = time.time()
-    mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, steps, obs, SEED, traj,
-                           mps_tjm.Options(chi_max=chi))
-    return steps, time.time() - t0
+    opt = mps_tjm.Options(chi_max=chi)
+    stats = mps_tjm.Stats()
+    tau = 0.05
+    # right environments of the whole chain, as U[dt] rebuilds them
+    t0 = time.perf_counter()
+    one = np.ones((1, 1, 1), dtype=np.complex128)
+    Renv = [None] * (L + 1)
+    Renv[L] = one
+    for s in range(L - 1, 0, -1):
+        Renv[s] = mps_tjm.right_update(Renv[s + 1], psi[s], Ws[s])
+    t_env = time.perf_counter() - t0
+    # one-site updates (forward Lanczos, QR, environment, backward bond
+    # evolution, absorption) of bulk sites, left to right, within the budget
+    Lenv = mps_tjm.left_update(one, psi[0], Ws[0])
+    for s in range(1, L // 4):
+        Lenv = mps_tjm.left_update(Lenv, psi[s], Ws[s])
+    s, done = L // 4, 0
+    t0 = time.perf_counter()
+    while s < L - L // 4 and time.perf_counter() - t0 < budget:
+        Le, W, Re = Lenv, Ws[s], Renv[s + 1]
+        psi[s] = mps_tjm.expm_krylov(lambda v: mps_tjm.h1_apply(Le, W, Re, v), psi[s], tau, 30, 1e-12, stats)
+        A, Cm = mps_tjm.qr_left(psi[s])
+        psi[s] = A
+        Lenv = mps_tjm.left_update(Lenv, A, Ws[s])
+        Cm = mps_tjm.expm_krylov(lambda v: mps_tjm.h0_apply(Lenv, Re, v), Cm, -tau, 30, 1e-12, stats)
+        psi[s + 1] = mps_tjm.absorb_right(Cm, psi[s + 1])
+        s += 1
+        done += 1
+    t_site = (time.perf_counter() - t0) / max(done, 1)
+    # a jump process without a jump (QR sweep for delta p, LQ sweep back) and
+    # the measurement of every observable
+    mps_tjm.canonicalize(psi)
+    Dh = [om.local_dissipator(jumps, q, tau) for q in range(L)]
+    t0 = time.perf_counter()
+    mps_tjm.dissipate(psi, Dh)
+    mps_tjm.jump_process(psi, jumps, 1.0, 0.5, opt)
+    t_jump = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    mps_tjm.expectation_values(psi, obs)
+    t_obs = time.perf_counter() - t0
+    step = t_env + 2 * (L - 1) * t_site + 2 * t_jump + t_obs
+    return {"updates": done, "t_site": t_site, "t_env": t_env, "t_jump": t_jump, "t_obs": t_obs, "t_step": step}
 
 
-def cpu_baseline(L, chi, steps=5):
-    """The oracle as it stands on the host cores, one trajectory per process
-    (trajectory ids 0..cores-1), each run for the first `steps` steps of the
-    job; rate = sum over processes of steps / seconds."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(L, chi, budget=15.0):
+    """The oracle as it stands on the host cores, one process per core with
+    single-threaded BLAS (one trajectory per thread, as in the paper's
+    runs).  A full saturated step of the FP64 NumPy oracle takes minutes, so
+    each process times a bounded sample of one (see _oracle_sample) and the
+    rate is the sum over processes of 1 / (estimated seconds per
+    trajectory-step)."""
     cores = max(1, min(os.cpu_count() or 1, 16))
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[v] = "1"                     # one core per trajectory, as in the paper's runs
+        os.environ[v] = "1"
     res = []
     with mp.get_context("spawn").Pool(cores) as pool:
-        for r in pool.imap_unordered(_oracle_worker, [(L, chi, steps, t) for t in range(cores)]):
+        for r in pool.imap_unordered(_oracle_sample, [(L, chi, budget, 1000 + t) for t in range(cores)]):
             res.append(r)
-            print("  cpu baseline: %d of %d trajectories done" % (len(res), cores), file=sys.stderr, flush=True)
-    rate = sum(n / el for n, el in res)
-    return {"value": rate, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 NumPy MPS-TJM of the same chain and seed, trajectory ids 0..%d (one per core), "
-                      "steps 1..%d from the Neel state, each run from F_0" % (cores - 1, steps)}
+            print("  cpu baseline: %d of %d processes done" % (len(res), cores), file=sys.stderr, flush=True)
+    rate = sum(1.0 / r["t_step"] for r in res)
+    med = sorted(res, key=lambda r: r["t_step"])[len(res) // 2]
+    return {"value": rate, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle", "cpu": cpu_model(),
+            "sample": "per process: the FP64 NumPy oracle's routines on a random right-canonical MPS of the "
+                      "L=%d chain with every bond at min(2^b, 2^(L-b), %d), the saturated regime of the timed "
+                      "steps: the right-environment rebuild, one-site TDVP updates of bulk sites for %.0f s "
+                      "(Lanczos forward, QR, environment update, backward bond evolution, absorption), one jump "
+                      "process without a jump and one measurement of all observables; seconds per "
+                      "trajectory-step = rebuild + 2(L-1) updates + 2 jump processes + measurement"
+                      % (L, chi, budget),
+            "median_process": {k: round(v, 4) if isinstance(v, float) else v for k, v in med.items()}}
 
 
 def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
@@ -105,26 +176,41 @@ def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
     return {"copy_bytes": n_bytes, "reps": reps, "avg_ms": ms, "GB/s": 2 * n_bytes / (ms * 1e-3) / 1e9}
 
 
-def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
-    """Run one job on the GPU; time steps warmup+1 .. warmup+K."""
+def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers, read_ids=0, deadline=None):
+    """Run one job on the GPU; time steps warmup+1 .. warmup+K.  With
+    read_ids, the records of trajectories 0..read_ids-1 after the window are
+    returned too.  With a deadline (perf_counter seconds), the job stops
+    early once it is passed and the result says so (partial)."""
     dt = 0.1
     n = int(round(T / dt))
     mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
     m = tjm.Model(L, mpo, s, o, r)
     m.set_initial_product(models.neel(L))
     opt = tjm.default_options(precision=prec, workers=workers)
+    name = "mixed" if prec == tjm.PREC_MIXED else "fp64"
     m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
     for k in range(warmup):
         m.advance(1)
-        print("  warmup step %d of %d done" % (k + 1, warmup), file=sys.stderr, flush=True)
+        print("  %s warmup step %d of %d done" % (name, k + 1, warmup), file=sys.stderr, flush=True)
+        if deadline and time.perf_counter() > deadline:
+            m.close()
+            return {"partial": True, "steps_done": k + 1}
     s0 = m.stats()
     t0 = time.perf_counter()
     for k in range(K):                # each advance returns after its launch has finished
         m.advance(1)
-        print("  %s step %d of %d done at %.1fs" % ("mixed" if prec == tjm.PREC_MIXED else "fp64", warmup + k + 1,
-                                                    warmup + K, time.perf_counter() - t0), file=sys.stderr, flush=True)
+        print("  %s step %d of %d done at %.1fs" % (name, warmup + k + 1, warmup + K, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+        if deadline and k + 1 < K and time.perf_counter() > deadline:
+            m.close()
+            return {"partial": True, "steps_done": warmup + k + 1}
     wall = time.perf_counter() - t0
     s1 = m.stats()
+    rec = None
+    if read_ids:
+        r = m.read()
+        last = warmup + K
+        rec = {"per_traj": r["per_traj"][:read_ids, :last + 1], "jumps": r["jumps"][:read_ids, :2 * last + 1]}
     m.close()                         # the rest of the job is not needed for timing
     if s1["failed_traj"]:
         raise RuntimeError("%d trajectories hit a non-finite norm" % s1["failed_traj"])
@@ -136,12 +222,25 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers):
     phases = {k: s1["phase_s"][k] - s0["phase_s"][k] for k in s1["phase_s"]}
     tot = phases["total"] or 1.0
     return {
-        "value": N * K / wall, "wall": wall, "avg_ms": avg_ms, "flops_per_launch": flops_per_launch,
+        "partial": False, "value": N * K / wall, "wall": wall, "avg_ms": avg_ms, "flops_per_launch": flops_per_launch,
         "achieved_tflops": flops_per_launch / (avg_ms * 1e-3) / 1e12, "workers": s1["workers"],
         "counts": {k: s1[k] - s0[k] for k in ("krylov_iters", "expm_calls", "one_site", "two_site",
                                               "factorizations", "jumps", "cmac_mix")},
-        "phase_frac": {k: round(v / tot, 4) for k, v in phases.items() if k != "total"},
+        "phase_frac": {k: round(v / tot, 4) for k, v in phases.items() if k not in ("total", "env")},
+        "records": rec,
     }
+
+
+def compare(a, b):
+    """Mixed against FP64 records of the same trajectory ids: trajectories
+    whose jump logs differ are counted (a decision within the FP32 error of
+    its threshold sends the trajectory elsewhere); over the rest, the
+    largest and mean absolute difference of the observables."""
+    same = np.all(a["jumps"] == b["jumps"], axis=1)
+    d = np.abs(a["per_traj"] - b["per_traj"])[same]
+    return {"trajectories": int(len(same)), "flipped": int((~same).sum()),
+            "max_abs": float(d.max()) if d.size else None, "mean_abs": float(d.mean()) if d.size else None,
+            "steps": int(a["per_traj"].shape[1] - 1)}
 
 
 def serving(tjm, models, K, precision):
@@ -201,15 +300,17 @@ def serving(tjm, models, K, precision):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6, help="timed steps")
-    ap.add_argument("--warmup", type=int, default=0, help="untimed steps before the timed ones")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--n-traj", type=int, default=None)
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=5, help="steps per trajectory of the CPU oracle sample")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of sampled oracle updates per process")
+    ap.add_argument("--budget", type=float, default=500.0,
+                    help="seconds after which the FP64 comparison is cut short (reported as partial)")
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel used to calibrate the traffic counters")
@@ -240,7 +341,10 @@ def main():
         print("warmup + steps must be within the %d steps of the job" % n, file=sys.stderr)
         sys.exit(2)
     prec = tjm.PREC_MIXED if args.precision == "mixed" else tjm.PREC_FP64
-    head = measure(tjm, models, L, chi, N, T, prec, W, K, args.workers)
+    t_start = time.perf_counter()
+    nf = min(N, args.fp64_traj)
+    compare_ids = nf if prec == tjm.PREC_MIXED and not args.no_fp64_compare else 0
+    head = measure(tjm, models, L, chi, N, T, prec, W, K, args.workers, read_ids=compare_ids)
     peak = PEAK_TFLOPS[args.precision]
     out = {
         "metric": "trajectory-steps/s at L=100 chi=64 (mixed vs FP64 path)",
@@ -269,14 +373,23 @@ def main():
         "counts": head["counts"],
         "phase_frac": head["phase_frac"],
     }
-    if prec == tjm.PREC_MIXED and not args.no_fp64_compare:
-        nf = min(N, args.fp64_traj)
-        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, args.workers)
-        out["fp64_path"] = {"value": f["value"], "n_traj": nf, "ms_per_step": 1e3 * f["wall"] / K,
-                            "achieved_tflops": f["achieved_tflops"], "peak": PEAK_TFLOPS["fp64"],
-                            "mixed_speedup": head["value"] / f["value"]}
+    if compare_ids:
+        # leave room for the CPU baseline after it
+        deadline = t_start + args.budget - (0 if args.no_cpu_baseline else args.cpu_budget + 40.0)
+        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, args.workers, read_ids=nf, deadline=deadline)
+        if f["partial"]:
+            out["fp64_path"] = {"value": None, "n_traj": nf, "partial": True, "steps_done": f["steps_done"],
+                                "reason": "stopped at the bench time budget (--budget %g s)" % args.budget}
+        else:
+            out["fp64_path"] = {"value": f["value"], "n_traj": nf, "ms_per_step": 1e3 * f["wall"] / K,
+                                "achieved_tflops": f["achieved_tflops"], "peak": PEAK_TFLOPS["fp64"],
+                                "frac": f["achieved_tflops"] / PEAK_TFLOPS["fp64"],
+                                "per_trajectory_speedup_of_mixed": (head["value"] / N) / (f["value"] / nf),
+                                "phase_frac": f["phase_frac"]}
+            out["error_vs_fp64"] = compare(head["records"], f["records"])
+            out["error_vs_fp64"]["ids"] = "0..%d" % (nf - 1)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(L, chi, min(args.cpu_steps, n))
+        out["cpu_baseline"] = cpu_baseline(L, chi, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -211,6 +211,15 @@ tjm_status tjm_run_advance(tjm_model *m, int steps);
 tjm_status tjm_run_end(tjm_model *m, double *mean, double *sem, double *per_traj_obs,
                        int32_t *jump_log, int32_t *bond_log);
 
+/*
+ * Copies the per-trajectory records of the run in progress as they stand
+ * after the steps applied so far (layouts as tjm_run_traces; entries of
+ * later steps are zero; any pointer may be NULL).  The run continues.
+ * TJM_E_BUSY without a run in progress, TJM_E_INVAL for bond_log without
+ * record_bonds.
+ */
+tjm_status tjm_run_read(tjm_model *m, double *per_traj_obs, int32_t *jump_log, int32_t *bond_log);
+
 /* Kernel timings and algorithmic counters of the current or last run. */
 tjm_status tjm_get_stats(const tjm_model *m, tjm_stats *out);
 

@@ -194,7 +194,9 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
 // fp32 accumulation).  All threads of the workgroup call it together; the
 // workgroup walks 64 x 32 (complex) output tiles, staging k-chunks of 16 in
 // LDS (`lds`, GEMM_LDS_BYTES); wavefront w owns the 32 x 16 sub-tile
-// (w / 2, w % 2).  The caller synchronises before reading C.
+// (w / 2, w % 2).  The caller synchronises before reading C, or before
+// another product accumulates into it (small products return without a
+// workgroup barrier).
 template <typename T, class OA, class OB, typename SC>
 TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
                        const OA& A, const OB& B,

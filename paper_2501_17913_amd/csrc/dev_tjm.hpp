@@ -122,11 +122,13 @@ template <typename Tc> struct Tjm {
       blk_cgemm<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
                     mix_cols(q, ptrL, P.mixL, dp, chr, 0L, (long)dp * chr, (long)chr), y, dp * chr, 0, false,
                     tjm_lds.gemm);
+      tjm_sync();        // the small-product path returns without a barrier
       acc = true;
     }
     if (nR > 0) {      // right class: (chl dp x chr) . (chr x chr), summed over channels
       blk_cgemm<Tc>(chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
                     chan_mat(Re, chr, (long)chr * chr, chanR), y, chr, 0, acc, tjm_lds.gemm);
+      tjm_sync();
       acc = true;
     }
     // local term in FP64: y[a][s'][c] += sum_s Oloc[s'][s] q[a][s][c]
@@ -217,6 +219,7 @@ template <typename Tc> struct Tjm {
         const int* lr = P.lr_chan + (long)b * P.Dmax;
         blk_cgemm<Tc>(kl, kr, kr, 1, true, cmat(q, kr), cmat(Re + (long)st * kr * kr, kr), y, kr, 0, false,
                       tjm_lds.gemm);
+        tjm_sync();      // the small-product path returns without a barrier
         blk_cgemm<Tc>(kl, kr, kl, 1, true, cmat(Le + (long)en * kl * kl, kl), cmat(q, kr), y, kr, 0, true,
                       tjm_lds.gemm);
         if (nlr > 0) {

@@ -883,6 +883,22 @@ extern "C" tjm_status tjm_run_end(tjm_model* m, double* mean, double* sem, doubl
   return TJM_OK;
 }
 
+extern "C" tjm_status tjm_run_read(tjm_model* m, double* per_traj_obs, int32_t* jump_log, int32_t* bond_log) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  Run* r = m->run;
+  if (!r) return fail(m, TJM_E_BUSY, "no run in progress");
+  if (bond_log && !r->d_blog) return fail(m, TJM_E_INVAL, "bond_log requested without record_bonds");
+  const long entries = (long)(r->n_steps + 1) * r->n_obs;
+  HIPCHK(m, hipStreamSynchronize(r->stream));
+  if (per_traj_obs && entries > 0)
+    HIPCHK(m, hipMemcpy(per_traj_obs, r->d_obs, (size_t)r->n_traj * entries * 8, hipMemcpyDeviceToHost));
+  if (jump_log)
+    HIPCHK(m, hipMemcpy(jump_log, r->d_jlog, (size_t)r->n_traj * 2 * r->n_steps * 4, hipMemcpyDeviceToHost));
+  if (bond_log)
+    HIPCHK(m, hipMemcpy(bond_log, r->d_blog, (size_t)r->n_traj * r->n_steps * (m->L + 1) * 4, hipMemcpyDeviceToHost));
+  return TJM_OK;
+}
+
 extern "C" tjm_status tjm_run_traces(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
                                      const int* obs_site, const double* obs_op, uint64_t seed,
                                      const tjm_options* opt, double* mean, double* sem, double* per_traj_obs,

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NUMERI
 EXPORTED = [
     "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps", "tjm_run",
     "tjm_run_traces",
-    "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_get_stats", "tjm_last_error",
+    "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_run_read", "tjm_get_stats", "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
     "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_wait", "tjm_server_last_error",
@@ -99,6 +99,8 @@ lib.tjm_run_advance.argtypes = [_vp, C.c_int]
 lib.tjm_run_advance.restype = C.c_int
 lib.tjm_run_end.argtypes = [_vp, _dp, _dp, _dp, _ip, _ip]
 lib.tjm_run_end.restype = C.c_int
+lib.tjm_run_read.argtypes = [_vp, _dp, _ip, _ip]
+lib.tjm_run_read.restype = C.c_int
 lib.tjm_get_stats.argtypes = [_vp, C.POINTER(Stats)]
 lib.tjm_get_stats.restype = C.c_int
 lib.tjm_last_error.argtypes = [_vp]
@@ -263,6 +265,15 @@ class Model:
         bl = np.zeros((nt, n, self.L + 1), dtype=np.int32) if (traces and self._rec) else None
         self._check(lib.tjm_run_end(self.h, _dptr(mean), _dptr(sem), _dptr(per), _iptr(jl), _iptr(bl)))
         return {"mean": mean, "sem": sem, "per_traj": per, "jumps": jl, "bonds": bl}
+
+    def read(self):
+        """Per-trajectory records of the run in progress (tjm_run_read)."""
+        n, no, nt = self._n, self._no, self._nt
+        per = np.zeros((nt, n + 1, no))
+        jl = np.zeros((nt, 2 * n), dtype=np.int32)
+        bl = np.zeros((nt, n, self.L + 1), dtype=np.int32) if self._rec else None
+        self._check(lib.tjm_run_read(self.h, _dptr(per), _iptr(jl), _iptr(bl)))
+        return {"per_traj": per, "jumps": jl, "bonds": bl}
 
     def stats(self):
         s = Stats()
