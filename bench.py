@@ -125,9 +125,17 @@ def _oracle_sample(args):
     mps_tjm.dissipate(psi, Dh)
     mps_tjm.jump_process(psi, jumps, 1.0, 0.5, opt)
     t_jump = time.perf_counter() - t0
+    # the measurement: a fixed part (the transfer environments of the whole
+    # chain) plus one contraction per observable; timed without observables
+    # and with four of bulk sites
     t0 = time.perf_counter()
-    mps_tjm.expectation_values(psi, obs)
-    t_obs = time.perf_counter() - t0
+    mps_tjm.expectation_values(psi, [])
+    t_fix = time.perf_counter() - t0
+    mid = L // 2
+    t0 = time.perf_counter()
+    mps_tjm.expectation_values(psi, [(mid, om.Z), (mid + 1, om.Z), (mid, om.X), (mid + 1, om.X)])
+    per_obs = max(time.perf_counter() - t0 - t_fix, 0.0) / 4.0
+    t_obs = t_fix + len(obs) * per_obs
     step = t_env + 2 * (L - 1) * t_site + 2 * t_jump + t_obs
     return {"updates": done, "t_site": t_site, "t_env": t_env, "t_jump": t_jump, "t_obs": t_obs, "t_step": step}
 
@@ -143,7 +151,7 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(L, chi, budget=15.0):
+def cpu_baseline(L, chi, budget=8.0):
     """The oracle as it stands on the host cores, one process per core with
     single-threaded BLAS (one trajectory per thread, as in the paper's
     runs).  A full saturated step of the FP64 NumPy oracle takes minutes, so
@@ -165,8 +173,9 @@ def cpu_baseline(L, chi, budget=15.0):
                       "L=%d chain with every bond at min(2^b, 2^(L-b), %d), the saturated regime of the timed "
                       "steps: the right-environment rebuild, one-site TDVP updates of bulk sites for %.0f s "
                       "(Lanczos forward, QR, environment update, backward bond evolution, absorption), one jump "
-                      "process without a jump and one measurement of all observables; seconds per "
-                      "trajectory-step = rebuild + 2(L-1) updates + 2 jump processes + measurement"
+                      "process without a jump, and the measurement without observables and with 4 of bulk sites "
+                      "(a fixed part plus a contraction per observable); seconds per trajectory-step = rebuild "
+                      "+ 2(L-1) updates + 2 jump processes + measurement of all 2L observables"
                       % (L, chi, budget),
             "median_process": {k: round(v, 4) if isinstance(v, float) else v for k, v in med.items()}}
 
@@ -308,7 +317,7 @@ def main():
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of sampled oracle updates per process")
+    ap.add_argument("--cpu-budget", type=float, default=8.0, help="seconds of sampled oracle updates per process")
     ap.add_argument("--budget", type=float, default=500.0,
                     help="seconds after which the FP64 comparison is cut short (reported as partial)")
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
@@ -375,7 +384,7 @@ def main():
     }
     if compare_ids:
         # leave room for the CPU baseline after it
-        deadline = t_start + args.budget - (0 if args.no_cpu_baseline else args.cpu_budget + 40.0)
+        deadline = t_start + args.budget - (0 if args.no_cpu_baseline else args.cpu_budget + 60.0)
         f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, args.workers, read_ids=nf, deadline=deadline)
         if f["partial"]:
             out["fp64_path"] = {"value": None, "n_traj": nf, "partial": True, "steps_done": f["steps_done"],

@@ -46,6 +46,25 @@ tjm_status tjm_selftest_svd(int m, int n, const double *G, double discard, int c
                             double deg_tol, int absorb_left, double *left, double *right,
                             double *S, int *k);
 
+/*
+ * The same truncated SVD for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): G, left, right, S and k are DEVICE pointers of the caller
+ * (layouts and sizes as tjm_selftest_svd; left needs m x min(m,n), right
+ * min(m,n) x n complex doubles), and the work arrays live in a fixed 1.5 MiB
+ * device array of the library (one per GPU, kept until the process ends;
+ * its address is looked up once per device).  Limits: max(m, n) <= 256 and
+ * n <= 128 (m <= 128 with absorb_left); larger sizes return TJM_E_INVAL.
+ * The kernel is launched on `stream` (a hipStream_t; NULL = the null
+ * stream) and the call returns without waiting; the caller synchronises
+ * before reading the outputs.  No hipMalloc, hipFree or allocating library
+ * call is made.  Every call on a GPU uses that GPU's one work array, so
+ * calls that overlap on one GPU (other streams, other threads) race: the
+ * caller orders them.  Messages go to tjm_last_error(NULL).
+ */
+tjm_status tjm_svd_noalloc(int m, int n, const double *G, double discard, int cap, double deg_tol,
+                           int absorb_left, double *left, double *right, double *S, int *k, void *stream);
+
 /* exp(-i t H) v by the Lanczos routine, H a dense Hermitian n x n matrix
  * (n <= 512) applied through the FP64 matrix-core GEMM.  *iters = Krylov
  * dimension used. */

@@ -34,6 +34,7 @@ def build(verbose=False):
     units = [("tjm_step.hip", "tjm_step_f32", ["-DTJM_TC=float"]),
              ("tjm_step.hip", "tjm_step_f64", ["-DTJM_TC=double"]),
              ("tjm_kernels.hip", "tjm_kernels", []),
+             ("tjm_noalloc.hip", "tjm_noalloc", []),
              ("tjm_api.cpp", "tjm_api", ["-x", "hip"]),
              ("tjm_server.cpp", "tjm_server", ["-x", "hip"])]
     for src, name, extra in units:

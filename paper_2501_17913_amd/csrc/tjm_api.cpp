@@ -61,6 +61,8 @@ static tjm_status fail(tjm_model* m, tjm_status st, const std::string& msg) {
   return st;
 }
 
+tjm_status tjm_fail_global(tjm_status st, const char* msg) { return fail(nullptr, st, msg); }
+
 static bool finite_arr(const double* p, long n) {
   for (long i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -1039,7 +1041,7 @@ extern "C" tjm_status tjm_selftest_svd(int m, int n, const double* G, double dis
   STCHK(ds.put((const double*)nullptr, 2L * nc * p, &dU));
   STCHK(ds.put((const double*)nullptr, 2L * m * n, &dT));
   STCHK(ds.put((const int*)nullptr, 1, &dk));
-  STCHK(tjm_launch_st_svd(m, n, dG, discard, cap, deg_tol, absorb_left, dl, dr, dS, dk, dW, dU, dT));
+  STCHK(tjm_launch_st_svd(m, n, dG, discard, cap, deg_tol, absorb_left, dl, dr, dS, dk, dW, dU, dT, 0));
   STCHK(hipDeviceSynchronize());
   STCHK(hipMemcpy(k, dk, 4, hipMemcpyDeviceToHost));
   const int kk = *k;

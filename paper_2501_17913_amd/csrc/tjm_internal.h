@@ -26,12 +26,15 @@ hipError_t tjm_launch_st_cgemm(int mixed, int M, int N, int K, int nb, int sum_b
 hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R, double* V);
 hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                              int absorb_left, double* left, double* right, double* S, int* k,
-                             double* Wc, double* Uc, double* Tg);
+                             double* Wc, double* Uc, double* Tg, hipStream_t s);
 hipError_t tjm_launch_st_expm(int n, const double* H, double* v, double t, int kmax, double tol,
                               double* Q, double* w, int* iters);
 hipError_t tjm_launch_st_philox(int count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
                                 uint32_t* out);
 hipError_t tjm_launch_st_copy(const void* src, void* dst, long n16, int blocks, hipStream_t s);
+
+// Records msg as the message tjm_last_error(NULL) returns and returns st.
+tjm_status tjm_fail_global(tjm_status st, const char* msg);
 
 // Host-side helpers of tjm_api.cpp used by the server (tjm_server.cpp).
 // A deep copy of a model's inputs (no run state); NULL if out of memory.

@@ -127,8 +127,8 @@ hipError_t tjm_launch_st_qr(int m, int n, double* X, double* Q, double* R, doubl
 
 hipError_t tjm_launch_st_svd(int m, int n, const double* G, double discard, int cap, double deg_tol,
                              int absorb_left, double* left, double* right, double* S, int* k,
-                             double* Wc, double* Uc, double* Tg) {
-  hipLaunchKernelGGL(st_svd_kernel, dim3(1), dim3(TJM_NT), 0, 0, m, n, (const zd*)G, discard, cap,
+                             double* Wc, double* Uc, double* Tg, hipStream_t s) {
+  hipLaunchKernelGGL(st_svd_kernel, dim3(1), dim3(TJM_NT), 0, s, m, n, (const zd*)G, discard, cap,
                      deg_tol, absorb_left, (zd*)left, (zd*)right, S, k, (zd*)Wc, (zd*)Uc, (zd*)Tg);
   return hipGetLastError();
 }

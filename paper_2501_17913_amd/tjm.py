@@ -23,7 +23,7 @@ EXPORTED = [
     "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps", "tjm_run",
     "tjm_run_traces",
     "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_run_read", "tjm_get_stats", "tjm_last_error",
-    "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd",
+    "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd", "tjm_svd_noalloc",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
     "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_wait", "tjm_server_last_error",
     "tjm_server_destroy",
@@ -117,6 +117,9 @@ lib.tjm_selftest_qr.restype = C.c_int
 lib.tjm_selftest_svd.argtypes = [C.c_int, C.c_int, _dp, C.c_double, C.c_int, C.c_double, C.c_int,
                                  _dp, _dp, _dp, _ip]
 lib.tjm_selftest_svd.restype = C.c_int
+lib.tjm_svd_noalloc.argtypes = [C.c_int, C.c_int, _vp, C.c_double, C.c_int, C.c_double, C.c_int,
+                                _vp, _vp, _vp, _vp, _vp]
+lib.tjm_svd_noalloc.restype = C.c_int
 lib.tjm_selftest_expm.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, C.c_double, _dp, _ip]
 lib.tjm_selftest_expm.restype = C.c_int
 lib.tjm_selftest_philox.argtypes = [C.c_int, _up, C.c_uint32, C.c_uint32, _up]

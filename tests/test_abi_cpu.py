@@ -225,3 +225,12 @@ def test_serving_stream_recipe():
         assert 0.01 <= q["gamma"] <= 0.2 and 0.0 <= q["g"] <= 1.0
         assert 10 <= q["n_steps"] <= 50 and abs(q["T"] / q["dt"] - q["n_steps"]) < 1e-9
     assert len({q["seed"] for q in a}) == len(a)
+
+
+def test_svd_noalloc_validates_before_touching_the_device():
+    import ctypes as C
+    bogus = C.c_void_p(1)          # never dereferenced: the sizes are rejected first
+    for (m, n, absorb) in [(300, 8, 0), (8, 200, 0), (200, 8, 1), (0, 4, 0)]:
+        st = tjm.lib.tjm_svd_noalloc(m, n, bogus, 1e-12, 4, 1e-12, absorb, bogus, bogus, bogus, bogus, None)
+        assert st == tjm.E_INVAL, (m, n, absorb)
+    assert tjm.lib.tjm_svd_noalloc(8, 8, None, 1e-12, 4, 1e-12, 0, None, None, None, None, None) == tjm.E_INVAL
