@@ -45,50 +45,59 @@ template <> struct Mfma<float> {
 // The k-chunk is 32 complex for f32 and 16 for f64 operands, so that both
 // fill the same staging area (and a chunk keeps the matrix cores busy long
 // enough to hide the next chunk's loads).
-constexpr int GEMM_BM = 64, GEMM_BN = 32;
+// Tile shapes: the workgroup computes BM x BN (complex) output tiles, its
+// four wavefronts the (BM/2) x (BN/2) quarters, each as TI x TJ
+// instructions of 16 rows x 8 complex columns.  64 x 32 is the default; the
+// wide shapes 64 x 128 and 128 x 64 read each operand panel of a 64 x 128
+// (or 128 x 64) product once instead of four (two) times.
 template <typename T> struct GemmK { static constexpr int BK = 16; };
 template <> struct GemmK<float> { static constexpr int BK = 32; };
-constexpr int GEMM_APAD = GEMM_BM + 2, GEMM_BPAD = GEMM_BN + 2;
-constexpr int GEMM_LDS_BYTES = (16 * GEMM_APAD + 16 * GEMM_BPAD) * 16;
-static_assert((GemmK<float>::BK * GEMM_APAD + GemmK<float>::BK * GEMM_BPAD) * 8 <= GEMM_LDS_BYTES,
-              "f32 staging fits the f64-sized area");
-template <typename T> struct GemmE {
-  static constexpr int BK = GemmK<T>::BK;
-  static constexpr int AE = GEMM_BM * BK / TJM_NT;   // A elements per thread
-  static constexpr int BE = BK * GEMM_BN / TJM_NT;   // B elements per thread
-  static_assert(AE * TJM_NT == GEMM_BM * BK && BE * TJM_NT == BK * GEMM_BN,
+constexpr int GEMM_BM = 64, GEMM_BN = 32;
+constexpr int GEMM_LDS_BYTES = 64 * 1024;          // staging area of every tile shape
+template <typename T, int BM, int BN> struct GemmT {
+  // a wide tile takes k-chunks of 16 in either precision: a chunk still
+  // keeps the matrix cores busy for 128 instructions per wavefront, and the
+  // staging registers stay within budget next to 16 accumulators
+  static constexpr int BK = BM * BN > GEMM_BM * GEMM_BN ? 16 : GemmK<T>::BK;
+  static constexpr int APAD = BM + 2, BPAD = BN + 2;
+  static constexpr int AE = BM * BK / TJM_NT;      // A elements per thread
+  static constexpr int BE = BK * BN / TJM_NT;      // B elements per thread
+  static constexpr int TI = BM / 32, TJ = BN / 16; // instructions per wavefront quarter
+  static_assert(AE * TJM_NT == BM * BK && BE * TJM_NT == BK * BN,
                 "the workgroup must tile the staging panels exactly");
+  static_assert((BK * APAD + BK * BPAD) * (int)sizeof(cplx<T>) <= GEMM_LDS_BYTES, "staging fits its LDS area");
 };
 
 // panel coordinates of the u-th element a thread stages
-template <int BK> TJM_DEV void a_coord(bool trans, int u, int& i, int& k) {
+template <int BM, int BK> TJM_DEV void a_coord(bool trans, int u, int& i, int& k) {
   const int e = tjm_tid() + u * TJM_NT;
-  if (trans) { i = e % GEMM_BM; k = e / GEMM_BM; }
+  if (trans) { i = e % BM; k = e / BM; }
   else { k = e % BK; i = e / BK; }
 }
-template <int BK> TJM_DEV void b_coord(bool trans, int u, int& k, int& j) {
+template <int BN, int BK> TJM_DEV void b_coord(bool trans, int u, int& k, int& j) {
   const int e = tjm_tid() + u * TJM_NT;
   if (trans) { k = e % BK; j = e / BK; }
-  else { j = e % GEMM_BN; k = e / GEMM_BN; }
+  else { j = e % BN; k = e / BN; }
 }
 
-template <typename T, class OA, class OB>
+template <typename T, int BM, int BN, class OA, class OB>
 TJM_DEV void gemm_load(const OA& A, const OB& B, int b, int i0, int j0, int k0, int M, int N, int K,
                        cplx<T>* ra, cplx<T>* rb) {
-  constexpr int BK = GemmE<T>::BK, AE = GemmE<T>::AE, BE = GemmE<T>::BE;
+  typedef GemmT<T, BM, BN> G;
+  constexpr int BK = G::BK, AE = G::AE, BE = G::BE;
   int ia[AE], ka[AE], kb[BE], jb[BE];
   bool oa[AE], ob[BE];
 #pragma unroll
   for (int u = 0; u < AE; ++u) {
     int i, k;
-    a_coord<BK>(A.trans, u, i, k);
+    a_coord<BM, BK>(A.trans, u, i, k);
     ia[u] = i0 + i; ka[u] = k0 + k;
     oa[u] = ia[u] < M && ka[u] < K;
   }
 #pragma unroll
   for (int u = 0; u < BE; ++u) {
     int k, j;
-    b_coord<BK>(B.trans, u, k, j);
+    b_coord<BN, BK>(B.trans, u, k, j);
     kb[u] = k0 + k; jb[u] = j0 + j;
     ob[u] = kb[u] < K && jb[u] < N;
   }
@@ -96,20 +105,21 @@ TJM_DEV void gemm_load(const OA& A, const OB& B, int b, int i0, int j0, int k0, 
   B.template gather<T, BE>(b, kb, jb, ob, rb);
 }
 
-template <typename T>
+template <typename T, int BM, int BN>
 TJM_DEV void gemm_store(bool ta, bool tb, const cplx<T>* ra, const cplx<T>* rb, cplx<T>* As, cplx<T>* Bs) {
-  constexpr int BK = GemmE<T>::BK, AE = GemmE<T>::AE, BE = GemmE<T>::BE;
+  typedef GemmT<T, BM, BN> G;
+  constexpr int BK = G::BK, AE = G::AE, BE = G::BE;
 #pragma unroll
   for (int u = 0; u < AE; ++u) {
     int i, k;
-    a_coord<BK>(ta, u, i, k);
-    As[k * GEMM_APAD + i] = ra[u];
+    a_coord<BM, BK>(ta, u, i, k);
+    As[k * G::APAD + i] = ra[u];
   }
 #pragma unroll
   for (int u = 0; u < BE; ++u) {
     int k, j;
-    b_coord<BK>(tb, u, k, j);
-    Bs[k * GEMM_BPAD + j] = rb[u];
+    b_coord<BN, BK>(tb, u, k, j);
+    Bs[k * G::BPAD + j] = rb[u];
   }
 }
 
@@ -192,78 +202,83 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
 //   sum_batches = false: C_b = [C_b +] op(A_b) op(B_b), C_b = C + b*cs
 // T selects the matrix-core precision (double: f64 MFMA, float: f32 MFMA with
 // fp32 accumulation).  All threads of the workgroup call it together; the
-// workgroup walks 64 x 32 (complex) output tiles, staging k-chunks of 16 in
-// LDS (`lds`, GEMM_LDS_BYTES); wavefront w owns the 32 x 16 sub-tile
-// (w / 2, w % 2).  The caller synchronises before reading C, or before
-// another product accumulates into it (small products return without a
-// workgroup barrier).
-template <typename T, class OA, class OB, typename SC>
-TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
-                       const OA& A, const OB& B,
-                       cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
+// workgroup walks BM x BN (complex) output tiles (GemmT), staging k-chunks in
+// LDS (`lds`, GEMM_LDS_BYTES).  The caller synchronises before reading C, or
+// before another product accumulates into it (small products return without
+// a workgroup barrier).
+template <typename T, int BM, int BN, class OA, class OB, typename SC>
+TJM_DEV void blk_cgemm_t(int M, int N, int K, int nb, bool sum_batches,
+                         const OA& A, const OB& B,
+                         cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
   typedef typename Mfma<T>::acc_t acc_t;
+  typedef GemmT<T, BM, BN> G;
   if (M <= 0 || N <= 0) return;
   if (M < 32 || N < 16 || K < 8) {
     wave_cgemm<T>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate);
     return;
   }
-  constexpr int BK = GemmE<T>::BK;
+  constexpr int BK = G::BK, TI = G::TI, TJ = G::TJ;
   cplx<T>* As = (cplx<T>*)lds;
-  cplx<T>* Bs = As + BK * GEMM_APAD;
+  cplx<T>* Bs = As + BK * G::APAD;
   const int lane = tjm_lane();
   const int r16 = lane & 15;
   const int q = lane >> 4;           // k sub-index 0..3 inside one instruction
   const int kq = q >> 1;             // complex k offset 0/1
   const int kp = q & 1;              // real/imag part of the k index
   const int cpart = r16 & 1;         // real/imag part of the output column
-  const int wi = (tjm_wave() >> 1) * 32;   // sub-tile origin inside the tile
-  const int wj = (tjm_wave() & 1) * 16;
-  const int nti = (M + GEMM_BM - 1) / GEMM_BM, ntj = (N + GEMM_BN - 1) / GEMM_BN;
+  const int wi = (tjm_wave() >> 1) * (BM / 2);   // quarter origin inside the tile
+  const int wj = (tjm_wave() & 1) * (BN / 2);
+  const int nti = (M + BM - 1) / BM, ntj = (N + BN - 1) / BN;
   const int nout = sum_batches ? 1 : nb;
   const int ntiles = nout * nti * ntj;
   const int nkc = (K + BK - 1) / BK;
   for (int it = 0; it < ntiles; ++it) {
     const int ob = it / (nti * ntj);
     const int rem = it - ob * (nti * ntj);
-    const int i0 = (rem / ntj) * GEMM_BM;
-    const int j0 = (rem % ntj) * GEMM_BN;
-    acc_t acc[2][2];
-    acc[0][0] = Mfma<T>::zero(); acc[0][1] = Mfma<T>::zero();
-    acc[1][0] = Mfma<T>::zero(); acc[1][1] = Mfma<T>::zero();
+    const int i0 = (rem / ntj) * BM;
+    const int j0 = (rem % ntj) * BN;
+    acc_t acc[TI][TJ];
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = Mfma<T>::zero();
     const int b_lo = sum_batches ? 0 : ob;
     const int nchunk = (sum_batches ? nb : 1) * nkc;
-    cplx<T> ra[GemmE<T>::AE], rb[GemmE<T>::BE];
-    gemm_load<T>(A, B, b_lo, i0, j0, 0, M, N, K, ra, rb);
+    cplx<T> ra[G::AE], rb[G::BE];
+    gemm_load<T, BM, BN>(A, B, b_lo, i0, j0, 0, M, N, K, ra, rb);
     for (int c = 0; c < nchunk; ++c) {
       tjm_sync();                                  // LDS free again
-      gemm_store<T>(A.trans, B.trans, ra, rb, As, Bs);
+      gemm_store<T, BM, BN>(A.trans, B.trans, ra, rb, As, Bs);
       tjm_sync();
       if (c + 1 < nchunk) {                        // next chunk in flight
         const int cn = c + 1;
-        gemm_load<T>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * BK, M, N, K, ra, rb);
+        gemm_load<T, BM, BN>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * BK, M, N, K, ra, rb);
       }
 #pragma unroll 2
       for (int kk = 0; kk < BK; kk += 2) {         // zero-padded past K
         const int kc = kk + kq;
-        T av[2], bv[2];
+        T av[TI], bv[TJ];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const cplx<T> ea = As[kc * GEMM_APAD + wi + 16 * t + r16];
+        for (int t = 0; t < TI; ++t) {
+          const cplx<T> ea = As[kc * G::APAD + wi + 16 * t + r16];
           av[t] = kp ? ea.im : ea.re;
-          const cplx<T> eb = Bs[kc * GEMM_BPAD + wj + 8 * t + (r16 >> 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < TJ; ++t) {
+          const cplx<T> eb = Bs[kc * G::BPAD + wj + 8 * t + (r16 >> 1)];
           bv[t] = (kp == cpart) ? eb.re : (kp ? -eb.im : eb.im);
         }
-        acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
-        acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
-        acc[1][0] = Mfma<T>::mma(av[1], bv[0], acc[1][0]);
-        acc[1][1] = Mfma<T>::mma(av[1], bv[1], acc[1][1]);
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = Mfma<T>::mma(av[ti], bv[tj], acc[ti][tj]);
       }
     }
     cplx<SC>* Cb = C + (long)ob * cs;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
+      for (int tj = 0; tj < TJ; ++tj) {
         const int col = j0 + wj + 8 * tj + (r16 >> 1);
         if (col >= N) continue;
 #pragma unroll
@@ -277,4 +292,32 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches,
       }
   }
   tjm_sync();                                      // LDS free for the caller
+}
+
+template <typename T, class OA, class OB, typename SC>
+TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches, const OA& A, const OB& B,
+                       cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
+  blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+}
+
+// The same with the tile shape chosen for the product's size: the wide
+// shapes where the output spans them (64 x 128 or 128 x 64 for f32
+// contractions, 64 x 64 for f64, whose accumulators take twice the
+// registers), the default otherwise.
+template <typename T, class OA, class OB, typename SC>
+TJM_DEV void blk_cgemm_auto(int M, int N, int K, int nb, bool sum_batches, const OA& A, const OB& B,
+                            cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
+  if constexpr (sizeof(T) == 4) {
+    if (M >= 48 && N >= 96)
+      blk_cgemm_t<T, 64, 128>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+    else if (M >= 96 && N >= 48)
+      blk_cgemm_t<T, 128, 64>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+    else
+      blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+  } else {
+    if (M >= 48 && N >= 48)
+      blk_cgemm_t<T, 64, 64>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+    else
+      blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+  }
 }

@@ -28,6 +28,7 @@ struct QrLds {
 constexpr int QRF_ROWS = 128, QRF_COLS = 64, QRF_RPT = QRF_ROWS / 4;
 struct QrfLds {
   zd v[2][QRF_ROWS];
+  zd v0[QRF_COLS];
   double bre[QRF_COLS], bim[QRF_COLS], vn[QRF_COLS];
 };
 

@@ -158,20 +158,31 @@ TJM_DEVNI void blk_qr_global(int m, int n, zd* X, zd* Q, zd* R) {
 // rows and n <= 64 columns (every site tensor of a bond of at most 64).
 // Thread t owns column c = t / 4 and the rows g + 4 i (g = t % 4,
 // i < 32) of it; the four threads of a column are neighbouring lanes of one
-// wavefront, so a column's sums are two lane shuffles.  Step j: the owners
-// of column j form its reflector and publish it in LDS, one barrier, and
-// every later column is updated in registers against it; the next step's
-// owners start at once (the reflector buffer alternates, so one barrier per
-// column suffices).  The reflectors also go to V (m x k, global scratch)
-// for the formation of Q, which runs the same way backwards over them on
-// [I; 0] held in the same registers.  Same reflectors, signs and gauge as
-// blk_qr_global (which serves larger shapes).  X may alias Q or R.
+// wavefront, so a column's sums are two lane shuffles.
+//   Reduction, step j: the owners of column j form its reflector and
+//   publish it in LDS, one barrier, and every later column is updated in
+//   registers against it; the next step's owners start at once (the
+//   reflector buffer alternates, so one barrier per column suffices).  No
+//   global memory is touched inside the loop, so the barriers wait for
+//   nothing but LDS.  Each column's reflector stays in its owners'
+//   registers (rows below the diagonal; v0 in LDS).
+//   Then R is written, and the reflectors go to V (m x k, global scratch)
+//   in one pass.
+//   Formation of Q = H_0 ... H_{k-1} [I; 0] in the same registers: the
+//   reflectors are staged in LDS in blocks of QRF_VB (the next block's
+//   loads in flight while the current one is applied), and a block is
+//   applied without barriers, since a column's update needs only its own
+//   four threads.
+// Same reflectors, signs and gauge as blk_qr_global (which serves larger
+// shapes).  X may alias Q or R.
 // With adj the matrix factorised is A = X^H for X of n x m (ld m), and the
 // factors are written adjoint: Q^H (k x m, ld m) to Q and R^H (n x k, ld k)
 // to R, plus R itself (k x n) to Rk if it is non-null; this is the LQ
 // X = R^H Q^H of a site tensor without transposed copies.
 // --------------------------------------------------------------------------
 static_assert(TJM_NT == 4 * QRF_COLS, "one column per four threads");
+constexpr int QRF_VB = 8;                          // reflectors per LDS block of the Q formation
+static_assert(2 * QRF_VB * QRF_ROWS * 16 <= GEMM_LDS_BYTES, "two reflector blocks fit the staging area");
 
 // One reflector application to a column held in registers (rows g + 4 i,
 // i < QRF_RPT): x <- x - (2/vn) (v^H x) v over the rows r >= j, r < m; the
@@ -229,8 +240,8 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     zd* vb = H.v[j & 1];
     if (c == j) {
       // reflector of column j: x0 = X[j][j], beta = -(x0/|x0|) ||x||,
-      // v = x with v0 = x0 - beta, ||v||^2 = 2 ||x|| (||x|| + |x0|)
-      // the whole column goes to the buffer (rows above j hold finished R
+      // v = x with v0 = x0 - beta, ||v||^2 = 2 ||x|| (||x|| + |x0|); the
+      // whole column goes to the buffer (rows above j hold finished R
       // entries and rows from m on zeros; the readers mask rows < j)
       double a2 = 0.0;
 #pragma unroll
@@ -253,12 +264,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
         vn = 2.0 * al * (al + ax0);
       }
       __builtin_amdgcn_wave_barrier();
-      if (g == 0) { vb[j] = v0; H.bre[j] = beta.re; H.bim[j] = beta.im; H.vn[j] = vn; }
-#pragma unroll
-      for (int i = 0; i < QRF_RPT; ++i) {
-        const int r = g + 4 * i;
-        if (r >= j && r < m) V[(long)j * m + r] = csel(r == j, v0, x[i]);
-      }
+      if (g == 0) { vb[j] = v0; H.bre[j] = beta.re; H.bim[j] = beta.im; H.vn[j] = vn; H.v0[j] = v0; }
     }
     tjm_sync();
     if (live && c > j) {
@@ -267,7 +273,8 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     }
   }
   tjm_sync();                                     // every reflector read; H.v free
-  // R: row r of the upper triangle times conj(ph_r), diagonal |beta_r|
+  // R: row r of the upper triangle times conj(ph_r), diagonal |beta_r|;
+  // the reflector of column c (v0 on the diagonal, x below it) to V
 #pragma unroll
   for (int i = 0; i < QRF_RPT; ++i) {
     const int r = g + 4 * i;
@@ -283,21 +290,46 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
         R[(long)r * n + c] = val;
       }
     }
+    if (c < k && r >= c && r < m) V[(long)c * m + r] = csel(r == c, H.v0[c], x[i]);
   }
-  // Q = H_0 ... H_{k-1} [I; 0], reflectors staged in LDS one step ahead
+  tjm_sync();                                     // V complete and visible
+  // Q = H_0 ... H_{k-1} [I; 0]
   const bool qlive = c < k;
   zd* q = x;
 #pragma unroll
   for (int i = 0; i < QRF_RPT; ++i) q[i] = cmk((qlive && g + 4 * i == c) ? 1.0 : 0.0, 0.0);
-  if (k > 0 && tid < m) H.v[(k - 1) & 1][tid] = tid >= k - 1 ? V[(long)(k - 1) * m + tid] : cmk(0.0, 0.0);
+  zd* blkbuf = (zd*)tjm_lds.gemm;                 // 2 x QRF_VB x QRF_ROWS
+  constexpr int PER = QRF_VB * QRF_ROWS / TJM_NT; // staged entries per thread
+  const int nblk = (k + QRF_VB - 1) / QRF_VB;
+  // block b holds reflectors j = jb .. jb + QRF_VB - 1 (jb = b QRF_VB), in
+  // rows [jj][row]; blocks are applied from the last one down
+  zd nxt[PER];
+  auto fetch = [&](int bi) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * TJM_NT, jj = e / QRF_ROWS, r = e % QRF_ROWS, j = bi * QRF_VB + jj;
+      zd v = cmk(0.0, 0.0);
+      if (j < k && r >= j && r < m) v = V[(long)j * m + r];
+      nxt[u] = v;
+    }
+  };
+  auto stage = [&](int bi) {
+    zd* dst = blkbuf + (bi & 1) * (QRF_VB * QRF_ROWS);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) dst[tid + u * TJM_NT] = nxt[u];
+  };
+  if (nblk > 0) { fetch(nblk - 1); stage(nblk - 1); }
   tjm_sync();
-  for (int j = k - 1; j >= 0; --j) {
-    const zd* vb = H.v[j & 1];
-    zd nxt = cmk(0.0, 0.0);
-    if (j > 0 && tid < m && tid >= j - 1) nxt = V[(long)(j - 1) * m + tid];
-    const double vn = H.vn[j];
-    if (qlive && c >= j && vn > 0.0) qrf_reflect(q, vb, j, m, g, vn);
-    if (j > 0 && tid < m) H.v[(j - 1) & 1][tid] = nxt;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    if (bi > 0) fetch(bi - 1);                    // in flight while this block is applied
+    const zd* cur = blkbuf + (bi & 1) * (QRF_VB * QRF_ROWS);
+    for (int jj = QRF_VB - 1; jj >= 0; --jj) {
+      const int j = bi * QRF_VB + jj;
+      if (j >= k) continue;
+      const double vn = H.vn[j];
+      if (qlive && c >= j && vn > 0.0) qrf_reflect(q, cur + jj * QRF_ROWS, j, m, g, vn);
+    }
+    if (bi > 0) stage(bi - 1);                    // the other buffer: read by nobody now
     tjm_sync();
   }
   // column c of Q times ph_c

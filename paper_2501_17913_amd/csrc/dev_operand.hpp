@@ -88,7 +88,7 @@ TJM_DEV cplx<T> mix_row(const int* rp, const MixEnt* ent, int row, const cplx<S>
 // read once and the NE source loads of each nonzero are issued together.
 template <typename T, typename S, int NE>
 TJM_DEV void mix_gather(const int* rp, const MixEnt* ent, const cplx<S>* src, long sw, long ss,
-                        const int* row, const long* base, const bool* ok, cplx<T>* out) {
+                        const int* row, const int* base, const bool* ok, cplx<T>* out) {
   // only in-range elements name a mixing row (an out-of-range one may not)
   int r0 = -1;
   bool same = true;
@@ -149,13 +149,12 @@ template <typename S> struct MixRows {
   }
   template <typename T, int NE>
   TJM_DEV void gather(int wo, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
-    int row[NE];
-    long base[NE];
+    int row[NE], base[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int a = ii[u] / dph, so = ii[u] - a * dph;
       row[u] = wo * dph + so;
-      base[u] = (long)a * sa + kk[u];
+      base[u] = a * (int)sa + kk[u];
     }
     mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
   }
@@ -174,13 +173,12 @@ template <typename S> struct MixCols {
   }
   template <typename T, int NE>
   TJM_DEV void gather(int wo, const int* aa, const int* kk, const bool* ok, cplx<T>* out) const {
-    int row[NE];
-    long base[NE];
+    int row[NE], base[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int so = kk[u] / nb_, b = kk[u] - so * nb_;
       row[u] = wo * dph + so;
-      base[u] = (long)aa[u] * sa + b;
+      base[u] = aa[u] * (int)sa + b;
     }
     mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
   }

@@ -119,14 +119,14 @@ template <typename Tc> struct Tjm {
     const int Dm = P.Dmax;
     bool acc = false;
     if (nL > 0) {      // left class: (chl x chl) . (chl x dp chr), summed over channels
-      blk_cgemm<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
+      blk_cgemm_auto<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
                     mix_cols(q, ptrL, P.mixL, dp, chr, 0L, (long)dp * chr, (long)chr), y, dp * chr, 0, false,
                     tjm_lds.gemm);
       tjm_sync();        // the small-product path returns without a barrier
       acc = true;
     }
     if (nR > 0) {      // right class: (chl dp x chr) . (chr x chr), summed over channels
-      blk_cgemm<Tc>(chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
+      blk_cgemm_auto<Tc>(chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
                     chan_mat(Re, chr, (long)chr * chr, chanR), y, chr, 0, acc, tjm_lds.gemm);
       tjm_sync();
       acc = true;

@@ -54,8 +54,8 @@ template <typename T>
 __global__ __launch_bounds__(TJM_NT) void st_cgemm_kernel(int M, int N, int K, int nb, int sum,
     const zd* A, int lda, long bsA, int tA, int cA, const zd* B, int ldb, long bsB, int tB, int cB,
     zd* C, int ldc, long cs, int acc) {
-  blk_cgemm<T>(M, N, K, nb, sum != 0, cmat(A, lda, bsA, tA != 0, cA != 0),
-               cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, tjm_lds.gemm);
+  blk_cgemm_auto<T>(M, N, K, nb, sum != 0, cmat(A, lda, bsA, tA != 0, cA != 0),
+                    cmat(B, ldb, bsB, tB != 0, cB != 0), C, ldc, cs, acc != 0, tjm_lds.gemm);
 }
 
 __global__ __launch_bounds__(TJM_NT) void st_qr_kernel(int m, int n, zd* X, zd* Q, zd* R, zd* V) {

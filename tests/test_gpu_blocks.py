@@ -27,7 +27,8 @@ def _op(X, trans, conj):
 
 @pytest.mark.parametrize("prec", [tjm.PREC_FP64, tjm.PREC_MIXED])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (7, 5, 3), (16, 8, 2), (33, 17, 9), (64, 64, 64),
-                                   (100, 37, 64), (128, 64, 128)])
+                                   (100, 37, 64), (128, 64, 128),
+                                   (64, 128, 64), (128, 64, 64), (100, 200, 37), (200, 100, 70), (64, 256, 64), (256, 64, 64)])
 def test_cgemm_plain(prec, M, N, K):
     A, B = cr(M, K), cr(K, N)
     C = tjm.selftest_cgemm(prec, M, N, K, A, B).reshape(M, N)
@@ -51,8 +52,9 @@ def test_cgemm_transpose_conjugate(prec, tA, cA, tB, cB):
 
 @pytest.mark.parametrize("prec", [tjm.PREC_FP64, tjm.PREC_MIXED])
 @pytest.mark.parametrize("sum_batches", [True, False])
-def test_cgemm_batched_and_accumulate(prec, sum_batches):
-    M, N, K, nb = 19, 24, 13, 5
+@pytest.mark.parametrize("M,N,K", [(19, 24, 13), (64, 128, 40), (128, 64, 40)])
+def test_cgemm_batched_and_accumulate(prec, sum_batches, M, N, K):
+    nb = 5
     A, B = cr(nb, M, K), cr(nb, K, N)
     C0 = cr(M, N) if sum_batches else cr(nb, M, N)
     C = tjm.selftest_cgemm(prec, M, N, K, A, B, C0=C0, nb=nb, sum_batches=sum_batches, bsA=M * K, bsB=K * N,
