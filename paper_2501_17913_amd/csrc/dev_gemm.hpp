@@ -80,48 +80,74 @@ template <int BN, int BK> TJM_DEV void b_coord(bool trans, int u, int& k, int& j
   else { j = e % BN; k = e / BN; }
 }
 
+// The raw elements of one k-chunk a thread stages, between their loads and
+// their conversion and store to LDS.
+template <typename T, int BM, int BN, class OA, class OB> struct GemmStage {
+  typedef GemmT<T, BM, BN> G;
+  typename OA::raw_t ra[G::AE];
+  typename OB::raw_t rb[G::BE];
+  bool oa[G::AE], ob[G::BE];
+};
+
 template <typename T, int BM, int BN, class OA, class OB>
 TJM_DEV void gemm_load(const OA& A, const OB& B, int b, int i0, int j0, int k0, int M, int N, int K,
-                       cplx<T>* ra, cplx<T>* rb) {
+                       GemmStage<T, BM, BN, OA, OB>& st) {
   typedef GemmT<T, BM, BN> G;
   constexpr int BK = G::BK, AE = G::AE, BE = G::BE;
   int ia[AE], ka[AE], kb[BE], jb[BE];
-  bool oa[AE], ob[BE];
 #pragma unroll
   for (int u = 0; u < AE; ++u) {
     int i, k;
     a_coord<BM, BK>(A.trans, u, i, k);
     ia[u] = i0 + i; ka[u] = k0 + k;
-    oa[u] = ia[u] < M && ka[u] < K;
+    st.oa[u] = ia[u] < M && ka[u] < K;
   }
 #pragma unroll
   for (int u = 0; u < BE; ++u) {
     int k, j;
     b_coord<BN, BK>(B.trans, u, k, j);
     kb[u] = k0 + k; jb[u] = j0 + j;
-    ob[u] = kb[u] < K && jb[u] < N;
+    st.ob[u] = kb[u] < K && jb[u] < N;
   }
-  A.template gather<T, AE>(b, ia, ka, oa, ra);
-  B.template gather<T, BE>(b, kb, jb, ob, rb);
+  A.template fetch<AE>(b, ia, ka, st.oa, st.ra);
+  B.template fetch<BE>(b, kb, jb, st.ob, st.rb);
 }
 
-template <typename T, int BM, int BN>
-TJM_DEV void gemm_store(bool ta, bool tb, const cplx<T>* ra, const cplx<T>* rb, cplx<T>* As, cplx<T>* Bs) {
+template <typename T, int BM, int BN, class OA, class OB>
+TJM_DEV void gemm_store(const OA& A, const OB& B, const GemmStage<T, BM, BN, OA, OB>& st, cplx<T>* As,
+                        cplx<T>* Bs) {
   typedef GemmT<T, BM, BN> G;
   constexpr int BK = G::BK, AE = G::AE, BE = G::BE;
 #pragma unroll
   for (int u = 0; u < AE; ++u) {
     int i, k;
-    a_coord<BM, BK>(ta, u, i, k);
-    As[k * G::APAD + i] = ra[u];
+    a_coord<BM, BK>(A.trans, u, i, k);
+    As[k * G::APAD + i] = A.template value<T>(st.ra[u], st.oa[u]);
   }
 #pragma unroll
   for (int u = 0; u < BE; ++u) {
     int k, j;
-    b_coord<BN, BK>(tb, u, k, j);
-    Bs[k * G::BPAD + j] = rb[u];
+    b_coord<BN, BK>(B.trans, u, k, j);
+    Bs[k * G::BPAD + j] = B.template value<T>(st.rb[u], st.ob[u]);
   }
 }
+
+// Lane constants of the real embedding (see the top of this file): lane
+// (q = lane / 16, r16 = lane % 16) feeds A the part kp = q % 2 of its complex
+// element, and B the entry [[Re, Im], [-Im, Re]][kp][cpart] (cpart = r16 % 2)
+// of its complex element, i.e. fa Re + fb Im.  Arithmetic selects, so that the
+// fragment reads are plain unconditional LDS loads.
+template <typename T> struct EmbedLane {
+  T aa, ab, fa, fb;
+  TJM_DEV EmbedLane(int kp, int cpart) {
+    aa = kp ? (T)0 : (T)1;
+    ab = kp ? (T)1 : (T)0;
+    fa = kp == cpart ? (T)1 : (T)0;
+    fb = kp == cpart ? (T)0 : (kp ? (T)-1 : (T)1);
+  }
+  TJM_DEV T a(cplx<T> e) const { return aa * e.re + ab * e.im; }
+  TJM_DEV T b(cplx<T> e) const { return fa * e.re + fb * e.im; }
+};
 
 // Small products: each wavefront owns 32 x 16 complex blocks and feeds the
 // matrix cores straight from memory (no LDS, no workgroup barriers).
@@ -136,6 +162,7 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
   const int kq = q >> 1;
   const int kp = q & 1;
   const int cpart = r16 & 1;
+  const EmbedLane<T> emb(kp, cpart);
   const int nti = (M + 31) / 32, ntj = (N + 15) / 16;
   const int nout = sum_batches ? 1 : nb;
   const int nitems = nout * nti * ntj;
@@ -158,19 +185,13 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const int row = i0 + 16 * t + r16;
-          T v = (T)0;
-          if (kin && row < M) {
-            cplx<T> e = A.template get<T>(b, row, kc);
-            v = kp ? e.im : e.re;
-          }
-          av[t] = v;
+          const bool oka = kin && row < M;
+          const cplx<T> ea = A.template get<T>(b, oka ? row : 0, oka ? kc : 0);
+          av[t] = oka ? emb.a(ea) : (T)0;
           const int col = j0 + 8 * t + (r16 >> 1);
-          T w = (T)0;
-          if (kin && col < N) {
-            cplx<T> e = B.template get<T>(b, kc, col);
-            w = (kp == cpart) ? e.re : (kp ? -e.im : e.im);
-          }
-          bv[t] = w;
+          const bool okb = kin && col < N;
+          const cplx<T> eb = B.template get<T>(b, okb ? kc : 0, okb ? col : 0);
+          bv[t] = okb ? emb.b(eb) : (T)0;
         }
         acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
         acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
@@ -226,6 +247,7 @@ TJM_DEV void blk_cgemm_t(int M, int N, int K, int nb, bool sum_batches,
   const int kq = q >> 1;             // complex k offset 0/1
   const int kp = q & 1;              // real/imag part of the k index
   const int cpart = r16 & 1;         // real/imag part of the output column
+  const EmbedLane<T> emb(kp, cpart);
   const int wi = (tjm_wave() >> 1) * (BM / 2);   // quarter origin inside the tile
   const int wj = (tjm_wave() & 1) * (BN / 2);
   const int nti = (M + BM - 1) / BM, ntj = (N + BN - 1) / BN;
@@ -244,30 +266,24 @@ TJM_DEV void blk_cgemm_t(int M, int N, int K, int nb, bool sum_batches,
       for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = Mfma<T>::zero();
     const int b_lo = sum_batches ? 0 : ob;
     const int nchunk = (sum_batches ? nb : 1) * nkc;
-    cplx<T> ra[G::AE], rb[G::BE];
-    gemm_load<T, BM, BN>(A, B, b_lo, i0, j0, 0, M, N, K, ra, rb);
+    GemmStage<T, BM, BN, OA, OB> st;
+    gemm_load<T, BM, BN>(A, B, b_lo, i0, j0, 0, M, N, K, st);
     for (int c = 0; c < nchunk; ++c) {
       tjm_sync();                                  // LDS free again
-      gemm_store<T, BM, BN>(A.trans, B.trans, ra, rb, As, Bs);
+      gemm_store<T, BM, BN>(A, B, st, As, Bs);
       tjm_sync();
       if (c + 1 < nchunk) {                        // next chunk in flight
         const int cn = c + 1;
-        gemm_load<T, BM, BN>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * BK, M, N, K, ra, rb);
+        gemm_load<T, BM, BN>(A, B, b_lo + cn / nkc, i0, j0, (cn % nkc) * BK, M, N, K, st);
       }
 #pragma unroll 2
       for (int kk = 0; kk < BK; kk += 2) {         // zero-padded past K
         const int kc = kk + kq;
         T av[TI], bv[TJ];
 #pragma unroll
-        for (int t = 0; t < TI; ++t) {
-          const cplx<T> ea = As[kc * G::APAD + wi + 16 * t + r16];
-          av[t] = kp ? ea.im : ea.re;
-        }
+        for (int t = 0; t < TI; ++t) av[t] = emb.a(As[kc * G::APAD + wi + 16 * t + r16]);
 #pragma unroll
-        for (int t = 0; t < TJ; ++t) {
-          const cplx<T> eb = Bs[kc * G::BPAD + wj + 8 * t + (r16 >> 1)];
-          bv[t] = (kp == cpart) ? eb.re : (kp ? -eb.im : eb.im);
-        }
+        for (int t = 0; t < TJ; ++t) bv[t] = emb.b(Bs[kc * G::BPAD + wj + 8 * t + (r16 >> 1)]);
 #pragma unroll
         for (int ti = 0; ti < TI; ++ti)
 #pragma unroll

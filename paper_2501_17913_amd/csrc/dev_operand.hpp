@@ -1,15 +1,23 @@
 // Operands of the workgroup GEMM.
 //
 // An operand is any object with
-//   bool trans;                                 which index is contiguous
+//   bool trans;                      which index is contiguous
+//   typedef ... raw_t;               one staged element between its load
+//                                    and its store to LDS
+//   template <int NE> void fetch(int b, const int* i, const int* k,
+//                                const bool* ok, raw_t* r) const;
+//   template <typename T> cplx<T> value(const raw_t& r, bool ok) const;
 //   template <typename T> cplx<T> get(int b, int i, int k) const;
-//   template <typename T, int NE> void gather(int b, const int* i, const int* k,
-//                                             const bool* ok, cplx<T>* out) const;
-// get returns element (i, k) of batch b converted to the compute type T;
-// gather fetches NE elements at once (zero where ok is false), so that their
-// loads are in flight together.  trans = false means k (the second index)
-// runs contiguously in memory, trans = true means i does; the stager walks
-// the contiguous index across neighbouring threads.
+// fetch issues the loads of NE elements of batch b and returns without
+// waiting for them: the address of an element outside the product (ok
+// false) is clamped into the operand, so that every load is unconditional
+// and all of them are in flight together.  value converts a loaded element
+// to the compute type T, zero where ok is false; the GEMM calls it only when
+// it stores the chunk to LDS, so the next chunk's loads overlap the current
+// chunk on the matrix cores.  get returns one element (i, k) of batch b,
+// which must be in range.  trans = false means k (the second index) runs
+// contiguously in memory, trans = true means i does; the stager walks the
+// contiguous index across neighbouring threads.
 #pragma once
 #include <dev_common.hpp>
 #include "tjm_params.h"
@@ -19,19 +27,26 @@
 //   trans = false: op(X)[i][k] = X[i][k]     trans = true: op(X)[i][k] = X[k][i]
 //   conj applies complex conjugation on top.
 template <typename S> struct CMat {
+  typedef cplx<S> raw_t;
   const cplx<S>* p;
   int ld;
   long bs;
   bool trans;
   bool conj;
+  TJM_DEV long off(int i, int k) const { return trans ? ((long)k * ld + i) : ((long)i * ld + k); }
   template <typename T> TJM_DEV cplx<T> get(int b, int i, int k) const {
-    const cplx<S> v = p[(long)b * bs + (trans ? ((long)k * ld + i) : ((long)i * ld + k))];
+    const cplx<S> v = p[(long)b * bs + off(i, k)];
     return cmk((T)v.re, conj ? (T)(-v.im) : (T)v.im);
   }
-  template <typename T, int NE>
-  TJM_DEV void gather(int b, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+  template <int NE>
+  TJM_DEV void fetch(int b, const int* ii, const int* kk, const bool* ok, raw_t* r) const {
+    const cplx<S>* base = p + (long)b * bs;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) out[u] = ok[u] ? get<T>(b, ii[u], kk[u]) : cmk((T)0, (T)0);
+    for (int u = 0; u < NE; ++u) r[u] = base[ok[u] ? off(ii[u], kk[u]) : 0L];
+  }
+  template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool ok) const {
+    const T re = (T)v.re, im = conj ? (T)(-v.im) : (T)v.im;
+    return cmk(ok ? re : (T)0, ok ? im : (T)0);
   }
 };
 
@@ -44,6 +59,7 @@ template <typename S> TJM_DEV CMat<S> cmat(const cplx<S>* p, int ld, long bs = 0
 // apart) of which batch b takes matrix chan[b]: the channels of an
 // environment that one class of effective-Hamiltonian terms uses.
 template <typename S> struct ChanMat {
+  typedef cplx<S> raw_t;
   const cplx<S>* p;
   int ld;
   long cs;
@@ -53,14 +69,14 @@ template <typename S> struct ChanMat {
     const cplx<S> v = p[(long)chan[b] * cs + (long)i * ld + k];
     return cmk((T)v.re, (T)v.im);
   }
-  template <typename T, int NE>
-  TJM_DEV void gather(int b, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+  template <int NE>
+  TJM_DEV void fetch(int b, const int* ii, const int* kk, const bool* ok, raw_t* r) const {
     const cplx<S>* base = p + (long)chan[b] * cs;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const cplx<S> v = ok[u] ? base[(long)ii[u] * ld + kk[u]] : cmk((S)0, (S)0);
-      out[u] = cmk((T)v.re, (T)v.im);
-    }
+    for (int u = 0; u < NE; ++u) r[u] = base[ok[u] ? (long)ii[u] * ld + kk[u] : 0L];
+  }
+  template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool ok) const {
+    return cmk(ok ? (T)v.re : (T)0, ok ? (T)v.im : (T)0);
   }
 };
 
@@ -83,49 +99,43 @@ TJM_DEV cplx<T> mix_row(const int* rp, const MixEnt* ent, int row, const cplx<S>
   return cmk(xr, xi);
 }
 
-// NE mixed elements; element u sums row row[u] at offset base[u].  When all
-// rows agree (the staging layouts make them agree) the row's nonzeros are
-// read once and the NE source loads of each nonzero are issued together.
-template <typename T, typename S, int NE>
-TJM_DEV void mix_gather(const int* rp, const MixEnt* ent, const cplx<S>* src, long sw, long ss,
-                        const int* row, const int* base, const bool* ok, cplx<T>* out) {
+// NE mixed elements, in FP64; element u sums row row[u] at offset base[u].
+// When all rows agree (the staging layouts make them agree) the row's
+// nonzeros are read once and the NE source loads of each nonzero are issued
+// together (clamped to the start of the source where ok is false).
+template <typename S, int NE>
+TJM_DEV void mix_fetch(const int* rp, const MixEnt* ent, const cplx<S>* src, long sw, long ss,
+                       const int* row, const int* base, const bool* ok, zd* out) {
   // only in-range elements name a mixing row (an out-of-range one may not)
   int r0 = -1;
   bool same = true;
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
+    out[u] = cmk(0.0, 0.0);
     if (!ok[u]) continue;
     if (r0 < 0) r0 = row[u];
     else same = same && row[u] == r0;
   }
-  if (r0 < 0) {
-#pragma unroll
-    for (int u = 0; u < NE; ++u) out[u] = cmk((T)0, (T)0);
-    return;
-  }
+  if (r0 < 0) return;
   if (same) {
-    T xr[NE], xi[NE];
-#pragma unroll
-    for (int u = 0; u < NE; ++u) { xr[u] = 0; xi[u] = 0; }
     const int q1 = rp[r0 + 1];
     for (int q = rp[r0]; q < q1; ++q) {
       const MixEnt m = ent[q];
       const long off = (long)m.w * sw + (long)m.s * ss;
-      const T mr = (T)m.re, mi = (T)m.im;
+      cplx<S> x[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) x[u] = src[ok[u] ? base[u] + off : off];
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
-        if (!ok[u]) continue;
-        const cplx<S> x = src[base[u] + off];
-        xr[u] += mr * (T)x.re - mi * (T)x.im;
-        xi[u] += mr * (T)x.im + mi * (T)x.re;
+        const double xr = ok[u] ? (double)x[u].re : 0.0, xi = ok[u] ? (double)x[u].im : 0.0;
+        out[u].re += m.re * xr - m.im * xi;
+        out[u].im += m.re * xi + m.im * xr;
       }
     }
-#pragma unroll
-    for (int u = 0; u < NE; ++u) out[u] = ok[u] ? cmk(xr[u], xi[u]) : cmk((T)0, (T)0);
   } else {
 #pragma unroll
     for (int u = 0; u < NE; ++u)
-      out[u] = ok[u] ? mix_row<T>(rp, ent, row[u], src + base[u], sw, ss) : cmk((T)0, (T)0);
+      if (ok[u]) out[u] = mix_row<double>(rp, ent, row[u], src + base[u], sw, ss);
   }
 }
 
@@ -137,6 +147,7 @@ TJM_DEV void mix_gather(const int* rp, const MixEnt* ent, const cplx<S>* src, lo
 //   MixCols:  op_wo[a][(so, b)] = the same sum
 // with the mixing rows indexed wo * dph + so.
 template <typename S> struct MixRows {
+  typedef zd raw_t;
   const cplx<S>* src;
   const int* rp;
   const MixEnt* ent;
@@ -147,8 +158,8 @@ template <typename S> struct MixRows {
     const int a = i / dph, so = i - a * dph;
     return mix_row<T>(rp, ent, wo * dph + so, src + (long)a * sa + b, sw, ss);
   }
-  template <typename T, int NE>
-  TJM_DEV void gather(int wo, const int* ii, const int* kk, const bool* ok, cplx<T>* out) const {
+  template <int NE>
+  TJM_DEV void fetch(int wo, const int* ii, const int* kk, const bool* ok, raw_t* out) const {
     int row[NE], base[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
@@ -156,11 +167,13 @@ template <typename S> struct MixRows {
       row[u] = wo * dph + so;
       base[u] = a * (int)sa + kk[u];
     }
-    mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
+    mix_fetch<S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
   }
+  template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool) const { return cmk((T)v.re, (T)v.im); }
 };
 
 template <typename S> struct MixCols {
+  typedef zd raw_t;
   const cplx<S>* src;
   const int* rp;
   const MixEnt* ent;
@@ -171,8 +184,8 @@ template <typename S> struct MixCols {
     const int so = k / nb_, b = k - so * nb_;
     return mix_row<T>(rp, ent, wo * dph + so, src + (long)a * sa + b, sw, ss);
   }
-  template <typename T, int NE>
-  TJM_DEV void gather(int wo, const int* aa, const int* kk, const bool* ok, cplx<T>* out) const {
+  template <int NE>
+  TJM_DEV void fetch(int wo, const int* aa, const int* kk, const bool* ok, raw_t* out) const {
     int row[NE], base[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
@@ -180,8 +193,9 @@ template <typename S> struct MixCols {
       row[u] = wo * dph + so;
       base[u] = aa[u] * (int)sa + b;
     }
-    mix_gather<T, S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
+    mix_fetch<S, NE>(rp, ent, src, sw, ss, row, base, ok, out);
   }
+  template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool) const { return cmk((T)v.re, (T)v.im); }
 };
 
 template <typename S>

@@ -27,6 +27,7 @@ struct Run {
   size_t bytes = 0;
   double init_ms = 0, step_ms_total = 0, step_ms_last = 0;
   int step_launches = 0;
+  int use_graph = 0;
   // device pointers needed at the end
   double* d_obs = nullptr;
   int* d_jlog = nullptr;
@@ -93,6 +94,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->certify_sweeps = -1;
   o->sweep_jumps = 1;
   o->generic_heff = 0;
+  o->graph = 0;
 }
 
 extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
@@ -684,6 +686,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
 
   Run* r = new Run();
   r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = n_obs; r->record_bonds = pl.P.record_bonds;
+  r->use_graph = opt.graph ? 1 : 0;
   r->P = pl.P;
   TjmParams& P = r->P;
   auto bail = [&](tjm_status st, const std::string& msg) {
@@ -782,11 +785,63 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   return TJM_OK;
 }
 
+// The launches of `steps` steps captured in one HIP graph on the run's
+// stream and replayed once: reset and step kernel per step, timing events
+// between the steps, one host synchronisation at the end.
+static tjm_status advance_graph(tjm_model* m, Run* r, int steps) {
+  std::vector<hipEvent_t> ev(steps + 1, nullptr);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  tjm_status st = TJM_OK;
+  std::string msg;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == TJM_OK) {
+      st = e == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE;
+      msg = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return st == TJM_OK;
+  };
+  for (auto& e : ev) if (!chk(hipEventCreate(&e), "hipEventCreate")) break;
+  bool capturing = false;
+  if (st == TJM_OK && chk(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {
+    capturing = true;
+    chk(hipEventRecord(ev[0], r->stream), "hipEventRecord");
+    for (int i = 0; i < steps && st == TJM_OK; ++i) {
+      chk(tjm_launch_reset(r->P.counter, r->stream), "reset");
+      chk(tjm_launch_step(r->P, r->steps_done + 1 + i, r->workers, r->stream), "step");
+      chk(hipEventRecord(ev[i + 1], r->stream), "hipEventRecord");
+    }
+  }
+  if (capturing) {
+    const hipError_t e = hipStreamEndCapture(r->stream, &g);
+    chk(e, "hipStreamEndCapture");
+  }
+  if (st == TJM_OK) chk(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (st == TJM_OK) chk(hipGraphLaunch(ge, r->stream), "hipGraphLaunch");
+  if (st == TJM_OK) chk(hipStreamSynchronize(r->stream), "hipStreamSynchronize");
+  if (st == TJM_OK) {
+    for (int i = 0; i < steps; ++i) {
+      float ms = 0;
+      if (!chk(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime")) break;
+      r->step_ms_last = ms;
+      r->step_ms_total += ms;
+      r->step_launches++;
+    }
+    r->steps_done += steps;
+  }
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
+  for (auto e : ev) if (e) (void)hipEventDestroy(e);
+  if (st != TJM_OK) return fail(m, st, msg);
+  return TJM_OK;
+}
+
 extern "C" tjm_status tjm_run_advance(tjm_model* m, int steps) {
   if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
   Run* r = m->run;
   if (!r) return fail(m, TJM_E_BUSY, "no run in progress");
   if (steps < 0 || r->steps_done + steps > r->n_steps) return fail(m, TJM_E_BUSY, "advance past the last step");
+  if (r->use_graph && steps > 0) return advance_graph(m, r, steps);
   for (int i = 0; i < steps; ++i) {
     const int k = r->steps_done + 1;
     HIPCHK(m, tjm_launch_reset(r->P.counter, r->stream));

@@ -240,6 +240,40 @@ def test_fp64_environment_jump_path_parity(case):
         assert np.abs(res['per_traj'][t] - ref).max() < 1e-10
 
 
+def test_graph_captured_steps_equal_direct_launches():
+    # the same run with its step launches captured in HIP graphs (one graph
+    # for the whole run, and one per call of a session advanced in uneven
+    # pieces with host work between the replays) equals the step-by-step
+    # launches bit for bit (FP64)
+    L, chi, init, n, N, g, gamma = inputs.small_cases()[5]
+    seed = inputs.SEED + 500
+    ref = gpu_run(L, chi, init, n, N, g, gamma, seed)
+    whole = gpu_run(L, chi, init, n, N, g, gamma, seed, graph=1)
+    mpo, s_, o_, r_ = models.xxx_model(L, 1.0, g, gamma)
+    m = tjm.Model(L, mpo, s_, o_, r_)
+    m.set_initial_product(models.product_state(inputs.init_bits(L, init)))
+    m.begin(N, 0.1, n * 0.1, chi, models.zx_observables(L), seed,
+            tjm.default_options(precision=tjm.PREC_FP64, record_bonds=1, graph=1))
+    done = 0
+    for piece in (1, 3, 2, n):
+        piece = min(piece, n - done)
+        if piece <= 0:
+            break
+        m.advance(piece)
+        done += piece
+        mid = m.read()                   # host work between the replays
+        assert np.array_equal(mid["jumps"][:, :2 * done], ref["jumps"][:, :2 * done])
+    parts = m.end(traces=True)
+    stats = m.stats()
+    m.close()
+    assert stats["step_launches"] == n
+    for res in (whole, parts):
+        assert np.array_equal(res["per_traj"], ref["per_traj"])
+        assert np.array_equal(res["jumps"], ref["jumps"])
+        assert np.array_equal(res["bonds"], ref["bonds"])
+        assert np.array_equal(res["mean"], ref["mean"])
+
+
 def test_degenerate_runs():
     """Edge cases of the method and the interface, each against the oracle:
     no jump operators at all, gamma = 0 (delta p = 0: never a jump), one

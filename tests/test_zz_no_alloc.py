@@ -9,8 +9,35 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-torch = pytest.importorskip("torch")
 from paper_2501_17913_amd import tjm  # noqa: E402
+
+# Device buffers come from the HIP runtime the library itself links (loaded
+# by soname, so this is the same copy): a second runtime in the process
+# (for example the one a framework bundles) would not share its devices.
+_hip = C.CDLL("libamdhip64.so.7")
+_hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+_hip.hipFree.argtypes = [C.c_void_p]
+_hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+_hip.hipDeviceSynchronize.argtypes = []
+_H2D, _D2H = 1, 2
+
+
+class _Dev:
+    """A device buffer holding a copy of a host array (or n bytes of NaN)."""
+
+    def __init__(self, host):
+        self.host = np.ascontiguousarray(host)
+        self.p = C.c_void_p()
+        assert _hip.hipMalloc(C.byref(self.p), max(self.host.nbytes, 16)) == 0
+        assert _hip.hipMemcpy(self.p, self.host.ctypes.data, self.host.nbytes, _H2D) == 0
+
+    def get(self):
+        out = np.empty_like(self.host)
+        assert _hip.hipMemcpy(out.ctypes.data, self.p, out.nbytes, _D2H) == 0
+        return out
+
+    def free(self):
+        _hip.hipFree(self.p)
 
 
 def _matrix(m, n, seed):
@@ -25,22 +52,22 @@ def _matrix(m, n, seed):
 def _noalloc(G, discard, cap, deg_tol, absorb):
     m, n = G.shape
     kmax = min(m, n)
-    dev = torch.device("cuda", 0)
-    dG = torch.from_numpy(np.ascontiguousarray(G).view(np.float64).reshape(-1).copy()).to(dev)
-    dleft = torch.full((2 * m * kmax,), np.nan, dtype=torch.float64, device=dev)
-    dright = torch.full((2 * kmax * n,), np.nan, dtype=torch.float64, device=dev)
-    dS = torch.full((kmax,), np.nan, dtype=torch.float64, device=dev)
-    dk = torch.zeros(1, dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-    st = tjm.lib.tjm_svd_noalloc(m, n, C.c_void_p(dG.data_ptr()), discard, cap, deg_tol, int(absorb),
-                                 C.c_void_p(dleft.data_ptr()), C.c_void_p(dright.data_ptr()),
-                                 C.c_void_p(dS.data_ptr()), C.c_void_p(dk.data_ptr()), None)
+    bufs = [_Dev(np.ascontiguousarray(G, np.complex128).view(np.float64)),
+            _Dev(np.full(2 * m * kmax, np.nan)), _Dev(np.full(2 * kmax * n, np.nan)),
+            _Dev(np.full(kmax, np.nan)), _Dev(np.zeros(1, np.int32))]
+    dG, dleft, dright, dS, dk = bufs
+    assert _hip.hipDeviceSynchronize() == 0
+    st = tjm.lib.tjm_svd_noalloc(m, n, dG.p, discard, cap, deg_tol, int(absorb), dleft.p, dright.p, dS.p, dk.p,
+                                 None)
     assert st == tjm.OK, tjm.lib.tjm_last_error(None)
-    torch.cuda.synchronize()
-    k = int(dk.cpu().item())
-    left = dleft.cpu().numpy()[:2 * m * k].view(np.complex128).reshape(m, k)
-    right = dright.cpu().numpy()[:2 * k * n].view(np.complex128).reshape(k, n)
-    return left, dS.cpu().numpy()[:k], right
+    assert _hip.hipDeviceSynchronize() == 0
+    k = int(dk.get()[0])
+    left = dleft.get()[:2 * m * k].view(np.complex128).reshape(m, k)
+    right = dright.get()[:2 * k * n].view(np.complex128).reshape(k, n)
+    S = dS.get()[:k]
+    for b in bufs:
+        b.free()
+    return left, S, right
 
 
 def test_svd_noalloc_equals_allocating_entry_point():
