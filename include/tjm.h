@@ -98,11 +98,13 @@ typedef struct {
                              L x W x M x R through a (D chi d chi)
                              intermediate.  Same operator, other rounding.  */
   int graph;              /* 1: tjm_run_advance captures its launches (work
-                             queue reset and step kernel of every step, with
-                             the timing events) in one HIP graph and replays
-                             it once, with no host synchronisation between
-                             steps; 0 (default): launches one step at a time
-                             and waits for each.  Same kernels, same results */
+                             queue reset and step kernel of every step) in
+                             one HIP graph and replays it once, with no host
+                             synchronisation between steps (the statistics
+                             then split the replay's duration equally over
+                             its steps); 0 (default): launches one step at a
+                             time and waits for each.  Same kernels, same
+                             results                                          */
 } tjm_options;
 
 typedef struct {

@@ -23,6 +23,34 @@ template <typename T, typename S> TJM_DEV cplx<T> ccast(cplx<S> a) { return cmk(
 typedef cplx<double> zd;
 typedef cplx<float> zf;
 
+// Load of element i of a complex array in global memory.  The pointer is
+// cast to the global address space: inside a separately compiled device
+// function a pointer argument is generic, and a generic (flat) load is
+// counted by the LDS wait counter too, so every wait for an LDS read would
+// also wait for it; a global load is not.
+template <typename S> TJM_DEV cplx<S> gload(const cplx<S>* p, long i) {
+  typedef S v2 __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(1))) v2 gv2;
+  const v2 v = ((gv2*)p)[i];
+  return cmk(v.x, v.y);
+}
+
+// Store of element i of a complex array in global memory (same reason).
+template <typename S> TJM_DEV void gstore(cplx<S>* p, long i, cplx<S> x) {
+  typedef S v2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) v2 gv2;
+  v2 v;
+  v.x = x.re;
+  v.y = x.im;
+  ((gv2*)p)[i] = v;
+}
+
+// The same for any trivially copyable value (tables of the run).
+template <typename V> TJM_DEV V gload_v(const V* p, long i) {
+  typedef const __attribute__((address_space(1))) V gV;
+  return ((gV*)p)[i];
+}
+
 // c ? a : b on complex values, as two scalar selects (a conditional on
 // struct lvalues becomes a select of addresses, which keeps a register
 // array in scratch memory)

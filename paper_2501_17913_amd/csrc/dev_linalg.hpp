@@ -232,7 +232,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
   for (int i = 0; i < QRF_RPT; ++i) {
     const int r = g + 4 * i;
     zd e = cmk(0.0, 0.0);
-    if (live && r < m) e = adj ? conjg(X[(long)c * m + r]) : X[(long)r * n + c];
+    if (live && r < m) e = adj ? conjg(gload(X, (long)c * m + r)) : gload(X, (long)r * n + c);
     x[i] = e;
   }
   tjm_sync();                                     // X is read before Q or R may overwrite it
@@ -284,13 +284,13 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
       const zd dg = ab > 0.0 ? cmk(ab, 0.0) : cmk(br, bi);
       const zd val = csel(r < c, ph * x[i], csel(r == c, dg, cmk(0.0, 0.0)));
       if (adj) {
-        R[(long)c * k + r] = conjg(val);
-        if (Rk) Rk[(long)r * n + c] = val;
+        gstore(R, (long)c * k + r, conjg(val));
+        if (Rk) gstore(Rk, (long)r * n + c, val);
       } else {
-        R[(long)r * n + c] = val;
+        gstore(R, (long)r * n + c, val);
       }
     }
-    if (c < k && r >= c && r < m) V[(long)c * m + r] = csel(r == c, H.v0[c], x[i]);
+    if (c < k && r >= c && r < m) gstore(V, (long)c * m + r, csel(r == c, H.v0[c], x[i]));
   }
   tjm_sync();                                     // V complete and visible
   // Q = H_0 ... H_{k-1} [I; 0]
@@ -309,7 +309,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     for (int u = 0; u < PER; ++u) {
       const int e = tid + u * TJM_NT, jj = e / QRF_ROWS, r = e % QRF_ROWS, j = bi * QRF_VB + jj;
       zd v = cmk(0.0, 0.0);
-      if (j < k && r >= j && r < m) v = V[(long)j * m + r];
+      if (j < k && r >= j && r < m) v = gload(V, (long)j * m + r);
       nxt[u] = v;
     }
   };
@@ -340,8 +340,8 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     for (int i = 0; i < QRF_RPT; ++i) {
       const int r = g + 4 * i;
       if (r < m) {
-        if (adj) Q[(long)c * m + r] = conjg(ph * q[i]);
-        else Q[(long)r * k + c] = ph * q[i];
+        if (adj) gstore(Q, (long)c * m + r, conjg(ph * q[i]));
+        else gstore(Q, (long)r * k + c, ph * q[i]);
       }
     }
   }
@@ -752,13 +752,17 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
   LanczosLds& Lz = tjm_lds.lz;
   BlkScratch& S = tjm_lds.S;
   const int tid = tjm_tid();
+  // the vector loops stride over the n entries with global loads unrolled by
+  // four, so that several iterations' loads are in flight together
   double b0 = 0.0;
-  for (int e = tid; e < n; e += TJM_NT) b0 += abs2(v[e]);
+#pragma unroll 4
+  for (int e = tid; e < n; e += TJM_NT) b0 += abs2(gload(v, e));
   b0 = sqrt(blk_sum(b0, S));
   if (b0 == 0.0) return 0;
   if (m_max > TJM_KMAX) m_max = TJM_KMAX;
   if (m_max > n) m_max = n;
-  for (int e = tid; e < n; e += TJM_NT) Q[e] = (1.0 / b0) * v[e];
+#pragma unroll 4
+  for (int e = tid; e < n; e += TJM_NT) gstore(Q, e, (1.0 / b0) * gload(v, e));
   tjm_sync();
   int used = 0;
   for (int j = 0; j < m_max; ++j) {
@@ -770,13 +774,16 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
     const int nq = j + 1;
     for (int i0 = 0; i0 < nq; i0 += 4) {
       double hr[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
+      const int nu = nq - i0 < 4 ? nq - i0 : 4;
+#pragma unroll 2
       for (int e = tid; e < n; e += TJM_NT) {
-        const zd x = w[e];
+        const zd x = gload(w, e);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (i0 + u >= nq) continue;
-          const zd p = cdotc(Q[(long)(i0 + u) * n + e], x);
-          hr[u] += p.re; hi[u] += p.im;
+          const zd qv = gload(Q, (long)(i0 + (u < nu ? u : 0)) * n + e);
+          const zd p = cdotc(qv, x);
+          hr[u] += u < nu ? p.re : 0.0;
+          hi[u] += u < nu ? p.im : 0.0;
         }
       }
 #pragma unroll
@@ -797,10 +804,11 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
     }
     tjm_sync();
     double bn = 0.0;
+#pragma unroll 2
     for (int e = tid; e < n; e += TJM_NT) {
-      zd x = w[e];
-      for (int i = 0; i < nq; ++i) x = x - cmk(Lz.hre[i], Lz.him[i]) * Q[(long)i * n + e];
-      w[e] = x;
+      zd x = gload(w, e);
+      for (int i = 0; i < nq; ++i) x = x - cmk(Lz.hre[i], Lz.him[i]) * gload(Q, (long)i * n + e);
+      gstore(w, e, x);
       bn += abs2(x);
     }
     bn = sqrt(blk_sum(bn, S));
@@ -815,14 +823,16 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
     used = j + 1;
     if (Lz.done) break;
     zd* qn = Q + (long)(j + 1) * n;
-    for (int e = tid; e < n; e += TJM_NT) qn[e] = (1.0 / bn) * w[e];
+#pragma unroll 4
+    for (int e = tid; e < n; e += TJM_NT) gstore(qn, e, (1.0 / bn) * gload(w, e));
     tjm_sync();
   }
   // v = b0 * sum_i c_i q_i
+#pragma unroll 2
   for (int e = tid; e < n; e += TJM_NT) {
     zd x = cmk(0.0, 0.0);
-    for (int i = 0; i < used; ++i) x = x + cmk(Lz.cre[i], Lz.cim[i]) * Q[(long)i * n + e];
-    v[e] = b0 * x;
+    for (int i = 0; i < used; ++i) x = x + cmk(Lz.cre[i], Lz.cim[i]) * gload(Q, (long)i * n + e);
+    gstore(v, e, b0 * x);
   }
   tjm_sync();
   return used;

@@ -35,14 +35,14 @@ template <typename S> struct CMat {
   bool conj;
   TJM_DEV long off(int i, int k) const { return trans ? ((long)k * ld + i) : ((long)i * ld + k); }
   template <typename T> TJM_DEV cplx<T> get(int b, int i, int k) const {
-    const cplx<S> v = p[(long)b * bs + off(i, k)];
+    const cplx<S> v = gload(p, (long)b * bs + off(i, k));
     return cmk((T)v.re, conj ? (T)(-v.im) : (T)v.im);
   }
   template <int NE>
   TJM_DEV void fetch(int b, const int* ii, const int* kk, const bool* ok, raw_t* r) const {
     const cplx<S>* base = p + (long)b * bs;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) r[u] = base[ok[u] ? off(ii[u], kk[u]) : 0L];
+    for (int u = 0; u < NE; ++u) r[u] = gload(base, ok[u] ? off(ii[u], kk[u]) : 0L);
   }
   template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool ok) const {
     const T re = (T)v.re, im = conj ? (T)(-v.im) : (T)v.im;
@@ -66,14 +66,14 @@ template <typename S> struct ChanMat {
   const int* chan;
   bool trans;
   template <typename T> TJM_DEV cplx<T> get(int b, int i, int k) const {
-    const cplx<S> v = p[(long)chan[b] * cs + (long)i * ld + k];
+    const cplx<S> v = gload(p, (long)gload_v(chan, b) * cs + (long)i * ld + k);
     return cmk((T)v.re, (T)v.im);
   }
   template <int NE>
   TJM_DEV void fetch(int b, const int* ii, const int* kk, const bool* ok, raw_t* r) const {
-    const cplx<S>* base = p + (long)chan[b] * cs;
+    const cplx<S>* base = p + (long)gload_v(chan, b) * cs;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) r[u] = base[ok[u] ? (long)ii[u] * ld + kk[u] : 0L];
+    for (int u = 0; u < NE; ++u) r[u] = gload(base, ok[u] ? (long)ii[u] * ld + kk[u] : 0L);
   }
   template <typename T> TJM_DEV cplx<T> value(const raw_t& v, bool ok) const {
     return cmk(ok ? (T)v.re : (T)0, ok ? (T)v.im : (T)0);
@@ -84,14 +84,25 @@ template <typename S> TJM_DEV ChanMat<S> chan_mat(const cplx<S>* p, int ld, long
   ChanMat<S> m; m.p = p; m.ld = ld; m.cs = cs; m.chan = chan; m.trans = false; return m;
 }
 
+// one mixing entry, loaded field by field from global memory
+TJM_DEV MixEnt gload_ent(const MixEnt* ent, int q) {
+  const MixEnt* e = ent + q;
+  MixEnt m;
+  m.w = gload_v(&e->w, 0);
+  m.s = gload_v(&e->s, 0);
+  m.re = gload_v(&e->re, 0);
+  m.im = gload_v(&e->im, 0);
+  return m;
+}
+
 // sum over the nonzeros (wi, si, v) of one mixing row of v * x(wi, si)
 template <typename T, typename S>
 TJM_DEV cplx<T> mix_row(const int* rp, const MixEnt* ent, int row, const cplx<S>* base, long sw, long ss) {
   T xr = 0, xi = 0;
-  const int q1 = rp[row + 1];
-  for (int q = rp[row]; q < q1; ++q) {
-    const MixEnt m = ent[q];
-    const cplx<S> x = base[(long)m.w * sw + (long)m.s * ss];
+  const int q1 = gload_v(rp, row + 1);
+  for (int q = gload_v(rp, row); q < q1; ++q) {
+    const MixEnt m = gload_ent(ent, q);
+    const cplx<S> x = gload(base, (long)m.w * sw + (long)m.s * ss);
     const T mr = (T)m.re, mi = (T)m.im;
     xr += mr * (T)x.re - mi * (T)x.im;
     xi += mr * (T)x.im + mi * (T)x.re;
@@ -118,13 +129,13 @@ TJM_DEV void mix_fetch(const int* rp, const MixEnt* ent, const cplx<S>* src, lon
   }
   if (r0 < 0) return;
   if (same) {
-    const int q1 = rp[r0 + 1];
-    for (int q = rp[r0]; q < q1; ++q) {
-      const MixEnt m = ent[q];
+    const int q1 = gload_v(rp, r0 + 1);
+    for (int q = gload_v(rp, r0); q < q1; ++q) {
+      const MixEnt m = gload_ent(ent, q);
       const long off = (long)m.w * sw + (long)m.s * ss;
       cplx<S> x[NE];
 #pragma unroll
-      for (int u = 0; u < NE; ++u) x[u] = src[ok[u] ? base[u] + off : off];
+      for (int u = 0; u < NE; ++u) x[u] = gload(src, ok[u] ? base[u] + off : off);
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
         const double xr = ok[u] ? (double)x[u].re : 0.0, xi = ok[u] ? (double)x[u].im : 0.0;
