@@ -23,6 +23,7 @@ X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
 Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
 Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 SIGMA_MINUS = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+SIGMA_PLUS = np.array([[0, 0], [1, 0]], dtype=np.complex128)     # |1><0|, the adjoint of SIGMA_MINUS
 SIGMA_PLUS = SIGMA_MINUS.conj().T
 
 
@@ -149,6 +150,16 @@ def relax_dephase_jumps(L, gamma_minus, gamma_z):
     return out
 
 
+def relax_excite_jumps(L, gamma_minus, gamma_plus):
+    """Relaxation and excitation on every site (Sec. "New frontiers", the
+    30-site comparison): sigma_minus then sigma_plus at each site, site-major."""
+    out = []
+    for l in range(L):
+        out.append((l, SIGMA_MINUS.copy(), float(gamma_minus)))
+        out.append((l, SIGMA_PLUS.copy(), float(gamma_plus)))
+    return out
+
+
 def local_dissipator(jumps, site, tau, d=2):
     """D_l[tau] = exp(-1/2 tau sum_{j in S(l)} gamma_j L_j^dag L_j)
     (Eq. DissipativeMPO)."""
@@ -178,6 +189,12 @@ def neel_bits(L):
 
 def zero_bits(L):
     return [0] * L
+
+
+def domain_wall_bits(L):
+    """Domain wall of Sec. "New frontiers": site l (1-based) in |0> for
+    l < L/2 and in |1> for l >= L/2."""
+    return [0 if (s + 1) < L / 2 else 1 for s in range(L)]
 
 
 def product_dense(site_vecs):

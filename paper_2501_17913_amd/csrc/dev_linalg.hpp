@@ -185,25 +185,24 @@ constexpr int QRF_VB = 8;                          // reflectors per LDS block o
 static_assert(2 * QRF_VB * QRF_ROWS * 16 <= GEMM_LDS_BYTES, "two reflector blocks fit the staging area");
 
 // One reflector application to a column held in registers (rows g + 4 i,
-// i < QRF_RPT): x <- x - (2/vn) (v^H x) v over the rows r >= j, r < m; the
-// four threads of the column reduce the product by two shuffles.  Branch
-// free: every row's v is read (the buffer has 128 rows; rows outside
-// [j, m) may hold stale values) and masked by a select; the reads are taken
-// in chunks of eight rows with a scheduling barrier between chunks, so that
-// at most eight of them are live next to the 32 register-resident entries.
-TJM_DEV void qrf_reflect(zd* x, const zd* vb, int j, int m, int g, double vn) {
+// i < QRF_RPT): x <- x - (2/vn) (v^H x) v; the four threads of the column
+// reduce the product by two shuffles.  The reflector buffer holds zeros
+// outside the rows [j, m) of the reflector, so no row needs a mask; its
+// entries are read eight at a time into registers before they are used,
+// so that eight LDS reads are in flight together.
+TJM_DEV void qrf_reflect(zd* x, const zd* vb, int g, double vn) {
   double sr = 0.0, si = 0.0;
 #pragma unroll
   for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
+    zd vv[8];
 #pragma unroll
-    for (int i = i0; i < i0 + 8; ++i) {
-      const int r = g + 4 * i;
-      const bool on = r >= j && r < m;
-      const zd p = cdotc(vb[r], x[i]);
-      sr += on ? p.re : 0.0;
-      si += on ? p.im : 0.0;
+    for (int u = 0; u < 8; ++u) vv[u] = vb[g + 4 * (i0 + u)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const zd p = cdotc(vv[u], x[i0 + u]);
+      sr += p.re;
+      si += p.im;
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
   sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
@@ -211,13 +210,11 @@ TJM_DEV void qrf_reflect(zd* x, const zd* vb, int j, int m, int g, double vn) {
   const zd sc = cmk(f * sr, f * si);
 #pragma unroll
   for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
+    zd vv[8];
 #pragma unroll
-    for (int i = i0; i < i0 + 8; ++i) {
-      const int r = g + 4 * i;
-      const bool on = r >= j && r < m;
-      x[i] = csel(on, x[i] - sc * vb[r], x[i]);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+    for (int u = 0; u < 8; ++u) vv[u] = vb[g + 4 * (i0 + u)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[i0 + u] = x[i0 + u] - sc * vv[u];
   }
 }
 
@@ -241,14 +238,15 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     if (c == j) {
       // reflector of column j: x0 = X[j][j], beta = -(x0/|x0|) ||x||,
       // v = x with v0 = x0 - beta, ||v||^2 = 2 ||x|| (||x|| + |x0|); the
-      // whole column goes to the buffer (rows above j hold finished R
-      // entries and rows from m on zeros; the readers mask rows < j)
+      // buffer gets the rows >= j of the column and zeros above (rows from
+      // m on are zero in x)
       double a2 = 0.0;
 #pragma unroll
       for (int i = 0; i < QRF_RPT; ++i) {
         const int r = g + 4 * i;
-        a2 += r >= j ? abs2(x[i]) : 0.0;
-        vb[r] = x[i];
+        const zd e = csel(r >= j, x[i], cmk(0.0, 0.0));
+        a2 += abs2(e);
+        vb[r] = e;
       }
       a2 += tjm_shfl_xor(a2, 1);
       a2 += tjm_shfl_xor(a2, 2);
@@ -269,7 +267,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     tjm_sync();
     if (live && c > j) {
       const double vn = H.vn[j];
-      if (vn > 0.0) qrf_reflect(x, vb, j, m, g, vn);
+      if (vn > 0.0) qrf_reflect(x, vb, g, vn);
     }
   }
   tjm_sync();                                     // every reflector read; H.v free
@@ -308,9 +306,8 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + u * TJM_NT, jj = e / QRF_ROWS, r = e % QRF_ROWS, j = bi * QRF_VB + jj;
-      zd v = cmk(0.0, 0.0);
-      if (j < k && r >= j && r < m) v = gload(V, (long)j * m + r);
-      nxt[u] = v;
+      const bool on = j < k && r >= j && r < m;
+      nxt[u] = csel(on, gload(V, on ? (long)j * m + r : 0L), cmk(0.0, 0.0));
     }
   };
   auto stage = [&](int bi) {
@@ -327,7 +324,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
       const int j = bi * QRF_VB + jj;
       if (j >= k) continue;
       const double vn = H.vn[j];
-      if (qlive && c >= j && vn > 0.0) qrf_reflect(q, cur + jj * QRF_ROWS, j, m, g, vn);
+      if (qlive && c >= j && vn > 0.0) qrf_reflect(q, cur + jj * QRF_ROWS, g, vn);
     }
     if (bi > 0) stage(bi - 1);                    // the other buffer: read by nobody now
     tjm_sync();

@@ -56,6 +56,21 @@ def test_mps_tjm_ensemble_matches_lindblad():
     _check(S, exact)
 
 
+def test_dense_tjm_ensemble_relaxation_excitation_domain_wall():
+    # the noise and initial state of the 30-site comparison, on a chain the
+    # exact integrator reaches: sigma_-/sigma_+ at 0.1, XXX with J = h = 1
+    # (Z field), domain wall.  Jumps here are rare events (about one per
+    # site in 50 steps), so the ensemble is large enough to sample them.
+    L, dt, n, N = 5, 0.1, 12, 1500
+    H = model.xxx_dense(L, 1.0, 0.0, 1.0)
+    jumps = model.relax_excite_jumps(L, 0.1, 0.1)
+    obs = [(s, model.Z) for s in range(L)] + [(s, model.X) for s in range(L)]
+    psi0 = model.product_dense(model.product_site_vectors(L, model.domain_wall_bits(L)))
+    exact = lindblad.evolve_observables(H, jumps, psi0, dt, n, obs)
+    S = np.array([dense_tjm.run_trajectory(H, jumps, psi0, dt, n, obs, SEED, t) for t in range(N)])
+    _check(S, exact)
+
+
 def test_textbook_mcwf_ensemble_matches_lindblad():
     # first-order MCWF (Sec. "Monte Carlo wave function method") at small dt
     L, dt, n, N = 3, 0.01, 100, 500

@@ -127,6 +127,29 @@ def test_lindblad_both_channels_closed_form():
     del c0
 
 
+def test_lindblad_relaxation_excitation_closed_form():
+    # sigma_minus at gm and sigma_plus at gp: d<Z>/dt = (gm - gp) - (gm + gp) <Z>,
+    # so <Z> relaxes to (gm - gp)/(gm + gp) at rate gm + gp; the coherence
+    # decays at (gm + gp)/2
+    gm, gp, dt, n = 0.3, 0.12, 0.25, 14
+    H = np.zeros((2, 2), dtype=complex)
+    psi = np.array([np.cos(0.4), np.sin(0.4)], dtype=complex)
+    out = lindblad.evolve_observables(H, [(0, model.SIGMA_MINUS, gm), (0, model.SIGMA_PLUS, gp)], psi, dt, n,
+                                      [(0, model.Z), (0, model.X)])
+    t = dt * np.arange(n + 1)
+    zinf = (gm - gp) / (gm + gp)
+    z0 = np.cos(0.8)
+    assert np.abs(out[:, 0] - (zinf + (z0 - zinf) * np.exp(-(gm + gp) * t))).max() < 1e-13
+    assert np.abs(out[:, 1] - np.sin(0.8) * np.exp(-0.5 * (gm + gp) * t)).max() < 1e-13
+
+
+def test_domain_wall_bits():
+    # sites 1..L/2-1 in |0>, sites L/2..L in |1> (1-based), odd L included
+    assert model.domain_wall_bits(30) == [0] * 14 + [1] * 16
+    assert model.domain_wall_bits(7) == [0] * 3 + [1] * 4
+    assert model.domain_wall_bits(2) == [1, 1]
+
+
 def test_lindblad_vectorised_vs_rk4_three_sites():
     L = 3
     H = model.xxx_dense(L, 1.0, 0.5)
