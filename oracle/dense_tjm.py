@@ -44,13 +44,13 @@ def _jump(psi, full_jumps, eps, r):
     return psi / np.linalg.norm(psi), m
 
 
-def run_trajectory(H, jumps, psi0, dt, n_steps, observables, seed, traj, record=None):
+def run_trajectory(H, jumps, psi0, dt, n_steps, observables, seed, traj, record=None, dense_observables=()):
     L = int(round(np.log2(H.shape[0])))
     U = sla.expm(-1j * H * dt)
     Dh = _kron_all([model.local_dissipator(jumps, s, 0.5 * dt) for s in range(L)])
     Df = _kron_all([model.local_dissipator(jumps, s, dt) for s in range(L)])
     full = [(model.site_op_dense(op, s, L), g) for (s, op, g) in jumps]
-    obs = [model.site_op_dense(op, s, L) for (s, op) in observables]
+    obs = [model.site_op_dense(op, s, L) for (s, op) in observables] + list(dense_observables)
 
     def measure(p):
         return [np.real(np.vdot(p, O @ p)) for O in obs]

@@ -120,6 +120,17 @@ def tfim_mpo(L, J, g):
     return _lower_triangular_mpo(L, bulk)
 
 
+def product_mpo(L, ops):
+    """MPO of bond dimension 1 of the product operator prod_l O_l, with
+    O_l = ops[l] where given and the identity elsewhere (for instance
+    X_i X_{i+1} of Sec. "Effect of bond dimension and elapsed time")."""
+    Ws = []
+    for l in range(L):
+        O = ops.get(l, I2)
+        Ws.append(np.asarray(O, dtype=np.complex128).reshape(2, 2, 1, 1).copy())
+    return Ws
+
+
 def mpo_to_dense(Ws):
     """Contract an MPO into the dense operator (Methods, MPO section):
     O[(s1..sL), (s1'..sL')] = prod_l W_l^{s_l, s_l'}."""

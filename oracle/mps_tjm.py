@@ -400,6 +400,19 @@ def expectation_values(mps, observables):
     return out
 
 
+def mpo_expectation(mps, Wo):
+    """<Psi|O|Psi>/<Psi|Psi> for an MPO O (Eq. TJMExpVal with O stored as an
+    MPO; Methods, "Resources required for calculating expectation values"):
+    the MPS-MPO-MPS network contracted site by site from the left, with the
+    same environment update as TDVP; the real part (O Hermitian)."""
+    E = np.ones((1, 1, 1), dtype=np.complex128)
+    N = np.ones((1, 1), dtype=np.complex128)
+    for M, W in zip(mps, Wo):
+        E = left_update(E, M, W)
+        N = np.einsum('xa,sxy,sab->yb', N, M.conj(), M)
+    return float(np.real(E[0, 0, 0]) / np.real(N[0, 0]))
+
+
 # --------------------------------------------------------------------------
 # States and the trajectory schedule
 # --------------------------------------------------------------------------
@@ -442,8 +455,10 @@ def bonds(mps):
 
 
 def run_trajectory(Ws, jumps, psi0, dt, n_steps, observables, seed, traj, opt,
-                   record=None):
-    """One trajectory; returns [n_steps+1, n_obs] expectation values.
+                   record=None, mpo_observables=()):
+    """One trajectory; returns [n_steps+1, n_obs + n_mpo] expectation values:
+    the single-site observables, then the MPO observables (each a list of
+    site tensors W[s', s, w, w']), all measured on the same states.
 
     record (optional dict) receives 'jumps' [(step, branch, index)], 'bonds'
     (bond dimensions of the sampling MPS after each U), 'stats'."""
@@ -453,8 +468,14 @@ def run_trajectory(Ws, jumps, psi0, dt, n_steps, observables, seed, traj, opt,
     stats = Stats()
     phi = [M.copy() for M in psi0]
     canonicalize(phi)
-    out = np.zeros((n_steps + 1, len(observables)))
-    out[0] = expectation_values(phi, observables)
+    n_site = len(observables)
+
+    def measure(psi):
+        return np.concatenate([expectation_values(psi, observables),
+                               [mpo_expectation(psi, Wo) for Wo in mpo_observables]])
+
+    out = np.zeros((n_steps + 1, n_site + len(mpo_observables)))
+    out[0] = measure(phi)
     jlog = []
     blog = []
     # F_0 = J D[dt/2]
@@ -470,7 +491,7 @@ def run_trajectory(Ws, jumps, psi0, dt, n_steps, observables, seed, traj, opt,
         eps, r = philox.draws(seed, traj, k, philox.BRANCH_SAMPLE)
         m, _ = jump_process(y, jumps, eps, r, opt)
         jlog.append((k, philox.BRANCH_SAMPLE, m))
-        out[k] = expectation_values(y, observables)
+        out[k] = measure(y)
         if k < n_steps:                                   # F_k = J D[dt] U[dt]
             dissipate(phi, Df)
             eps, r = philox.draws(seed, traj, k, philox.BRANCH_MAIN)

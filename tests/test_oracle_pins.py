@@ -451,3 +451,63 @@ def test_expm_krylov_matches_dense_expm():
         assert np.abs(got - ref).max() < 1e-10 * np.linalg.norm(v)
     small = mps_tjm.expm_krylov(lambda x: Hm[:2, :2] @ x, v[:2], 0.7, 30, 1e-12)
     assert np.abs(small - sla.expm(-0.7j * Hm[:2, :2]) @ v[:2]).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# MPO observables (Eq. TJMExpVal with O an MPO; Methods, "Resources required
+# for calculating expectation values"): the MPS-MPO-MPS contraction against
+# dense linear algebra with operators built from Kronecker products
+# --------------------------------------------------------------------------
+
+def _random_mps(rng, bonds):
+    L = len(bonds) - 1
+    return [rng.normal(size=(2, bonds[s], bonds[s + 1])) + 1j * rng.normal(size=(2, bonds[s], bonds[s + 1]))
+            for s in range(L)]
+
+
+@pytest.mark.parametrize("bonds", [[1, 2, 4, 8, 4, 2, 1], [1, 2, 3, 3, 3, 2, 1], [1, 1, 1, 1, 1, 1, 1]])
+def test_mpo_expectation_matches_dense(bonds):
+    rng = np.random.default_rng(sum(bonds))
+    L = len(bonds) - 1
+    mps = _random_mps(rng, bonds)            # any gauge, any norm
+    psi = mps_tjm.mps_to_dense(mps)
+    nrm = np.real(np.vdot(psi, psi))
+
+    def dense_ev(O):
+        return np.real(np.vdot(psi, O @ psi)) / nrm
+
+    H = model.xxx_dense(L, 1.0, 0.3, 0.7)
+    assert abs(mps_tjm.mpo_expectation(mps, model.xxx_mpo(L, 1.0, 0.3, 0.7)) - dense_ev(H)) < 1e-12 * max(1, abs(dense_ev(H)))
+    for i in range(L - 1):
+        XX = model.site_op_dense(model.X, i, L) @ model.site_op_dense(model.X, i + 1, L)
+        v = mps_tjm.mpo_expectation(mps, model.product_mpo(L, {i: model.X, i + 1: model.X}))
+        assert abs(v - dense_ev(XX)) < 1e-12
+    ZYZ = model.site_op_dense(model.Z, 0, L) @ model.site_op_dense(model.Y, 2, L) @ model.site_op_dense(model.Z, L - 1, L)
+    v = mps_tjm.mpo_expectation(mps, model.product_mpo(L, {0: model.Z, 2: model.Y, L - 1: model.Z}))
+    assert abs(v - dense_ev(ZYZ)) < 1e-12
+    assert abs(mps_tjm.mpo_expectation(mps, model.product_mpo(L, {})) - 1.0) < 1e-12
+
+
+def test_full_rank_mpo_observables_equal_dense_tjm_per_trajectory():
+    # energy and nearest-neighbour XX correlators measured on the MPS
+    # trajectories equal the dense-vector TJM's with Kronecker-product
+    # operators, trajectory by trajectory
+    L = 4
+    rng = np.random.default_rng(44)
+    psi = rng.normal(size=2 ** L) + 1j * rng.normal(size=2 ** L)
+    psi /= np.linalg.norm(psi)
+    m0 = mps_tjm.dense_to_mps(psi, L)
+    Ws = model.xxx_mpo(L, 1.0, 0.5)
+    H = model.xxx_dense(L, 1.0, 0.5)
+    jumps = model.relax_dephase_jumps(L, 0.2, 0.2)
+    obs = [(s, model.Z) for s in range(L)]
+    mpo_obs = [Ws] + [model.product_mpo(L, {i: model.X, i + 1: model.X}) for i in range(L - 1)]
+    dense_obs = [H] + [model.site_op_dense(model.X, i, L) @ model.site_op_dense(model.X, i + 1, L) for i in range(L - 1)]
+    opt = mps_tjm.Options(chi_max=16, chi_cap=16, svd_discard=-1.0)
+    for traj in range(4):
+        r1, r2 = {}, {}
+        a = mps_tjm.run_trajectory(Ws, jumps, m0, 0.1, 6, obs, 3, traj, opt, r1, mpo_observables=mpo_obs)
+        b = dense_tjm.run_trajectory(H, jumps, psi, 0.1, 6, obs, 3, traj, r2, dense_observables=dense_obs)
+        assert r1['jumps'] == r2['jumps']
+        assert a.shape == b.shape == (7, L + L)
+        assert np.abs(a - b).max() < 1e-11
