@@ -235,7 +235,7 @@ def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers, read_ids=0, dea
         "achieved_tflops": flops_per_launch / (avg_ms * 1e-3) / 1e12, "workers": s1["workers"],
         "counts": {k: s1[k] - s0[k] for k in ("krylov_iters", "expm_calls", "one_site", "two_site",
                                               "factorizations", "jumps", "cmac_mix")},
-        "phase_frac": {k: round(v / tot, 4) for k, v in phases.items() if k not in ("total", "env")},
+        "phase_frac": {k: round(v / tot, 4) for k, v in phases.items() if k != "total"},
         "records": rec,
     }
 

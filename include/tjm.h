@@ -120,9 +120,11 @@ typedef struct {
   size_t device_bytes;            /* device memory held by the run            */
   /* workgroup-seconds summed over trajectories, by phase: [0] whole step
    * functions, [1] contractions (effective Hamiltonians, environments),
-   * [2] unused (0), [3] SVDs,
-   * [4] QR/LQ, [5] Lanczos exponentials including their contractions,
-   * [6] bond-matrix absorption and two-site products, [7] unused            */
+   * [2] jump processes (dissipation, sweeps, measurement, with their
+   * factorisations), [3] SVDs, [4] QR/LQ, [5] Lanczos exponentials
+   * including their contractions, [6] bond-matrix absorption and two-site
+   * products, [7] the matrix-core products inside the effective
+   * Hamiltonians (part of [1]).  Phases overlap where stated.             */
   double phase_s[8];
   int failed_traj;                /* trajectories flagged with a non-finite
                                      norm so far (tjm_run_end then returns

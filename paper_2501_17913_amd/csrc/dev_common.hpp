@@ -69,7 +69,7 @@ struct BlkScratch {
 // of additions is fixed (butterfly in each wavefront, then waves in order),
 // so the result does not depend on scheduling.
 TJM_DEV double blk_sum(double v, BlkScratch& S) {
-  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) v += tjm_shfl_xor(v, m);
+  v = tjm_grp_sum<TJM_WAVE>(v);
   if (tjm_lane() == 0) S.red[tjm_wave()] = v;
   tjm_sync();
   double s = 0.0;
@@ -80,7 +80,8 @@ TJM_DEV double blk_sum(double v, BlkScratch& S) {
 
 // Two (or up to four) simultaneous sums.
 TJM_DEV void blk_sum2(double& a, double& b, BlkScratch& S) {
-  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) { a += tjm_shfl_xor(a, m); b += tjm_shfl_xor(b, m); }
+  a = tjm_grp_sum<TJM_WAVE>(a);
+  b = tjm_grp_sum<TJM_WAVE>(b);
   if (tjm_lane() == 0) { S.red[2 * tjm_wave()] = a; S.red[2 * tjm_wave() + 1] = b; }
   tjm_sync();
   double sa = 0.0, sb = 0.0;
@@ -90,10 +91,8 @@ TJM_DEV void blk_sum2(double& a, double& b, BlkScratch& S) {
 }
 
 TJM_DEV void blk_sum4(double& a, double& b, double& c, double& d, BlkScratch& S) {
-  for (int m = TJM_WAVE / 2; m > 0; m >>= 1) {
-    a += tjm_shfl_xor(a, m); b += tjm_shfl_xor(b, m);
-    c += tjm_shfl_xor(c, m); d += tjm_shfl_xor(d, m);
-  }
+  a = tjm_grp_sum<TJM_WAVE>(a); b = tjm_grp_sum<TJM_WAVE>(b);
+  c = tjm_grp_sum<TJM_WAVE>(c); d = tjm_grp_sum<TJM_WAVE>(d);
   if (tjm_lane() == 0) {
     S.red[4 * tjm_wave()] = a; S.red[4 * tjm_wave() + 1] = b;
     S.red[4 * tjm_wave() + 2] = c; S.red[4 * tjm_wave() + 3] = d;
@@ -107,28 +106,34 @@ TJM_DEV void blk_sum4(double& a, double& b, double& c, double& d, BlkScratch& S)
   a = sa; b = sb; c = sc; d = sd;
 }
 
-// Sum of v over groups of g consecutive lanes (g a power of two <= 64); all
-// lanes of the group receive the group's sum.
-TJM_DEV double grp_sum(double v, int g) {
-  for (int m = g / 2; m > 0; m >>= 1) v += tjm_shfl_xor(v, m);
-  return v;
-}
-
-// The same for two and four values at once: the shuffles of one butterfly
-// step are issued together and wait once.
-TJM_DEV void grp_sum2(double& a, double& b, int g) {
-  for (int m = g / 2; m > 0; m >>= 1) {
-    const double ta = tjm_shfl_xor(a, m), tb = tjm_shfl_xor(b, m);
-    a += ta; b += tb;
-  }
+// Sum of v over groups of g consecutive lanes (g a power of two <= 64, a
+// run-time value); all lanes of the group receive the group's sum.
+template <int G>
+TJM_DEV void grp_sum4_t(double& a, double& b, double& c, double& d) {
+  a = tjm_grp_sum<G>(a); b = tjm_grp_sum<G>(b); c = tjm_grp_sum<G>(c); d = tjm_grp_sum<G>(d);
 }
 
 TJM_DEV void grp_sum4(double& a, double& b, double& c, double& d, int g) {
-  for (int m = g / 2; m > 0; m >>= 1) {
-    const double ta = tjm_shfl_xor(a, m), tb = tjm_shfl_xor(b, m);
-    const double tc = tjm_shfl_xor(c, m), td = tjm_shfl_xor(d, m);
-    a += ta; b += tb; c += tc; d += td;
+  switch (g) {
+    case 1: break;
+    case 2: grp_sum4_t<2>(a, b, c, d); break;
+    case 4: grp_sum4_t<4>(a, b, c, d); break;
+    case 8: grp_sum4_t<8>(a, b, c, d); break;
+    case 16: grp_sum4_t<16>(a, b, c, d); break;
+    case 32: grp_sum4_t<32>(a, b, c, d); break;
+    default: grp_sum4_t<64>(a, b, c, d); break;
   }
+}
+
+TJM_DEV void grp_sum2(double& a, double& b, int g) {
+  double c = 0.0, d = 0.0;
+  grp_sum4(a, b, c, d, g);
+}
+
+TJM_DEV double grp_sum(double v, int g) {
+  double b = 0.0, c = 0.0, d = 0.0;
+  grp_sum4(v, b, c, d, g);
+  return v;
 }
 
 // --------------------------------------------------------------------------

@@ -50,6 +50,8 @@ struct LanczosLds {
   double alpha[TJM_KMAX], beta[TJM_KMAX];
   double cre[TJM_KMAX], cim[TJM_KMAX];
   double hre[TJM_KMAX], him[TJM_KMAX];
+  double hsre[TJM_KMAX], hsim[TJM_KMAX];   // h_i s_i, then b0 c_i s_i
+  double scale[TJM_KMAX];                  // s_i: q_i = s_i B_i
   double red[TJM_NWAVE][2 * TJM_KMAX];
   double ur[TJM_KMAX], ui[TJM_KMAX], tr[TJM_KMAX], ti[TJM_KMAX];
   int done;

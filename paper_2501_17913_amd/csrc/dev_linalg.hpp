@@ -10,6 +10,26 @@
 #pragma once
 #include <dev_lds.hpp>
 
+// st(e, ld(e)) for every e < n (n >= 1), each thread's eight entries loaded
+// before any of them is stored, so that their loads are in flight together.
+// For maps whose stores do not feed their own loads.
+template <class Ld, class St>
+TJM_DEV void blk_map(int n, Ld ld, St st) {
+  for (int base = 0; base < n; base += 8 * TJM_NT) {
+    zd buf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + tjm_tid() + u * TJM_NT;
+      buf[u] = ld(e < n ? e : n - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + tjm_tid() + u * TJM_NT;
+      if (e < n) st(e, buf[u]);
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // Householder QR.  X (m x n, ld n, m <= 128) is destroyed.  On return Q
 // (m x k, ld k) and R (k x n, ld n) hold the thin factors, k = min(m, n),
@@ -186,12 +206,14 @@ static_assert(2 * QRF_VB * QRF_ROWS * 16 <= GEMM_LDS_BYTES, "two reflector block
 
 // One reflector application to a column held in registers (rows g + 4 i,
 // i < QRF_RPT): x <- x - (2/vn) (v^H x) v; the four threads of the column
-// reduce the product by two shuffles.  The reflector buffer holds zeros
-// outside the rows [j, m) of the reflector, so no row needs a mask; its
-// entries are read eight at a time into registers before they are used,
-// so that eight LDS reads are in flight together.
+// reduce the product by two shuffles.  The reflector buffer vb holds zeros
+// outside the rows [j, m) of the reflector, so no row needs a mask.  The
+// entries of vb are read eight at a time into registers, all eight reads
+// issued before the first is used, so that one LDS latency covers eight
+// rows.
 TJM_DEV void qrf_reflect(zd* x, const zd* vb, int g, double vn) {
-  double sr = 0.0, si = 0.0;
+  // four independent FMA chains: sum conj(v) x = (a + b) + i (c - e)
+  double sa = 0.0, sb = 0.0, sc = 0.0, se = 0.0;
 #pragma unroll
   for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
     zd vv[8];
@@ -199,26 +221,36 @@ TJM_DEV void qrf_reflect(zd* x, const zd* vb, int g, double vn) {
     for (int u = 0; u < 8; ++u) vv[u] = vb[g + 4 * (i0 + u)];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const zd p = cdotc(vv[u], x[i0 + u]);
-      sr += p.re;
-      si += p.im;
+      sa = fma(vv[u].re, x[i0 + u].re, sa);
+      sb = fma(vv[u].im, x[i0 + u].im, sb);
+      sc = fma(vv[u].re, x[i0 + u].im, sc);
+      se = fma(vv[u].im, x[i0 + u].re, se);
     }
+    __builtin_amdgcn_sched_barrier(0);            // keep the next batch's reads after this one
   }
-  sr += tjm_shfl_xor(sr, 1); si += tjm_shfl_xor(si, 1);
-  sr += tjm_shfl_xor(sr, 2); si += tjm_shfl_xor(si, 2);
+  double sr = sa + sb, si = sc - se;
+  sr = tjm_grp_sum<4>(sr);
+  si = tjm_grp_sum<4>(si);
   const double f = 2.0 / vn;
-  const zd sc = cmk(f * sr, f * si);
+  const double ar = f * sr, ai = f * si;
 #pragma unroll
   for (int i0 = 0; i0 < QRF_RPT; i0 += 8) {
     zd vv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) vv[u] = vb[g + 4 * (i0 + u)];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[i0 + u] = x[i0 + u] - sc * vv[u];
+    for (int u = 0; u < 8; ++u) {
+      x[i0 + u].re = fma(ai, vv[u].im, fma(-ar, vv[u].re, x[i0 + u].re));
+      x[i0 + u].im = fma(-ai, vv[u].re, fma(-ar, vv[u].im, x[i0 + u].im));
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool adj, zd* Rk) {
+// Reduction of the register QR: X (or X^H) to R, the reflectors to V
+// (m x k, column j's reflector at V + j m, rows [j, m)); the reflectors'
+// scalars stay in tjm_lds.qrf.
+TJM_DEVNI void qrf_reduce(int m, int n, const zd* X, zd* R, zd* V, bool adj, zd* Rk) {
   QrfLds& H = tjm_lds.qrf;
   const int tid = tjm_tid();
   const int c = tid >> 2, g = tid & 3;
@@ -228,9 +260,9 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
 #pragma unroll
   for (int i = 0; i < QRF_RPT; ++i) {
     const int r = g + 4 * i;
-    zd e = cmk(0.0, 0.0);
-    if (live && r < m) e = adj ? conjg(gload(X, (long)c * m + r)) : gload(X, (long)r * n + c);
-    x[i] = e;
+    const bool on = live && r < m;
+    const zd e = gload(X, on ? (adj ? (long)c * m + r : (long)r * n + c) : 0L);
+    x[i] = csel(on, adj ? conjg(e) : e, cmk(0.0, 0.0));
   }
   tjm_sync();                                     // X is read before Q or R may overwrite it
   for (int j = 0; j < k; ++j) {
@@ -248,8 +280,7 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
         a2 += abs2(e);
         vb[r] = e;
       }
-      a2 += tjm_shfl_xor(a2, 1);
-      a2 += tjm_shfl_xor(a2, 2);
+      a2 = tjm_grp_sum<4>(a2);
       __builtin_amdgcn_wave_barrier();
       const zd x0 = vb[j];                        // written by a lane of this wavefront
       const double ax0 = sqrt(abs2(x0)), al = sqrt(a2);
@@ -291,16 +322,26 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     if (c < k && r >= c && r < m) gstore(V, (long)c * m + r, csel(r == c, H.v0[c], x[i]));
   }
   tjm_sync();                                     // V complete and visible
-  // Q = H_0 ... H_{k-1} [I; 0]
+}
+
+// Formation of Q = H_0 ... H_{k-1} [I; 0] from the reflectors in V, in
+// registers (the layout of the reduction), written as Q (m x k) or, with
+// adj, Q^H (k x m).
+TJM_DEVNI void qrf_form(int m, int n, zd* Q, const zd* V, bool adj) {
+  QrfLds& H = tjm_lds.qrf;
+  const int tid = tjm_tid();
+  const int c = tid >> 2, g = tid & 3;
+  const int k = m < n ? m : n;
   const bool qlive = c < k;
-  zd* q = x;
+  zd q[QRF_RPT];
 #pragma unroll
   for (int i = 0; i < QRF_RPT; ++i) q[i] = cmk((qlive && g + 4 * i == c) ? 1.0 : 0.0, 0.0);
   zd* blkbuf = (zd*)tjm_lds.gemm;                 // 2 x QRF_VB x QRF_ROWS
   constexpr int PER = QRF_VB * QRF_ROWS / TJM_NT; // staged entries per thread
   const int nblk = (k + QRF_VB - 1) / QRF_VB;
   // block b holds reflectors j = jb .. jb + QRF_VB - 1 (jb = b QRF_VB), in
-  // rows [jj][row]; blocks are applied from the last one down
+  // rows [jj][row], zero outside the rows [j, m) of each; blocks are applied
+  // from the last one down
   zd nxt[PER];
   auto fetch = [&](int bi) {
 #pragma unroll
@@ -343,6 +384,11 @@ TJM_DEVNI void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool 
     }
   }
   tjm_sync();
+}
+
+TJM_DEV void blk_qr_regs(int m, int n, const zd* X, zd* Q, zd* R, zd* V, bool adj, zd* Rk) {
+  qrf_reduce(m, n, X, R, V, adj, Rk);
+  qrf_form(m, n, Q, V, adj);
 }
 
 // Thin QR X = Q R (k = min(m, n), diag(R) real >= 0) of an m x n matrix,
@@ -402,7 +448,7 @@ TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
 }
 
 // One cyclic sweep of one-sided Jacobi rotations over the ncol columns of W
-// (column-major, p rows, global memory or LDS): every pair once, the pairs
+// (column-major, p rows, the LDS work area tjm_lds.gemm): every pair once, the pairs
 // of a round in parallel, one thread group per pair.  With n1 > 0 only the
 // pairs between the first n1 columns and the others are visited: in round
 // r, column i meets column n1 + (i + r) mod max(n1, ncol - n1).  A pair whose columns
@@ -412,8 +458,9 @@ TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
 // off-diagonal |w_a^H w_b| / (|w_a| |w_b|) measured.  Ends with a barrier.
 constexpr int JAC_RPT = 8;           // rows per thread a pair keeps in registers
 
-TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double tol) {
+TJM_DEVNI void jacobi_sweep(int p, int ncol, int n1, double zero2, double tol) {
   SvdLds& SL = tjm_lds.sv;
+  zd* W = (zd*)tjm_lds.gemm;             // the columns, staged in LDS
   const int tid = tjm_tid();
   const int np = (ncol + 1) & ~1;        // players, a dummy if ncol is odd
   const int n2 = ncol - n1;
@@ -429,6 +476,10 @@ TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double
   const int span = JAC_RPT * tpp;         // rows one pass over the registers covers
   const int ngrp = TJM_NT / tpp;
   const int g = tid / tpp, gl = tid % tpp;
+  // this thread's largest relative off-diagonal and whether it rotated,
+  // merged into SL once at the end (not by an LDS atomic per pair and round)
+  double offm = 0.0;
+  bool rot = false;
   for (int rnd = 0; rnd < nrnd; ++rnd) {
     for (int pr = g; pr < npair; pr += ngrp) {
       int a, b;
@@ -464,10 +515,8 @@ TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double
       const double ac = hypot(cr, ci);
       if (!(aa > zero2 && bb > zero2)) continue;
       const double sab = sqrt(aa) * sqrt(bb);     // no overflow for large norms
-      if (gl == 0) {
-        const double rel = ac / sab;              // >= 0: its bits order like the value
-        atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1.0));
-      }
+      const double rel = ac / sab;
+      offm = fmax(offm, rel == rel ? rel : 1.0);
       if (ac > tol * sab) {
         const double inv = 1.0 / ac;
         const double zeta = 0.5 * (bb - aa) * inv;
@@ -495,11 +544,19 @@ TJM_DEVNI void jacobi_sweep(zd* W, int p, int ncol, int n1, double zero2, double
             }
           }
         }
-        if (gl == 0) atomicOr(&SL.rotated, 1);
+        rot = true;
       }
     }
     tjm_sync();
   }
+  for (int s = TJM_WAVE / 2; s > 0; s >>= 1) offm = fmax(offm, tjm_shfl_xor(offm, s));
+  const bool wrot = __any(rot);
+  if (tjm_lane() == 0) {
+    // offm >= 0: the bits of a non-negative double order like its value
+    atomicMax(&SL.offmax, (unsigned long long)__double_as_longlong(offm));
+    if (wrot) atomicOr(&SL.rotated, 1);
+  }
+  tjm_sync();
 }
 
 TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absorb_left,
@@ -524,10 +581,10 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
   // else in the global array Wc; glds is free until the final product
   double f2 = 0.0;
   if (pre) {
-    for (int e = tid; e < xr * p; e += TJM_NT) {
+    blk_map(xr * p, [&](int e) {
       const int i = e / p, c = e % p;    // X[i][c]
-      Tg[e] = tr ? G[(long)i * n + c] : conjg(G[(long)c * n + i]);
-    }
+      return tr ? gload(G, (long)i * n + c) : conjg(gload(G, (long)c * n + i));
+    }, [&](int e, zd x) { gstore(Tg, e, x); });
     tjm_sync();
     QrLds& H = *(QrLds*)glds;
     qr_reduce(xr, p, Tg, H, S);
@@ -535,14 +592,13 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
     tjm_sync();                          // H (in glds) is dead from here
   }
   if ((long)p * nc * 16 <= SVD_LDS_BYTES) Wc = (zd*)glds;
-  for (int e = tid; e < p * nc; e += TJM_NT) {
-    int c = e / p, r = e % p;            // Wc[c][r] = Gw[r][c]
+  blk_map(p * nc, [&](int e) {
+    const int c = e / p, r = e % p;      // Wc[c][r] = Gw[r][c]
     zd x;
-    if (pre) x = r < c ? cmk(0.0, 0.0) : conjg(Tg[(long)c * p + r]);   // (R^H)[r][c]
-    else x = tr ? conjg(G[(long)c * n + r]) : G[(long)r * n + c];
-    Wc[e] = x;
-    f2 += abs2(x);
-  }
+    if (pre) x = csel(r < c, cmk(0.0, 0.0), conjg(gload(Tg, (long)c * p + r)));   // (R^H)[r][c]
+    else x = tr ? conjg(gload(G, (long)c * n + r)) : gload(G, (long)r * n + c);
+    return x;
+  }, [&](int e, zd x) { Wc[e] = x; f2 += abs2(x); });
   // columns below 1e-14 ||G||_F carry weight < 1e-28 of the total, far
   // below any truncation threshold: they are not rotated (rotating them only
   // stirs rounding noise and never converges)
@@ -559,30 +615,47 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
   // column pair is visited once per sweep, and the matrix is read and
   // written nb times per sweep instead of once per column pair.
   const bool in_lds = (long)p * nc * 16 <= SVD_LDS_BYTES;
-  const int bw = in_lds ? nc : SVD_LDS_BYTES / (32 * p);
-  const bool blocked = !in_lds && bw >= 2;
+  const int bw = in_lds ? nc : SVD_LDS_BYTES / (32 * p);   // >= 2 for p <= 1024
+  const bool blocked = !in_lds;
   const int nb = blocked ? (nc + bw - 1) / bw : 1;
   const int nbp = (nb + 1) & ~1;
-  zd* Lc = (zd*)glds;
+  zd* Lc = (zd*)tjm_lds.gemm;
   for (int sweep = 0; sweep < 40 && nc >= 2; ++sweep) {
     if (tid == 0) { SL.rotated = 0; SL.offmax = 0ull; }
     tjm_sync();
     if (!blocked) {
-      jacobi_sweep(Wc, p, nc, 0, zero2, tol);
+      jacobi_sweep(p, nc, 0, zero2, tol);
     } else {
-      // stage columns [c0, c0 + cI) and [c1, c1 + cJ) in Lc, or write them back
+      // stage columns [c0, c0 + cI) and [c1, c1 + cJ) in Lc, or write them
+      // back; eight entries per thread in flight
       auto move = [&](bool in, int c0, int cI, int c1, int cJ) {
-        for (int e = tid; e < (cI + cJ) * p; e += TJM_NT) {
-          const int c = e / p, r = e % p;
-          zd* w = Wc + (long)(c < cI ? c0 + c : c1 + c - cI) * p + r;
-          if (in) Lc[e] = *w; else *w = Lc[e];
+        const int tot = (cI + cJ) * p;
+        for (int base = 0; base < tot; base += 8 * TJM_NT) {
+          zd buf[8];
+          long gi[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            int e = base + tid + u * TJM_NT;
+            e = e < tot ? e : tot - 1;
+            const int c = e / p, r = e % p;
+            gi[u] = (long)(c < cI ? c0 + c : c1 + c - cI) * p + r;
+            buf[u] = in ? gload(Wc, gi[u]) : Lc[e];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = base + tid + u * TJM_NT;
+            if (e < tot) {
+              if (in) Lc[e] = buf[u];
+              else gstore(Wc, gi[u], buf[u]);
+            }
+          }
         }
         tjm_sync();
       };
       for (int I = 0; I < nb; ++I) {
         const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
         move(true, c0, cI, 0, 0);
-        jacobi_sweep(Lc, p, cI, 0, zero2, tol);
+        jacobi_sweep(p, cI, 0, zero2, tol);
         move(false, c0, cI, 0, 0);
       }
       for (int rnd = 0; rnd < nbp - 1; ++rnd)
@@ -593,7 +666,7 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
           const int c0 = I * bw, cI = nc - c0 < bw ? nc - c0 : bw;
           const int c1 = J * bw, cJ = nc - c1 < bw ? nc - c1 : bw;
           move(true, c0, cI, c1, cJ);
-          jacobi_sweep(Lc, p, cI + cJ, cI, zero2, tol);
+          jacobi_sweep(p, cI + cJ, cI, zero2, tol);
           move(false, c0, cI, c1, cJ);
         }
     }
@@ -631,30 +704,25 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
   tjm_sync();
   const int k = SL.k;
   // kept orthonormal vectors of Gw in sorted order: Uc[j][r] = w_{o_j}[r] / s
-  for (int e = tid; e < k * p; e += TJM_NT) {
-    int j = e / p, r = e % p;
-    int o = SL.order[j];
-    Uc[e] = (1.0 / SL.s[o]) * Wc[(long)o * p + r];
-  }
+  blk_map(k * p, [&](int e) {
+    const int j = e / p, r = e % p, o = SL.order[j];
+    return (1.0 / SL.s[o]) * Wc[(long)o * p + r];
+  }, [&](int e, zd x) { gstore(Uc, e, x); });
   tjm_sync();
   if (!tr) {
     // G = U S V^H with U from the rotated columns: right = U^H G = S V^H
     blk_cgemm<double>(k, n, m, 1, true, cmat((const zd*)Uc, p, 0, false, true), cmat(G, n), Tg, n, 0, false, glds);
     tjm_sync();
-    for (int e = tid; e < m * k; e += TJM_NT) {
-      int r = e / k, j = e % k;
-      left[e] = Uc[(long)j * p + r];
-    }
-    for (int e = tid; e < k * n; e += TJM_NT) right[e] = Tg[e];
+    blk_map(m * k, [&](int e) { const int r = e / k, j = e % k; return gload(Uc, (long)j * p + r); },
+            [&](int e, zd x) { gstore(left, e, x); });
+    blk_map(k * n, [&](int e) { return gload(Tg, e); }, [&](int e, zd x) { gstore(right, e, x); });
   } else {
     // G^H = V S U^H with V from the rotated columns: left = G V = U S
     blk_cgemm<double>(m, k, n, 1, true, cmat(G, n), cmat((const zd*)Uc, p, 0, true, false), Tg, k, 0, false, glds);
     tjm_sync();
-    for (int e = tid; e < k * n; e += TJM_NT) {
-      int j = e / n, c = e % n;
-      right[e] = conjg(Uc[(long)j * p + c]);
-    }
-    for (int e = tid; e < m * k; e += TJM_NT) left[e] = Tg[e];
+    blk_map(k * n, [&](int e) { const int j = e / n, c = e % n; return conjg(gload(Uc, (long)j * p + c)); },
+            [&](int e, zd x) { gstore(right, e, x); });
+    blk_map(m * k, [&](int e) { return gload(Tg, e); }, [&](int e, zd x) { gstore(left, e, x); });
   }
   tjm_sync();
   return k;
@@ -663,8 +731,16 @@ TJM_DEVNI int blk_svd(int m, int n, const zd* G, zd* left, zd* right, bool absor
 // --------------------------------------------------------------------------
 // Lanczos exponential.  v (n complex doubles) is replaced by exp(-i t H) v.
 // Op must provide  void apply(const zd* q, zd* w)  (a collective call that
-// leaves w complete for all threads).  Q holds up to m_max basis vectors of
-// length n, w is an n-vector of scratch.  Returns the Krylov dimension used.
+// leaves w complete for all threads).  Q holds up to m_max - 1 basis vectors
+// of length n, w is an n-vector of scratch.  Returns the Krylov dimension
+// used.
+//
+// The basis is stored unnormalised: q_i = s_i B_i with B_0 = v itself (no
+// copy) and B_i = Q + (i-1) n, the scales s_i in LDS.  H is applied to B_j
+// (H q_j = s_j H B_j), and the Gram-Schmidt pass writes the orthogonalised
+// vector straight into B_{j+1} with s_{j+1} = 1/||.||: no separate
+// normalisation pass.  The arithmetic of the basis, the projections and the
+// small exponential is FP64 throughout.
 // --------------------------------------------------------------------------
 // exp(-i t T) e_0 for the symmetric tridiagonal T = tridiag(beta, alpha, beta)
 // of size m <= 32: shift by alpha_0, split t into s pieces with
@@ -744,13 +820,104 @@ TJM_DEV void tridiag_exp_e0(int m, double t, LanczosLds& Lz) {
   }
 }
 
+// Lanczos vector kernels.  Each streams the n entries (thread stride
+// TJM_NT, two entries per thread in flight) and reads NB basis vectors
+// B_u = bp[u] per entry with all NB loads issued together.
+//
+// Projections h_u = sum_e conj(B_u[e]) w[e]: each wave's sum to
+// Lz.red[wave][2 (i0 + u)] (real) and + 1 (imaginary).
+template <int NB>
+TJM_DEV void lz_project(const zd* const* bp, const zd* w, int n, int i0, LanczosLds& Lz) {
+  double hr[NB], hi[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) { hr[u] = 0.0; hi[u] = 0.0; }
+#pragma unroll 2
+  for (int e = tjm_tid(); e < n; e += TJM_NT) {
+    const zd x = gload(w, e);
+    zd b[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) b[u] = gload(bp[u], e);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      hr[u] = fma(b[u].re, x.re, fma(b[u].im, x.im, hr[u]));
+      hi[u] = fma(b[u].re, x.im, fma(-b[u].im, x.re, hi[u]));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    hr[u] = tjm_grp_sum<TJM_WAVE>(hr[u]);
+    hi[u] = tjm_grp_sum<TJM_WAVE>(hi[u]);
+    if (tjm_lane() == 0) {
+      Lz.red[tjm_wave()][2 * (i0 + u)] = hr[u];
+      Lz.red[tjm_wave()][2 * (i0 + u) + 1] = hi[u];
+    }
+  }
+}
+
+// x_k + sum_u c_u B_u[e_k] for two entries e_0, e_1 and the coefficients
+// c_u = (cr[u], ci[u]) (LDS)
+template <int NB>
+TJM_DEV void lz_comb(const zd* const* bp, const double* cr, const double* ci, int e0, int e1, zd& x0, zd& x1) {
+  zd b0[NB], b1[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) { b0[u] = gload(bp[u], e0); b1[u] = gload(bp[u], e1); }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    x0.re = fma(cr[u], b0[u].re, fma(-ci[u], b0[u].im, x0.re));
+    x0.im = fma(cr[u], b0[u].im, fma(ci[u], b0[u].re, x0.im));
+    x1.re = fma(cr[u], b1[u].re, fma(-ci[u], b1[u].im, x1.re));
+    x1.im = fma(cr[u], b1[u].im, fma(ci[u], b1[u].re, x1.im));
+  }
+}
+
+// out[e] = f * in[e] + sum_{i < nb} c_i B_i[e] (c_i in LDS), for every e; in
+// may be null (then 0); out may be in or one of the B_i (each entry is read
+// before it is written, by the same thread; the two entries a thread
+// handles at once are distinct).  Returns this thread's part of ||out||^2.
+template <class Basis>
+TJM_DEV double lz_axpy(Basis basis, int nb, const double* cr, const double* ci, const zd* in, double f, zd* out,
+                       int n) {
+  double nrm = 0.0;
+  for (int e0 = tjm_tid(); e0 < n; e0 += 2 * TJM_NT) {
+    const bool ok1 = e0 + TJM_NT < n;
+    const int e1 = ok1 ? e0 + TJM_NT : e0;
+    zd x0 = cmk(0.0, 0.0), x1 = cmk(0.0, 0.0);
+    if (in) { x0 = f * gload(in, e0); x1 = f * gload(in, e1); }
+    int i0 = 0;
+    for (; i0 + 8 <= nb; i0 += 8) {
+      const zd* bp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) bp[u] = basis(i0 + u);
+      lz_comb<8>(bp, cr + i0, ci + i0, e0, e1, x0, x1);
+    }
+    if (nb - i0 >= 4) {
+      const zd* bp[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bp[u] = basis(i0 + u);
+      lz_comb<4>(bp, cr + i0, ci + i0, e0, e1, x0, x1);
+      i0 += 4;
+    }
+    if (nb - i0 >= 2) {
+      const zd* bp[2] = {basis(i0), basis(i0 + 1)};
+      lz_comb<2>(bp, cr + i0, ci + i0, e0, e1, x0, x1);
+      i0 += 2;
+    }
+    if (nb - i0 >= 1) {
+      const zd* bp[1] = {basis(i0)};
+      lz_comb<1>(bp, cr + i0, ci + i0, e0, e1, x0, x1);
+    }
+    gstore(out, e0, x0);
+    nrm += abs2(x0);
+    if (ok1) { gstore(out, e1, x1); nrm += abs2(x1); }
+  }
+  return nrm;
+}
+
 template <class Op>
 TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd* Q, zd* w) {
   LanczosLds& Lz = tjm_lds.lz;
   BlkScratch& S = tjm_lds.S;
   const int tid = tjm_tid();
-  // the vector loops stride over the n entries with global loads unrolled by
-  // four, so that several iterations' loads are in flight together
   double b0 = 0.0;
 #pragma unroll 4
   for (int e = tid; e < n; e += TJM_NT) b0 += abs2(gload(v, e));
@@ -758,56 +925,48 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
   if (b0 == 0.0) return 0;
   if (m_max > TJM_KMAX) m_max = TJM_KMAX;
   if (m_max > n) m_max = n;
-#pragma unroll 4
-  for (int e = tid; e < n; e += TJM_NT) gstore(Q, e, (1.0 / b0) * gload(v, e));
+  auto basis = [=](int i) -> zd* { return i == 0 ? v : Q + (long)(i - 1) * n; };
+  if (tid == 0) Lz.scale[0] = 1.0 / b0;
   tjm_sync();
   int used = 0;
   for (int j = 0; j < m_max; ++j) {
-    const zd* qj = Q + (long)j * n;
-    op.apply(qj, w);                                   // w = H q_j
+    op.apply(basis(j), w);                           // w = H B_j = (H q_j) / s_j
     // one classical Gram-Schmidt pass against q_0..q_j (alpha_j = Re h_j,
-    // the three-term part included): h = Q^H w with w read once per block
-    // of four basis vectors
+    // the three-term part included): h_i = s_i s_j B_i^H w, with w read once
+    // per block of up to eight basis vectors
     const int nq = j + 1;
-    for (int i0 = 0; i0 < nq; i0 += 4) {
-      double hr[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
-      const int nu = nq - i0 < 4 ? nq - i0 : 4;
-#pragma unroll 2
-      for (int e = tid; e < n; e += TJM_NT) {
-        const zd x = gload(w, e);
+    const double sj = Lz.scale[j];
+    for (int i0 = 0; i0 < nq; i0 += 8) {
+      const int nu = nq - i0 < 8 ? nq - i0 : 8;
+      const zd* bp[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const zd qv = gload(Q, (long)(i0 + (u < nu ? u : 0)) * n + e);
-          const zd p = cdotc(qv, x);
-          hr[u] += u < nu ? p.re : 0.0;
-          hi[u] += u < nu ? p.im : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        for (int s = TJM_WAVE / 2; s > 0; s >>= 1) { hr[u] += tjm_shfl_xor(hr[u], s); hi[u] += tjm_shfl_xor(hi[u], s); }
-        if (tjm_lane() == 0 && i0 + u < nq) {
-          Lz.red[tjm_wave()][2 * (i0 + u)] = hr[u];
-          Lz.red[tjm_wave()][2 * (i0 + u) + 1] = hi[u];
-        }
+      for (int u = 0; u < 8; ++u) bp[u] = basis(i0 + (u < nu ? u : 0));
+      switch (nu) {
+        case 1: lz_project<1>(bp, w, n, i0, Lz); break;
+        case 2: lz_project<2>(bp, w, n, i0, Lz); break;
+        case 3: lz_project<3>(bp, w, n, i0, Lz); break;
+        case 4: lz_project<4>(bp, w, n, i0, Lz); break;
+        case 5: lz_project<5>(bp, w, n, i0, Lz); break;
+        case 6: lz_project<6>(bp, w, n, i0, Lz); break;
+        case 7: lz_project<7>(bp, w, n, i0, Lz); break;
+        default: lz_project<8>(bp, w, n, i0, Lz); break;
       }
     }
     tjm_sync();
     for (int i = tid; i < nq; i += TJM_NT) {
       double hr = 0.0, hi = 0.0;
       for (int wv = 0; wv < TJM_NWAVE; ++wv) { hr += Lz.red[wv][2 * i]; hi += Lz.red[wv][2 * i + 1]; }
+      const double f = Lz.scale[i] * sj;
+      hr *= f; hi *= f;
       Lz.hre[i] = hr; Lz.him[i] = hi;
+      Lz.hsre[i] = -hr * Lz.scale[i]; Lz.hsim[i] = -hi * Lz.scale[i];   // -h_i s_i
       if (i == j) Lz.alpha[j] = hr;
     }
     tjm_sync();
-    double bn = 0.0;
-#pragma unroll 2
-    for (int e = tid; e < n; e += TJM_NT) {
-      zd x = gload(w, e);
-      for (int i = 0; i < nq; ++i) x = x - cmk(Lz.hre[i], Lz.him[i]) * gload(Q, (long)i * n + e);
-      gstore(w, e, x);
-      bn += abs2(x);
-    }
+    // w' = H q_j - sum_i h_i q_i = s_j w - sum_i (h_i s_i) B_i, into B_{j+1}
+    // (w itself where the basis is full: w' is then only needed for beta)
+    zd* nb = j + 1 < m_max ? basis(j + 1) : w;
+    double bn = lz_axpy(basis, nq, Lz.hsre, Lz.hsim, w, sj, nb, n);
     bn = sqrt(blk_sum(bn, S));
     tridiag_exp_e0(j + 1, t, Lz);
     tjm_sync();
@@ -815,22 +974,20 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
       double cj = sqrt(Lz.cre[j] * Lz.cre[j] + Lz.cim[j] * Lz.cim[j]);
       Lz.done = (bn * cj <= tol || j == m_max - 1) ? 1 : 0;
       Lz.beta[j] = bn;
+      Lz.scale[j + 1 < TJM_KMAX ? j + 1 : j] = 1.0 / bn;
     }
     tjm_sync();
     used = j + 1;
     if (Lz.done) break;
-    zd* qn = Q + (long)(j + 1) * n;
-#pragma unroll 4
-    for (int e = tid; e < n; e += TJM_NT) gstore(qn, e, (1.0 / bn) * gload(w, e));
-    tjm_sync();
   }
-  // v = b0 * sum_i c_i q_i
-#pragma unroll 2
-  for (int e = tid; e < n; e += TJM_NT) {
-    zd x = cmk(0.0, 0.0);
-    for (int i = 0; i < used; ++i) x = x + cmk(Lz.cre[i], Lz.cim[i]) * gload(Q, (long)i * n + e);
-    gstore(v, e, b0 * x);
+  // v = b0 * sum_i c_i q_i = b0 * sum_i (c_i s_i) B_i, in place (B_0 = v is
+  // read before it is written, entry by entry)
+  for (int i = tid; i < used; i += TJM_NT) {
+    Lz.hsre[i] = b0 * Lz.scale[i] * Lz.cre[i];
+    Lz.hsim[i] = b0 * Lz.scale[i] * Lz.cim[i];
   }
+  tjm_sync();
+  lz_axpy(basis, used, Lz.hsre, Lz.hsim, nullptr, 0.0, v, n);
   tjm_sync();
   return used;
 }

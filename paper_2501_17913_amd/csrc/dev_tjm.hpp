@@ -105,6 +105,46 @@ template <typename Tc> struct Tjm {
     since(TJM_ST_T_CONTRACT, t0);
   }
 
+  // y[a][s'][c] (+)= sum_s O[s'][s] q[a][s][c] for every (a, c), with DP
+  // physical values (d or d^2; d = 2 is the only local dimension); the loads
+  // of 8 / DP entries per thread are issued before their stores, and an
+  // entry's stores follow its own loads, so y may be q.
+  template <int DP>
+  TJM_DEV void local_term(const zd* q, zd* y, int chl, int chr, const zd* O, bool acc) {
+    constexpr int NE = 8 / DP;
+    const int n = chl * chr;
+    zd o[DP * DP];
+#pragma unroll
+    for (int i = 0; i < DP * DP; ++i) o[i] = gload(O, i);
+    for (int base = 0; base < n; base += NE * TJM_NT) {
+      zd in[NE][DP], yo[NE][DP];
+      long off[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        int e = base + tjm_tid() + u * TJM_NT;
+        e = e < n ? e : n - 1;
+        const int a = e / chr, c = e - a * chr;
+        off[u] = (long)a * DP * chr + c;
+#pragma unroll
+        for (int s = 0; s < DP; ++s) {
+          in[u][s] = gload(q, off[u] + (long)s * chr);
+          yo[u][s] = acc ? gload((const zd*)y, off[u] + (long)s * chr) : cmk(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        if (base + tjm_tid() + u * TJM_NT >= n) continue;
+#pragma unroll
+        for (int so = 0; so < DP; ++so) {
+          zd v = yo[u][so];
+#pragma unroll
+          for (int s = 0; s < DP; ++s) v = v + o[so * DP + s] * in[u][s];
+          gstore(y, off[u] + (long)so * chr, v);
+        }
+      }
+    }
+  }
+
   // ------------------------------------------------------------------
   // Effective Hamiltonians as matrix-free products (Fig. TDVP)
   // ------------------------------------------------------------------
@@ -117,6 +157,7 @@ template <typename Tc> struct Tjm {
                            const int* ptrL, const int* ptrR, const int* chanL, const int* chanR, int nL, int nR,
                            const double* loc) {
     const int Dm = P.Dmax;
+    const unsigned long long tg = tjm_clock();
     bool acc = false;
     if (nL > 0) {      // left class: (chl x chl) . (chl x dp chr), summed over channels
       blk_cgemm_auto<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
@@ -131,19 +172,10 @@ template <typename Tc> struct Tjm {
       tjm_sync();
       acc = true;
     }
+    since(TJM_ST_T_GEMM, tg);
     // local term in FP64: y[a][s'][c] += sum_s Oloc[s'][s] q[a][s][c]
-    const zd* O = (const zd*)loc;
-    const long n = (long)chl * chr;
-    for (long e = tjm_tid(); e < n; e += TJM_NT) {
-      const int a = (int)(e / chr), c = (int)(e % chr);
-      zd in[4];
-      for (int s = 0; s < dp; ++s) in[s] = q[((long)a * dp + s) * chr + c];
-      for (int so = 0; so < dp; ++so) {
-        zd v = acc ? y[((long)a * dp + so) * chr + c] : cmk(0.0, 0.0);
-        for (int s = 0; s < dp; ++s) v = v + O[so * dp + s] * in[s];
-        y[((long)a * dp + so) * chr + c] = v;
-      }
-    }
+    if (dp == 2) local_term<2>(q, y, chl, chr, (const zd*)loc, acc);
+    else local_term<4>(q, y, chl, chr, (const zd*)loc, acc);      // dp = d^2
     tjm_sync();
     count(TJM_ST_CMAC_MFMA, (unsigned long long)nL * chl * chl * dp * chr + (unsigned long long)nR * chl * dp * chr * chr);
     count(TJM_ST_CMAC_MIX, (unsigned long long)(ptrL[Dm * dp] - ptrL[0] + ptrR[Dm * dp] - ptrR[0]) * chl * chr);
@@ -231,6 +263,7 @@ template <typename Tc> struct Tjm {
         }
         tjm_sync();
         t->count(TJM_ST_CMAC_MFMA, (unsigned long long)(1 + nlr) * kl * kr * (kl + kr));
+        t->since(TJM_ST_T_GEMM, t0);
         t->since(TJM_ST_T_CONTRACT, t0);
         return;
       }
@@ -257,7 +290,7 @@ template <typename Tc> struct Tjm {
   // Site moves (FP64 factorisations)
   // ------------------------------------------------------------------
   TJM_DEV void copy(zd* dst, const zd* src, long n) {
-    for (long e = tjm_tid(); e < n; e += TJM_NT) dst[e] = src[e];
+    if (n > 0) blk_map((int)n, [&](int e) { return gload(src, e); }, [&](int e, zd x) { gstore(dst, e, x); });
   }
 
   // next (k x d x c) = C (k x m) . next (m x d x c), via v
@@ -562,12 +595,7 @@ template <typename Tc> struct Tjm {
       zd* M = site(mps, P, s);
       const zd* D = (const zd*)Dtab + (long)s * d * d;
       const int chl = bd[s], chr = bd[s + 1];
-      for (long e = tjm_tid(); e < (long)chl * chr; e += TJM_NT) {
-        int a = (int)(e / chr), b = (int)(e % chr);
-        zd in0 = M[((long)a * d + 0) * chr + b], in1 = M[((long)a * d + 1) * chr + b];
-        M[((long)a * d + 0) * chr + b] = D[0] * in0 + D[1] * in1;
-        M[((long)a * d + 1) * chr + b] = D[2] * in0 + D[3] * in1;
-      }
+      local_term<2>(M, M, chl, chr, D, false);      // M <- D M in place, entry by entry
     }
     tjm_sync();
   }
@@ -841,9 +869,11 @@ template <typename Tc> struct Tjm {
     for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
     tjm_sync();
     double* ok = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
+    const unsigned long long tj = tjm_clock();
     int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok);
     int mm = -1;
     if (k < P.n_steps && ms != -2) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr);
+    since(TJM_ST_T_JUMP, tj);
     if (tjm_tid() == 0) {
       int* jl = P.jlog + (long)traj * 2 * P.n_steps;
       jl[2 * k - 1] = ms;

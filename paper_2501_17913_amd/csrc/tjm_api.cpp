@@ -865,12 +865,11 @@ static void collect_stats(tjm_model* m, Run* r) {
   if (hipMemcpy(st.data(), r->d_stats, st.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return;
   for (int t = 0; t < r->n_traj; ++t) {
     const unsigned long long* q = &st[(size_t)t * TJM_NSTAT];
-    for (int i = 0; i < 7; ++i) s.phase_s[i] += 1e-8 * (double)q[TJM_ST_T_TOTAL + i];
+    for (int i = 0; i < 8; ++i) s.phase_s[i] += 1e-8 * (double)q[TJM_ST_T_TOTAL + i];
     s.cmac_mfma += q[TJM_ST_CMAC_MFMA]; s.cmac_mix += q[TJM_ST_CMAC_MIX];
     s.krylov_iters += q[TJM_ST_KRYLOV]; s.expm_calls += q[TJM_ST_EXPM];
     s.one_site += q[TJM_ST_ONE_SITE]; s.two_site += q[TJM_ST_TWO_SITE];
     s.factorizations += q[TJM_ST_FACT]; s.jumps += q[TJM_ST_JUMPS];
-    s.cmac_env += q[TJM_ST_CMAC_FP64];
   }
   std::vector<int> fl(r->n_traj);
   if (hipMemcpy(fl.data(), r->d_flags, fl.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return;

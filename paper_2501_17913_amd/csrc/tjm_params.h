@@ -106,11 +106,11 @@ enum {
   // device-clock ticks (100 MHz) spent by the trajectory's workgroup in:
   TJM_ST_T_TOTAL = 8,     //   the whole step function
   TJM_ST_T_CONTRACT = 9,  //   effective-Hamiltonian and environment contractions
-  TJM_ST_T_ENV = 10,      //   (unused)
+  TJM_ST_T_JUMP = 10,     //   jump processes (dissipation, sweeps, measurement), their factorisations included
   TJM_ST_T_SVD = 11,      //   SVD factorisations
   TJM_ST_T_QR = 12,       //   QR / LQ factorisations
   TJM_ST_T_EXPM = 13,     //   Lanczos exponentials (including their contractions)
   TJM_ST_T_ABSORB = 14,   //   bond-matrix absorption and two-site products
-  TJM_ST_CMAC_FP64 = 15,  // (unused)
+  TJM_ST_T_GEMM = 15,     //   matrix-core products of the effective Hamiltonians (part of contractions)
   TJM_NSTAT = 16
 };

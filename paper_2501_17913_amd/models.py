@@ -12,6 +12,7 @@ PAULI_Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
 PAULI_Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 IDENT = np.eye(2, dtype=np.complex128)
 LOWER = np.array([[0, 1], [0, 0]], dtype=np.complex128)    # sigma_minus
+RAISE = np.array([[0, 0], [1, 0]], dtype=np.complex128)    # sigma_plus
 
 
 def _finite_state_mpo(L, blocks, D):
@@ -53,6 +54,17 @@ def relaxation_dephasing(L, gamma_minus, gamma_z):
     return np.array(sites, dtype=np.int32), np.array(ops), np.array(rates, dtype=np.float64)
 
 
+def relaxation_excitation(L, gamma_minus, gamma_plus):
+    """sigma_minus and sigma_plus on every site, site-major (the jump set of
+    the 30-site comparison, Sec. "New frontiers")."""
+    sites, ops, rates = [], [], []
+    for l in range(L):
+        sites += [l, l]
+        ops += [LOWER, RAISE]
+        rates += [gamma_minus, gamma_plus]
+    return np.array(sites, dtype=np.int32), np.array(ops), np.array(rates, dtype=np.float64)
+
+
 def zx_observables(L):
     """<Z_l> for every site, then <X_l> for every site."""
     return [(l, PAULI_Z) for l in range(L)] + [(l, PAULI_X) for l in range(L)]
@@ -69,6 +81,12 @@ def neel(L):
     return product_state([l % 2 for l in range(L)])
 
 
+def domain_wall(L):
+    """Domain wall of the 30-site comparison: site l (1-based) in |0> for
+    l < L/2 and in |1> from L/2 on."""
+    return product_state([0 if l + 1 < L / 2 else 1 for l in range(L)])
+
+
 def all_zero(L):
     return product_state([0] * L)
 
@@ -78,3 +96,11 @@ def xxx_model(L, J=1.0, g=0.5, gamma=0.1):
     jumps at rate gamma on every site.  Returns (mpo, sites, ops, rates)."""
     s, o, r = relaxation_dephasing(L, gamma, gamma)
     return xxx_mpo(L, J, g), s, o, r
+
+
+def domain_wall_model(L, J=1.0, h=1.0, gamma=0.1):
+    """The 30-site comparison chain (Sec. "New frontiers"): XXX with a Z
+    field h, sigma_minus and sigma_plus at rate gamma on every site.  Returns
+    (mpo, sites, ops, rates); the initial state is domain_wall(L)."""
+    s, o, r = relaxation_excitation(L, gamma, gamma)
+    return xxx_mpo(L, J, 0.0, h), s, o, r

@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("device_bytes", C.c_size_t), ("phase_s", C.c_double * 8), ("failed_traj", C.c_int),
                 ("cmac_env", C.c_ulonglong)]
 
-    PHASES = ("total", "contract", "env", "svd", "qr", "expm", "absorb")
+    PHASES = ("total", "contract", "jump", "svd", "qr", "expm", "absorb", "gemm")
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_s"}

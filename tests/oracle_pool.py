@@ -24,25 +24,51 @@ def _one(args):
     return out, [m for (_, _, m) in rec["jumps"]], np.array(rec["bonds"])
 
 
+def _one_domain_wall(args):
+    L, chi, n, seed, t = args
+    import numpy as np
+    from oracle import model as om, mps_tjm
+    Ws = om.xxx_mpo(L, 1.0, 0.0, 1.0)
+    jumps = om.relax_excite_jumps(L, 0.1, 0.1)
+    obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
+    sv = om.product_site_vectors(L, om.domain_wall_bits(L))
+    rec = {}
+    out = mps_tjm.run_trajectory(Ws, jumps, mps_tjm.product_mps(sv), 0.1, n, obs, seed, t,
+                                 mps_tjm.Options(chi_max=chi), rec)
+    return out, [m for (_, _, m) in rec["jumps"]], np.array(rec["bonds"])
+
+
 def workers(n_tasks, cap=16):
     """Worker count: at most `cap` (the CPU share of one GPU machine) and the host's cores."""
     return max(1, min(n_tasks, cap, os.cpu_count() or 1))
 
 
-def oracle_trajectories(L, chi, init, n, g, gamma, seed, ids, chi_cap=None):
-    """{trajectory id: (observables [n+1][2L], jump log, bond log)} for the
-    XXX chain with sigma- and Z jumps, observables Z then X on every site."""
-    ids = list(ids)
+def _pool_map(fn, tasks):
     saved = {v: os.environ.get(v) for v in _BLAS_VARS}
     for v in _BLAS_VARS:
         os.environ[v] = "1"
     try:
-        with mp.get_context("spawn").Pool(workers(len(ids))) as pool:
-            res = pool.map(_one, [(L, chi, chi_cap, init, n, g, gamma, seed, t) for t in ids], chunksize=1)
+        with mp.get_context("spawn").Pool(workers(len(tasks))) as pool:
+            return pool.map(fn, tasks, chunksize=1)
     finally:
         for v, x in saved.items():
             if x is None:
                 os.environ.pop(v, None)
             else:
                 os.environ[v] = x
+
+
+def oracle_trajectories(L, chi, init, n, g, gamma, seed, ids, chi_cap=None):
+    """{trajectory id: (observables [n+1][2L], jump log, bond log)} for the
+    XXX chain with sigma- and Z jumps, observables Z then X on every site."""
+    ids = list(ids)
+    res = _pool_map(_one, [(L, chi, chi_cap, init, n, g, gamma, seed, t) for t in ids])
+    return dict(zip(ids, res))
+
+
+def domain_wall_trajectories(L, chi, n, seed, ids):
+    """The same for the 30-site comparison chain: XXX with a Z field h = 1,
+    sigma_minus and sigma_plus at 0.1 on every site, domain-wall start."""
+    ids = list(ids)
+    res = _pool_map(_one_domain_wall, [(L, chi, n, seed, t) for t in ids])
     return dict(zip(ids, res))
