@@ -175,13 +175,36 @@ tjm_status tjm_set_initial_product(tjm_model *m, const double *site_vec);
 tjm_status tjm_set_initial_mps(tjm_model *m, const int *bond, const double *tensors);
 
 /*
+ * Registers an MPO observable O with the model (Eq. TJMExpVal with O stored
+ * as an MPO; Methods, "Resources required for calculating expectation
+ * values").  mpo_bond and mpo have the layout of tjm_create; O must be
+ * Hermitian (the real part of <Psi|O|Psi> is reported).  Every later run
+ * reports the registered MPO observables after its n_obs site observables,
+ * in registration order: the output rows of mean, sem and per_traj_obs are
+ * n_obs + (number registered) wide.  Each is measured on the same states
+ * as the site observables (Psi(0), then Psi_k after the sampling layer),
+ * by an MPS-MPO-MPS contraction from the right end in FP64 on both
+ * precision paths (L environment updates per observable and step).
+ * *index (may be NULL) receives its position among the MPO observables.
+ * Errors: TJM_E_INVAL (as tjm_create for the MPO; more than 64
+ * observables), TJM_E_BUSY while a run is in progress.  The library copies
+ * the input.
+ */
+tjm_status tjm_add_mpo_observable(tjm_model *m, const int *mpo_bond, const double *mpo, int *index);
+
+/* Removes every registered MPO observable (TJM_E_BUSY during a run). */
+tjm_status tjm_clear_mpo_observables(tjm_model *m);
+
+/*
  * One whole run (Sec. "Algorithm"): N = n_traj trajectories from t = 0 to
  * T = n dt (n = T/dt must be an integer within 1e-9), chi_max the bond
  * dimension at which dynamic TDVP switches to 1TDVP, and single-site
  * observables (obs_site[i], obs_op[i] complex d x d).  Outputs:
- *   mean  [(n+1)][n_obs]  trajectory average of <Psi_i(t_k)|O|Psi_i(t_k)>
- *                         (real part), t_k = k dt, k = 0..n (Eq. TJMExpVal)
- *   sem   [(n+1)][n_obs]  standard error of that mean, or NULL
+ *   mean  [(n+1)][n_out]  trajectory average of <Psi_i(t_k)|O|Psi_i(t_k)>
+ *                         (real part), t_k = k dt, k = 0..n (Eq. TJMExpVal);
+ *                         n_out = n_obs + the MPO observables registered
+ *                         with tjm_add_mpo_observable
+ *   sem   [(n+1)][n_out]  standard error of that mean, or NULL
  * opt may be NULL (defaults).  Errors: TJM_E_INVAL for bad arguments,
  * TJM_E_NUMERIC if a trajectory's norm became non-finite, TJM_E_NOMEM /
  * TJM_E_DEVICE from the GPU.
@@ -193,7 +216,7 @@ tjm_status tjm_run(tjm_model *m, int n_traj, double dt, double T, int chi_max,
 /*
  * As tjm_run, additionally returning per-trajectory records (each pointer may
  * be NULL):
- *   per_traj_obs [n_traj][n+1][n_obs]
+ *   per_traj_obs [n_traj][n+1][n_out]
  *   jump_log     [n_traj][2n]: index m of the applied jump operator or -1,
  *                in the order F_0, then (sampling layer k, main step k) for
  *                k = 1..n (no main step at k = n)
@@ -305,7 +328,7 @@ tjm_status tjm_poll(tjm_server *s, uint64_t job, int *done);
 /*
  * Blocks until the job has finished, then writes its outputs into
  * caller-allocated buffers (each may be NULL): mean and sem as in tjm_run,
- * [(n+1)][n_obs] each, and the report.  Returns the job's own status (the
+ * [(n+1)][n_out] each (n_out as in tjm_run), and the report.  Returns the job's own status (the
  * outputs are written only for TJM_OK) and releases the job: its id is
  * unknown afterwards (TJM_E_INVAL).  TJM_E_BUSY if another call is already
  * waiting for the same job.

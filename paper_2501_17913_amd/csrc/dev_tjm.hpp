@@ -30,6 +30,7 @@ template <typename Tc> struct Tjm {
   int* bB;            // LDS [L+1]: bonds of the sampling-layer copy
   // worker scratch
   zc* env; zd* smps; zd* Q; zd* w; zd* v; zc* T1; zd* X; zd* Y; zd* Z; zd* Cb; double* wts;
+  zd* oenv; zd* ot;   // MPO observables: two FP64 environments and a stage buffer
   int d, L;
 
   TJM_DEV Tjm(const TjmParams& p, int* dyn, int worker) : P(p) {
@@ -49,6 +50,8 @@ template <typename Tc> struct Tjm {
     Z = (zd*)(base + P.off_Z);
     Cb = (zd*)(base + P.off_C);
     wts = (double*)(base + P.off_wts);
+    oenv = (zd*)(base + P.off_oenv);
+    ot = (zd*)(base + P.off_ot);
     if (tjm_tid() == 0)                              // environment slot of each bond
       for (int b = 0; b < L + 2; ++b) slot[b] = b;
     tjm_sync();
@@ -89,20 +92,55 @@ template <typename Tc> struct Tjm {
   }
 
   // R_{s-1}[w][a][a'] = sum B[a][s][b] R_s[w'][b][b'] W[w][w'][s'][s] conj(B[a'][s'][b'])
+  // for an MPO block of bonds (Dl, Dr) with mixing rows rp (entries ents),
+  // environments and stage buffer Tb in precision TE
+  template <typename TE>
+  TJM_DEV void env_right(const zd* B, int chl, int chr, int Dl, int Dr, const int* rp, const MixEnt* ents,
+                         const cplx<TE>* Rold, cplx<TE>* Rnew, cplx<TE>* Tb) {
+    blk_cgemm<TE>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
+                  Tb, chr, (long)chl * d * chr, false, tjm_lds.gemm);
+    tjm_sync();
+    blk_cgemm<TE>(chl, chl, d * chr, Dl, false,
+                  mix_cols((const cplx<TE>*)Tb, rp, ents, d, chr, (long)chl * d * chr, (long)d * chr, (long)chr),
+                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, tjm_lds.gemm);
+    tjm_sync();
+  }
+
   TJM_DEVNI void rupdate(int s, const zd* B, int chl, int chr, const zc* Rold, zc* Rnew) {
     const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixR_ptr + (long)s * (P.Dmax * d + 1);
-    blk_cgemm<Tc>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
-                  T1, chr, (long)chl * d * chr, false, tjm_lds.gemm);
-    tjm_sync();
-    blk_cgemm<Tc>(chl, chl, d * chr, Dl, false,
-                  mix_cols((const zc*)T1, rp, P.mixR, d, chr, (long)chl * d * chr, (long)d * chr, (long)chr),
-                  cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, tjm_lds.gemm);
-    tjm_sync();
+    env_right<Tc>(B, chl, chr, Dl, Dr, rp, P.mixR, Rold, Rnew, T1);
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dl, d, rp) * chl * chr);
     since(TJM_ST_T_CONTRACT, t0);
+  }
+
+  // <Psi|O_q|Psi> of MPO observable q on a normalised MPS (Eq. TJMExpVal;
+  // Methods, "Resources required for calculating expectation values"): the
+  // MPS-MPO-MPS network contracted from the right end with the environment
+  // update of TDVP, in FP64 on both paths; the real part
+  TJM_DEVNI double mpo_expect(int q, const zd* mps, const int* bd) {
+    const int* D = P.oD + (long)q * (L + 1);
+    const int rows = P.oDmax * d + 1;
+    zd* Ra = oenv;
+    zd* Rb = oenv + P.oenv_cap;
+    if (tjm_tid() == 0) Ra[0] = cmk(1.0, 0.0);
+    tjm_sync();
+    for (int s = L - 1; s >= 0; --s) {
+      env_right<double>(site((zd*)mps, P, s), bd[s], bd[s + 1], D[s], D[s + 1],
+                        P.omixR_ptr + ((long)q * L + s) * rows, P.mixR, Ra, Rb, ot);
+      zd* t = Ra; Ra = Rb; Rb = t;
+    }
+    return gload((const zd*)Ra, 0).re;
+  }
+
+  // the MPO observables of a normalised MPS (centre anywhere) into out
+  TJM_DEVNI void measure_mpo(const zd* mps, const int* bd, double* out) {
+    for (int q = 0; q < P.n_mpo_obs; ++q) {
+      const double v = mpo_expect(q, mps, bd);
+      if (tjm_tid() == 0) out[P.n_site_obs + q] = v;
+    }
   }
 
   // y[a][s'][c] (+)= sum_s O[s'][s] q[a][s][c] for every (a, c), with DP
@@ -843,6 +881,7 @@ template <typename Tc> struct Tjm {
       }
       finish(mps, bA, o0);
     }
+    if (P.n_mpo_obs) measure_mpo(mps, bA, o0);       // Psi(0), normalised
     int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
     if (tjm_tid() == 0) {
       P.jlog[(long)traj * 2 * P.n_steps] = m;
@@ -871,6 +910,7 @@ template <typename Tc> struct Tjm {
     double* ok = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
     const unsigned long long tj = tjm_clock();
     int ms = jump_process(smps, bB, P.Dhalf, (uint32_t)k, 1u, ok);
+    if (P.n_mpo_obs && ms != -2) measure_mpo(smps, bB, ok);
     int mm = -1;
     if (k < P.n_steps && ms != -2) mm = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, nullptr);
     since(TJM_ST_T_JUMP, tj);

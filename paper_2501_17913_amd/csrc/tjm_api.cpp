@@ -50,6 +50,8 @@ struct tjm_model {
   std::vector<cd> jop;                // [n_jump][d][d]
   std::vector<double> jrate;
   std::vector<cd> init;               // [L][d]
+  std::vector<std::vector<int>> omD;  // MPO observables: bond dimensions
+  std::vector<std::vector<std::vector<cd>>> oW;   //   and site tensors [wl][wr][so][si]
   std::vector<int> init_bond;         // non-empty: Psi(0) is the MPS init_mps
   std::vector<cd> init_mps;           // M_l[s][a][b] concatenated
   std::string err;
@@ -97,6 +99,57 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->graph = 0;
 }
 
+// Validates an MPO in the layout of tjm_create (bond dimensions mpo_bond[0..L],
+// site tensors W[s_out][s_in][w_l][w_r] concatenated) and copies it into
+// per-site arrays [w_l][w_r][s_out][s_in].  Returns an error message or "".
+static std::string read_mpo(int L, int d, const int* mpo_bond, const double* mpo, std::vector<int>& D,
+                            std::vector<std::vector<cd>>& W) {
+  if (!mpo_bond || !mpo) return "mpo_bond / mpo is NULL";
+  if (mpo_bond[0] != 1 || mpo_bond[L] != 1) return "MPO boundary bonds must be 1";
+  for (int b = 0; b <= L; ++b)
+    if (mpo_bond[b] < 1 || mpo_bond[b] > 8) return "MPO bond dimensions must be in 1..8";
+  D.assign(mpo_bond, mpo_bond + L + 1);
+  W.assign(L, {});
+  long off = 0;
+  for (int s = 0; s < L; ++s) {
+    const int Dl = mpo_bond[s], Dr = mpo_bond[s + 1];
+    const long n = (long)d * d * Dl * Dr;
+    if (!finite_arr(mpo + 2 * off, 2 * n)) return "MPO has non-finite entries";
+    W[s].assign((size_t)n, cd(0, 0));
+    for (int so = 0; so < d; ++so)
+      for (int si = 0; si < d; ++si)
+        for (int wl = 0; wl < Dl; ++wl)
+          for (int wr = 0; wr < Dr; ++wr) {
+            long src = off + (((long)so * d + si) * Dl + wl) * Dr + wr;
+            W[s][(((long)wl * Dr + wr) * d + so) * d + si] = cd(mpo[2 * src], mpo[2 * src + 1]);
+          }
+    off += n;
+  }
+  return "";
+}
+
+extern "C" tjm_status tjm_add_mpo_observable(tjm_model* m, const int* mpo_bond, const double* mpo, int* index) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (m->run) return fail(m, TJM_E_BUSY, "a run is active");
+  if (m->oW.size() >= 64) return fail(m, TJM_E_INVAL, "at most 64 MPO observables");
+  std::vector<int> D;
+  std::vector<std::vector<cd>> W;
+  const std::string e = read_mpo(m->L, m->d, mpo_bond, mpo, D, W);
+  if (!e.empty()) return fail(m, TJM_E_INVAL, e);
+  m->omD.push_back(D);
+  m->oW.push_back(W);
+  if (index) *index = (int)m->oW.size() - 1;
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_clear_mpo_observables(tjm_model* m) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (m->run) return fail(m, TJM_E_BUSY, "a run is active");
+  m->omD.clear();
+  m->oW.clear();
+  return TJM_OK;
+}
+
 extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_bond, const double* mpo,
                                  int n_jump, const int* jump_site, const double* jump_op,
                                  const double* rate) {
@@ -104,36 +157,15 @@ extern "C" tjm_status tjm_create(tjm_model** out, int L, int d, const int* mpo_b
   *out = nullptr;
   if (L < 1) return fail(nullptr, TJM_E_INVAL, "L must be >= 1");
   if (d != 2) return fail(nullptr, TJM_E_UNSUPPORTED, "only local dimension d = 2 is supported");
-  if (!mpo_bond || !mpo) return fail(nullptr, TJM_E_INVAL, "mpo_bond / mpo is NULL");
-  if (mpo_bond[0] != 1 || mpo_bond[L] != 1)
-    return fail(nullptr, TJM_E_INVAL, "MPO boundary bonds must be 1");
-  for (int b = 0; b <= L; ++b)
-    if (mpo_bond[b] < 1 || mpo_bond[b] > 8)
-      return fail(nullptr, TJM_E_INVAL, "MPO bond dimensions must be in 1..8");
   if (n_jump < 0) return fail(nullptr, TJM_E_INVAL, "n_jump must be >= 0");
   if (n_jump > 0 && (!jump_site || !jump_op || !rate))
     return fail(nullptr, TJM_E_INVAL, "jump arrays are NULL");
   tjm_model* m = new tjm_model();
   m->L = L; m->d = d;
-  m->mpoD.assign(mpo_bond, mpo_bond + L + 1);
-  long off = 0;
-  m->W.resize(L);
-  for (int s = 0; s < L; ++s) {
-    const int Dl = mpo_bond[s], Dr = mpo_bond[s + 1];
-    const long n = (long)d * d * Dl * Dr;
-    if (!finite_arr(mpo + 2 * off, 2 * n)) {
-      delete m;
-      return fail(nullptr, TJM_E_INVAL, "MPO has non-finite entries");
-    }
-    m->W[s].assign((size_t)n, cd(0, 0));
-    for (int so = 0; so < d; ++so)
-      for (int si = 0; si < d; ++si)
-        for (int wl = 0; wl < Dl; ++wl)
-          for (int wr = 0; wr < Dr; ++wr) {
-            long src = off + (((long)so * d + si) * Dl + wl) * Dr + wr;
-            m->W[s][(((long)wl * Dr + wr) * d + so) * d + si] = cd(mpo[2 * src], mpo[2 * src + 1]);
-          }
-    off += n;
+  const std::string e = read_mpo(L, d, mpo_bond, mpo, m->mpoD, m->W);
+  if (!e.empty()) {
+    delete m;
+    return fail(nullptr, TJM_E_INVAL, e);
   }
   m->n_jump = n_jump;
   for (int j = 0; j < n_jump; ++j) {
@@ -258,6 +290,7 @@ struct Plan {
   // structured effective Hamiltonians (see the structure section of plan_run)
   std::vector<int> sptr1, schan1, sn1, sptr2, schan2, sn2, env_st, env_en, lr_chan, lr_n;
   std::vector<double> sloc1, sloc2;
+  std::vector<int> oD, omix_ptr;        // MPO observables
   std::vector<double> Dh, Df, jopd, initd, obsd, init_t;
   std::vector<long> soff;
   double per_traj = 0;       // device bytes per trajectory (MPS, logs, outputs)
@@ -293,9 +326,11 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   for (int i = 0; i < n_obs; ++i)
     if (obs_site[i] < 0 || obs_site[i] >= L) return fail(m, TJM_E_INVAL, "observable site out of range");
   if (n_obs > 0 && !finite_arr(obs_op, 2L * n_obs * d * d)) return fail(m, TJM_E_INVAL, "observable not finite");
-  if ((double)n_traj * (double)(n + 1) * std::max(n_obs, 1) > 4e9)
+  const int n_mobs = (int)m->oW.size();
+  const int n_out = n_obs + n_mobs;          // output columns: site observables, then MPO observables
+  if ((double)n_traj * (double)(n + 1) * std::max(n_out, 1) > 4e9)
     return fail(m, TJM_E_INVAL, "output too large");
-  if ((double)(n + 1) * std::max(n_obs, 1) > 2e9) return fail(m, TJM_E_INVAL, "too many output entries per trajectory");
+  if ((double)(n + 1) * std::max(n_out, 1) > 2e9) return fail(m, TJM_E_INVAL, "too many output entries per trajectory");
   double tol = opt.krylov_tol;
   if (!(tol > 0.0)) tol = opt.precision == TJM_PREC_MIXED ? 1e-6 : 1e-12;   // mixed: at the FP32 contraction accuracy
 
@@ -307,7 +342,8 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   P.Dmax = *std::max_element(m->mpoD.begin(), m->mpoD.end());
   P.n_traj = n_traj; P.n_steps = (int)n;
   P.chi_max = chi_max; P.chi_cap = chi_cap; P.krylov_max = opt.krylov_max;
-  P.n_jump = m->n_jump; P.n_obs = n_obs; P.record_bonds = opt.record_bonds ? 1 : 0;
+  P.n_jump = m->n_jump; P.n_obs = n_out; P.record_bonds = opt.record_bonds ? 1 : 0;
+  P.n_site_obs = n_obs; P.n_mpo_obs = n_mobs;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
@@ -366,6 +402,32 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
           }
     }
   }
+  // MPO observables: right-environment rows (w, s_out) -> (w', s_in) per site
+  int oDm = 1;
+  for (const auto& D : m->omD) oDm = std::max(oDm, *std::max_element(D.begin(), D.end()));
+  P.oDmax = oDm;
+  pl.oD.clear();
+  pl.omix_ptr.assign((size_t)std::max(n_mobs, 1) * L * (oDm * d + 1), 0);
+  for (int q = 0; q < n_mobs; ++q) {
+    const auto& D = m->omD[q];
+    pl.oD.insert(pl.oD.end(), D.begin(), D.end());
+    for (int s = 0; s < L; ++s) {
+      const int Dl = D[s], Dr = D[s + 1];
+      const auto& W = m->oW[q][s];
+      int* rp = &pl.omix_ptr[((size_t)q * L + s) * (oDm * d + 1)];
+      for (int row = 0; row <= oDm * d; ++row) {
+        rp[row] = (int)ents.size();
+        if (row == oDm * d || row >= Dl * d) continue;
+        const int wl = row / d, so = row % d;
+        for (int wr = 0; wr < Dr; ++wr)
+          for (int si = 0; si < d; ++si) {
+            const cd v = W[(((long)wl * Dr + wr) * d + so) * d + si];
+            if (v != cd(0, 0)) push(wr, si, v);
+          }
+      }
+    }
+  }
+
 
   // ---- structure of the effective Hamiltonians -------------------------------
   // With the sites left of bond b left-canonical, the left environment L_b
@@ -611,9 +673,13 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   P.off_Z = o; o = align256(o + P.mat_cap * 16);
   P.off_C = o; o = align256(o + P.mat_cap * 16);
   P.off_wts = o; o = align256(o + (long)std::max(m->n_jump, 1) * 8);
+  P.oenv_cap = n_mobs ? (long)oDm * chic * chic : 0;
+  P.ot_cap = n_mobs ? (long)oDm * chic * d * chic : 0;
+  P.off_oenv = o; o = align256(o + 2 * P.oenv_cap * 16);
+  P.off_ot = o; o = align256(o + P.ot_cap * 16);
   P.scratch_stride = o;
 
-  pl.per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_obs * 8.0 + 2.0 * n * 4 +
+  pl.per_traj = (double)P.mps_cap * 16 + (L + 1) * 4.0 + (n + 1) * n_out * 8.0 + 2.0 * n * 4 +
                 (P.record_bonds ? (double)n * (L + 1) * 4 : 0.0) + TJM_NSTAT * 8 + 4;
   return TJM_OK;
 }
@@ -660,9 +726,10 @@ tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int 
              vec_bytes(pl.Dh) + vec_bytes(pl.Df) + vec_bytes(pl.jopd) + vec_bytes(m->jrate) +
              vec_bytes(m->jsite) + vec_bytes(pl.jptr) + vec_bytes(pl.jidx) + vec_bytes(pl.optr) +
              vec_bytes(pl.oidx) + vec_bytes(pl.obsd) + vec_bytes(pl.initd) + vec_bytes(pl.init_t) +
-             vec_bytes(m->init_bond) + vec_bytes(pl.soff) + vec_bytes(pl.bcap) + vec_bytes(m->mpoD);
+             vec_bytes(m->init_bond) + vec_bytes(pl.soff) + vec_bytes(pl.bcap) + vec_bytes(m->mpoD) +
+             vec_bytes(pl.oD) + vec_bytes(pl.omix_ptr);
   b += pl.per_traj * n_traj + (double)w * pl.P.scratch_stride + 256;
-  b += 2.0 * 8 * (pl.n + 1) * std::max(n_obs, 1);        // reduction outputs
+  b += 2.0 * 8 * (pl.n + 1) * std::max(pl.P.n_obs, 1);   // reduction outputs
   b += 64.0 * 1024 * 64;                                  // allocation granularity, 64 allocations
   *bytes = (size_t)b;
   *workers = (int)w;
@@ -685,7 +752,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   const long n = pl.n;
 
   Run* r = new Run();
-  r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = n_obs; r->record_bonds = pl.P.record_bonds;
+  r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = pl.P.n_obs; r->record_bonds = pl.P.record_bonds;
   r->use_graph = opt.graph ? 1 : 0;
   r->P = pl.P;
   TjmParams& P = r->P;
@@ -727,6 +794,8 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   RCHK(upload(r, pl.mixL_ptr, (int**)&P.mixL_ptr));
   RCHK(upload(r, pl.mixR_ptr, (int**)&P.mixR_ptr));
   RCHK(upload(r, pl.mix2_ptr, (int**)&P.mix2_ptr));
+  RCHK(upload(r, pl.oD, (int**)&P.oD));
+  RCHK(upload(r, pl.omix_ptr, (int**)&P.omixR_ptr));
   RCHK(upload(r, pl.sptr1, (int**)&P.s1_ptr));
   RCHK(upload(r, pl.schan1, (int**)&P.s1_chan));
   RCHK(upload(r, pl.sn1, (int**)&P.s1_n));
@@ -758,7 +827,7 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   void* p = nullptr;
   RCHK(dalloc(r, (size_t)n_traj * P.mps_cap * 16, &p)); P.mps = (double*)p;
   RCHK(dalloc(r, (size_t)n_traj * (L + 1) * 4, &p)); P.bonds = (int*)p;
-  RCHK(dalloc(r, (size_t)n_traj * (n + 1) * std::max(n_obs, 1) * 8, &p)); P.obs = (double*)p; r->d_obs = P.obs;
+  RCHK(dalloc(r, (size_t)n_traj * (n + 1) * std::max(P.n_obs, 1) * 8, &p)); P.obs = (double*)p; r->d_obs = P.obs;
   RCHK(dalloc(r, (size_t)n_traj * 2 * n * 4, &p)); P.jlog = (int*)p; r->d_jlog = P.jlog;
   if (r->record_bonds) {
     RCHK(dalloc(r, (size_t)n_traj * n * (L + 1) * 4, &p)); P.blog = (int*)p; r->d_blog = P.blog;
@@ -983,6 +1052,7 @@ tjm_model* tjm_model_copy(const tjm_model* m) {
     c->L = m->L; c->d = m->d; c->mpoD = m->mpoD; c->W = m->W;
     c->n_jump = m->n_jump; c->jsite = m->jsite; c->jop = m->jop; c->jrate = m->jrate;
     c->init = m->init; c->init_bond = m->init_bond; c->init_mps = m->init_mps;
+    c->omD = m->omD; c->oW = m->oW;
   } catch (...) {
     delete c;
     return nullptr;
@@ -991,6 +1061,7 @@ tjm_model* tjm_model_copy(const tjm_model* m) {
 }
 
 int tjm_model_d(const tjm_model* m) { return m ? m->d : 0; }
+int tjm_model_n_mpo_obs(const tjm_model* m) { return m ? (int)m->oW.size() : 0; }
 
 extern "C" void tjm_destroy(tjm_model* m) {
   if (!m) return;

@@ -40,6 +40,7 @@ tjm_status tjm_fail_global(tjm_status st, const char* msg);
 // A deep copy of a model's inputs (no run state); NULL if out of memory.
 tjm_model* tjm_model_copy(const tjm_model* m);
 int tjm_model_d(const tjm_model* m);
+int tjm_model_n_mpo_obs(const tjm_model* m);   // MPO observables registered (output columns after n_obs)
 // Validates a run as tjm_run_begin does and returns the device memory it
 // would hold and the resident workgroups it would use (opt->workers caps
 // them).  Makes opt->device current.  Errors as tjm_run_begin, message on m.

@@ -18,7 +18,8 @@ struct TjmParams {
   int L, d, Dmax;
   int n_traj, n_steps;
   int chi_max, chi_cap, krylov_max;
-  int n_jump, n_obs;
+  int n_jump, n_obs;                 // n_obs: output columns (site observables, then MPO observables)
+  int n_site_obs, n_mpo_obs;         // site observables are columns 0..n_site_obs-1
   int record_bonds;
   int mixed;                         // 1: complex-FP32 contractions
   int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
@@ -50,6 +51,11 @@ struct TjmParams {
   const int* env_en;                 // [L+1] identity channel of R_b (right-canonical right part)
   const int* lr_chan;                // [L+1][Dmax] the other channels of bond b
   const int* lr_n;                   // [L+1]
+  // MPO observables q < n_mpo_obs (column n_site_obs + q): bond dimensions
+  // and right-environment mixing rows in the layout of mixR_ptr
+  int oDmax;
+  const int* oD;                     // [n_mpo_obs][L+1]
+  const int* omixR_ptr;              // [n_mpo_obs][L][oDmax*d+1], entries in mixR
   const double* Dhalf;               // [L][d][d] complex: D_l[dt/2]
   const double* Dfull;               // [L][d][d] complex: D_l[dt]
   const double* jump_op;             // [n_jump][d][d] complex
@@ -89,6 +95,8 @@ struct TjmParams {
   long off_T1, t_cap;                // stage buffer, t_cap complex (T_c)
   long off_X, off_Y, off_Z, off_C, mat_cap;   // mat_cap complex doubles each
   long off_wts;                      // n_jump doubles
+  long off_oenv, oenv_cap;           // MPO observables: two FP64 environments of oenv_cap complex
+  long off_ot, ot_cap;               //   and their FP64 stage buffer of ot_cap complex
 
   int* counter;                      // work queue head
 };

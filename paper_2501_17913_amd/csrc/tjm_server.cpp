@@ -38,6 +38,7 @@ struct Job {
   uint64_t id = 0;
   tjm_model* model = nullptr;          // the server's own copy
   int n_traj = 0, chi_max = 0, n_obs = 0;
+  int n_out = 0;                       // output columns: n_obs site observables + the model's MPO observables
   double dt = 0, T = 0;
   uint64_t seed = 0;
   std::vector<int> obs_site;
@@ -77,7 +78,7 @@ struct tjm_server {
 };
 
 static void run_job(Job* j) {
-  const long entries = (long)(j->n_steps + 1) * j->n_obs;
+  const long entries = (long)(j->n_steps + 1) * j->n_out;
   j->mean.assign(std::max<long>(entries, 1), 0.0);
   j->sem.assign(std::max<long>(entries, 1), 0.0);
   j->status = tjm_run(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
@@ -156,6 +157,7 @@ extern "C" tjm_status tjm_submit(tjm_server* s, const tjm_model* m, const tjm_ru
   }
   const int d = tjm_model_d(m);
   j->n_traj = a->n_traj; j->dt = a->dt; j->T = a->T; j->chi_max = a->chi_max; j->n_obs = a->n_obs;
+  j->n_out = a->n_obs + tjm_model_n_mpo_obs(j->model);
   j->seed = a->seed;
   try {
     if (a->n_obs > 0) {
@@ -231,7 +233,7 @@ extern "C" tjm_status tjm_wait(tjm_server* s, uint64_t job, double* mean, double
     s->cv.wait(lk, [j] { return j->done != 0; });
     s->jobs.erase(j->id);
   }
-  const long entries = (long)(j->n_steps + 1) * j->n_obs;
+  const long entries = (long)(j->n_steps + 1) * j->n_out;
   if (j->status == TJM_OK) {
     if (mean) std::copy(j->mean.begin(), j->mean.begin() + entries, mean);
     if (sem) std::copy(j->sem.begin(), j->sem.begin() + entries, sem);

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NUMERI
                 5: "E_UNSUPPORTED", 6: "E_BUSY"}
 
 EXPORTED = [
-    "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps", "tjm_run",
+    "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps",
+    "tjm_add_mpo_observable", "tjm_clear_mpo_observables", "tjm_run",
     "tjm_run_traces",
     "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_run_read", "tjm_get_stats", "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd", "tjm_svd_noalloc",
@@ -87,6 +88,10 @@ lib.tjm_set_initial_product.argtypes = [_vp, _dp]
 lib.tjm_set_initial_product.restype = C.c_int
 lib.tjm_set_initial_mps.argtypes = [_vp, _ip, _dp]
 lib.tjm_set_initial_mps.restype = C.c_int
+lib.tjm_add_mpo_observable.argtypes = [_vp, _ip, _dp, _ip]
+lib.tjm_add_mpo_observable.restype = C.c_int
+lib.tjm_clear_mpo_observables.argtypes = [_vp]
+lib.tjm_clear_mpo_observables.restype = C.c_int
 lib.tjm_run.argtypes = [_vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_uint64,
                         C.POINTER(Options), _dp, _dp]
 lib.tjm_run.restype = C.c_int
@@ -189,6 +194,29 @@ class Model:
         self.h = h
         self.L = L
         self.d = d
+        self.n_mpo_obs = 0
+
+    def add_mpo_observable(self, mpo):
+        """Registers an MPO observable (site tensors W[s_out, s_in, w_l, w_r],
+        the layout of the Hamiltonian); runs report it after the site
+        observables, in registration order.  Returns its column offset among
+        the MPO observables."""
+        mpo = [_c128(W) for W in mpo]
+        if len(mpo) != self.L:
+            raise ValueError("need one MPO tensor per site")
+        bonds = np.array([1] + [W.shape[3] for W in mpo], dtype=np.int32)
+        if any(W.ndim != 4 or W.shape[2] != bonds[l] for l, W in enumerate(mpo)):
+            raise ValueError("site tensors must be (d, d, w_left, w_right) with matching neighbouring bonds")
+        flat = np.concatenate([W.reshape(-1) for W in mpo])
+        idx = C.c_int()
+        self._check(lib.tjm_add_mpo_observable(self.h, _iptr(bonds), flat.view(np.float64).ctypes.data_as(_dp),
+                                               C.byref(idx)))
+        self.n_mpo_obs += 1
+        return idx.value
+
+    def clear_mpo_observables(self):
+        self._check(lib.tjm_clear_mpo_observables(self.h))
+        self.n_mpo_obs = 0
 
     def _check(self, st):
         if st != OK:
@@ -226,7 +254,7 @@ class Model:
         opt = options or default_options()
         n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
         sites, ops = self._obs(observables)
-        no = len(observables)
+        no = len(observables) + self.n_mpo_obs
         mean = np.zeros((n + 1, no))
         sem = np.zeros((n + 1, no))
         out = {"mean": mean, "sem": sem}
@@ -234,12 +262,12 @@ class Model:
             per = np.zeros((n_traj, n + 1, no))
             jl = np.zeros((n_traj, 2 * n), dtype=np.int32)
             bl = np.zeros((n_traj, n, self.L + 1), dtype=np.int32) if opt.record_bonds else None
-            st = lib.tjm_run_traces(self.h, n_traj, dt, T, chi_max, no, _iptr(sites),
+            st = lib.tjm_run_traces(self.h, n_traj, dt, T, chi_max, len(observables), _iptr(sites),
                                     ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt),
                                     _dptr(mean), _dptr(sem), _dptr(per), _iptr(jl), _iptr(bl))
             out.update(per_traj=per, jumps=jl, bonds=bl)
         else:
-            st = lib.tjm_run(self.h, n_traj, dt, T, chi_max, no, _iptr(sites),
+            st = lib.tjm_run(self.h, n_traj, dt, T, chi_max, len(observables), _iptr(sites),
                              ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt),
                              _dptr(mean), _dptr(sem))
         self._check(st)
@@ -250,10 +278,10 @@ class Model:
         opt = options or default_options()
         sites, ops = self._obs(observables)
         self._n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
-        self._no = len(observables)
+        self._no = len(observables) + self.n_mpo_obs
         self._nt = n_traj
         self._rec = bool(opt.record_bonds)
-        self._check(lib.tjm_run_begin(self.h, n_traj, dt, T, chi_max, self._no, _iptr(sites),
+        self._check(lib.tjm_run_begin(self.h, n_traj, dt, T, chi_max, len(observables), _iptr(sites),
                                       ops.view(np.float64).ctypes.data_as(_dp), C.c_uint64(seed), C.byref(opt)))
 
     def advance(self, steps):
@@ -308,7 +336,7 @@ class Server:
         job = C.c_uint64()
         self._sc(lib.tjm_submit(self.h, model.h, C.byref(a), C.byref(job)))
         n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
-        self._jobs[job.value] = (n, len(observables))
+        self._jobs[job.value] = (n, len(observables) + model.n_mpo_obs)
         return job.value
 
     def poll(self, job):

@@ -234,3 +234,30 @@ def test_svd_noalloc_validates_before_touching_the_device():
         st = tjm.lib.tjm_svd_noalloc(m, n, bogus, 1e-12, 4, 1e-12, absorb, bogus, bogus, bogus, bogus, None)
         assert st == tjm.E_INVAL, (m, n, absorb)
     assert tjm.lib.tjm_svd_noalloc(8, 8, None, 1e-12, 4, 1e-12, 0, None, None, None, None, None) == tjm.E_INVAL
+
+
+def test_mpo_observable_registration_validation():
+    m = _model()
+    L = m.L
+    good = models.xxx_mpo(L, 1.0, 0.5)
+    assert m.add_mpo_observable(good) == 0
+    xx = [np.eye(2, dtype=np.complex128).reshape(2, 2, 1, 1) for _ in range(L)]
+    assert m.add_mpo_observable(xx) == 1 and m.n_mpo_obs == 2
+    # boundary bond, bond range and non-finite entries are rejected
+    bad = [W.copy() for W in good]
+    bad[-1] = np.zeros((2, 2, 5, 2), dtype=np.complex128)      # right boundary bond 2
+    with pytest.raises(tjm.TjmError) as e:
+        m.add_mpo_observable(bad)
+    assert e.value.status == tjm.E_INVAL
+    with pytest.raises(ValueError):                             # inconsistent neighbouring bonds
+        m.add_mpo_observable([good[0][:, :, :, :2]] + good[1:])
+    nan = [W.copy() for W in good]
+    nan[1][0, 0, 0, 0] = np.nan
+    with pytest.raises(tjm.TjmError) as e:
+        m.add_mpo_observable(nan)
+    assert e.value.status == tjm.E_INVAL
+    assert m.n_mpo_obs == 2
+    m.clear_mpo_observables()
+    assert m.n_mpo_obs == 0
+    assert tjm.lib.tjm_add_mpo_observable(None, None, None, None) == tjm.E_INVAL
+    assert tjm.lib.tjm_clear_mpo_observables(None) == tjm.E_INVAL
