@@ -44,7 +44,12 @@ def _jump(psi, full_jumps, eps, r):
     return psi / np.linalg.norm(psi), m
 
 
-def run_trajectory(H, jumps, psi0, dt, n_steps, observables, seed, traj, record=None, dense_observables=()):
+def run_trajectory(H, jumps, psi0, dt, n_steps, observables, seed, traj, record=None, dense_observables=(),
+                   order=2):
+    """Dense-vector TJM: the schedule of the MPS oracle with exact
+    propagators.  order = 2 is Eq. (TimeEvolutionFunctions); order = 1 the
+    first-order splitting of Sec. "Higher-order Trotterization" (F_k =
+    J D[dt] U[dt], no F_0, measured after each step)."""
     L = int(round(np.log2(H.shape[0])))
     U = sla.expm(-1j * H * dt)
     Dh = _kron_all([model.local_dissipator(jumps, s, 0.5 * dt) for s in range(L)])
@@ -59,6 +64,15 @@ def run_trajectory(H, jumps, psi0, dt, n_steps, observables, seed, traj, record=
     out = np.zeros((n_steps + 1, len(obs)))
     out[0] = measure(phi)
     jlog = []
+    if order == 1:
+        for k in range(1, n_steps + 1):
+            eps, r = philox.draws(seed, traj, k, philox.BRANCH_MAIN)
+            phi, m = _jump(Df @ (U @ phi), full, eps, r)
+            jlog.append((k, philox.BRANCH_MAIN, m))
+            out[k] = measure(phi)
+        if record is not None:
+            record['jumps'] = jlog
+        return out
     eps, r = philox.draws(seed, traj, 0, philox.BRANCH_MAIN)
     phi, m = _jump(Dh @ phi, full, eps, r)
     jlog.append((0, philox.BRANCH_MAIN, m))

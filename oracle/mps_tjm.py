@@ -35,6 +35,10 @@ listed in the design notes of the repository):
   R8  at most one jump per jump process;
   R9  the sampling layer uses its own draws;
   R10 t = 0 observables are measured on Psi(0).
+  R19 the first-order variant of Sec. "Higher-order Trotterization" (the
+      baseline splitting e^{-i H_D dt} e^{-i H_0 dt}): no F_0, every step
+      F_k = J D[dt] U[dt] with the main draws of step k, measured on its
+      result (no separate sampling layer).
 """
 import numpy as np
 
@@ -455,7 +459,7 @@ def bonds(mps):
 
 
 def run_trajectory(Ws, jumps, psi0, dt, n_steps, observables, seed, traj, opt,
-                   record=None, mpo_observables=()):
+                   record=None, mpo_observables=(), order=2):
     """One trajectory; returns [n_steps+1, n_obs + n_mpo] expectation values:
     the single-site observables, then the MPO observables (each a list of
     site tensors W[s', s, w, w']), all measured on the same states.
@@ -478,6 +482,21 @@ def run_trajectory(Ws, jumps, psi0, dt, n_steps, observables, seed, traj, opt,
     out[0] = measure(phi)
     jlog = []
     blog = []
+    if order == 1:
+        # first-order splitting (R19): F_k = J D[dt] U[dt] for k = 1..n
+        for k in range(1, n_steps + 1):
+            tdvp_step(phi, Ws, dt, opt, stats)
+            blog.append(bonds(phi))
+            dissipate(phi, Df)
+            eps, r = philox.draws(seed, traj, k, philox.BRANCH_MAIN)
+            m, _ = jump_process(phi, jumps, eps, r, opt)
+            jlog.append((k, philox.BRANCH_MAIN, m))
+            out[k] = measure(phi)
+        if record is not None:
+            record['jumps'] = jlog
+            record['bonds'] = blog
+            record['stats'] = stats
+        return out
     # F_0 = J D[dt/2]
     dissipate(phi, Dh)
     eps, r = philox.draws(seed, traj, 0, philox.BRANCH_MAIN)

@@ -8,6 +8,7 @@ them re-types the oracle's own formula.
 import os
 
 import numpy as np
+import scipy.linalg as sla
 import pytest
 
 from oracle import dense_tjm, lindblad, model, mps_tjm, philox
@@ -511,3 +512,130 @@ def test_full_rank_mpo_observables_equal_dense_tjm_per_trajectory():
         assert r1['jumps'] == r2['jumps']
         assert a.shape == b.shape == (7, L + L)
         assert np.abs(a - b).max() < 1e-11
+
+
+# --------------------------------------------------------------------------
+# The first-order splitting of Sec. "Higher-order Trotterization" against
+# the second-order schedule: for one spin with a field and sigma_minus
+# damping, every jump resets the spin to |0>, so the exact trajectory
+# average of each schedule follows from the distribution of the last reset
+# (computed here with 2x2 matrices from the definitions, independently of
+# the oracle's TJM code) and is compared with the exact Lindblad solution
+# from the 4x4 Liouvillian written out below.
+# --------------------------------------------------------------------------
+
+def _spin_setup(g, gam, dt):
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    Zm = np.diag([1.0, -1.0]).astype(complex)
+    sm = np.array([[0, 1], [0, 0]], dtype=complex)
+    H = -g * X
+    U = sla.expm(-1j * H * dt)
+    Dof = lambda tau: sla.expm(-0.5 * tau * gam * sm.conj().T @ sm)
+    return X, Zm, sm, H, U, Dof
+
+
+def _exact_schedule_average(order, g, gam, dt, n, psi0):
+    """E[<Z>(t_k)] over trajectories of the schedule (k = 0..n)."""
+    X, Zm, sm, H, U, Dof = _spin_setup(g, gam, dt)
+    Dh, Df = Dof(0.5 * dt), Dof(dt)
+    zero = np.array([1.0, 0.0], dtype=complex)
+    ez = lambda v: np.real(np.vdot(v, Zm @ v)) / np.real(np.vdot(v, v))
+
+    def jump_step(D, v):
+        """(no-jump state, no-jump probability) of J D applied to v (|v| = 1)."""
+        w = D @ v
+        p0 = np.real(np.vdot(w, w))
+        return w / np.sqrt(p0), p0
+
+    # a distribution over main-chain states: list of (probability, state)
+    out = [ez(psi0)]
+    if order == 1:
+        dist = [(1.0, psi0)]
+        for k in range(1, n + 1):
+            nd, reset = [], 0.0
+            for (p, v) in dist:
+                w, p0 = jump_step(Df, U @ v)
+                nd.append((p * p0, w))
+                reset += p * (1 - p0)
+            dist = nd + [(reset, zero)]
+            out.append(sum(p * ez(v) for p, v in dist))
+        return np.array(out)
+    w, p0 = jump_step(Dh, psi0)                        # F_0 = J D[dt/2]
+    dist = [(p0, w), (1 - p0, zero)]
+    for k in range(1, n + 1):
+        xs = [(p, U @ v) for (p, v) in dist]           # X = U Phi
+        # measured sample J_s D[dt/2] X, averaged over its own draw
+        e = 0.0
+        for (p, x) in xs:
+            ws, ps = jump_step(Dh, x)
+            e += p * (ps * ez(ws) + (1 - ps) * ez(zero))
+        out.append(e)
+        nd, reset = [], 0.0
+        for (p, x) in xs:                              # Phi = J D[dt] X
+            w, p0 = jump_step(Df, x)
+            nd.append((p * p0, w))
+            reset += p * (1 - p0)
+        dist = nd + [(reset, zero)]
+    return np.array(out)
+
+
+def _lindblad_spin_z(g, gam, T, psi0):
+    X, Zm, sm, H, U, Dof = _spin_setup(g, gam, 1.0)
+    I = np.eye(2)
+    # vec(A rho B) = (B^T kron A) vec(rho), column stacking
+    Lv = (-1j * (np.kron(I, H) - np.kron(H.T, I))
+          + gam * (np.kron(sm.conj(), sm) - 0.5 * np.kron(I, sm.conj().T @ sm)
+                   - 0.5 * np.kron((sm.conj().T @ sm).T, I)))
+    rho = np.outer(psi0, psi0.conj()).reshape(-1, order='F')
+    r = (sla.expm(Lv * T) @ rho).reshape(2, 2, order='F')
+    return np.real(np.trace(Zm @ r))
+
+
+def test_first_order_splitting_error_is_first_order_and_strang_second_order():
+    g, gam, T = 1.0, 0.8, 2.0
+    psi0 = np.array([np.cos(0.3), np.sin(0.3)], dtype=complex)
+    exact = _lindblad_spin_z(g, gam, T, psi0)
+    e1, e2 = [], []
+    for dt in (0.1, 0.05, 0.025):
+        n = int(round(T / dt))
+        e1.append(abs(_exact_schedule_average(1, g, gam, dt, n, psi0)[-1] - exact))
+        e2.append(abs(_exact_schedule_average(2, g, gam, dt, n, psi0)[-1] - exact))
+    assert 1.7 < e1[0] / e1[1] < 2.3 and 1.7 < e1[1] / e1[2] < 2.3
+    assert 3.4 < e2[0] / e2[1] < 4.6 and 3.4 < e2[1] / e2[2] < 4.6
+    assert e2[-1] < e1[-1] / 10
+
+
+def test_first_order_oracle_ensemble_matches_its_exact_average():
+    # the oracle's first-order MPS TJM on one spin, averaged over trajectories,
+    # against the exact average of the same schedule
+    g, gam, dt, n, N = 1.0, 0.8, 0.1, 20, 3000
+    psi0 = np.array([np.cos(0.3), np.sin(0.3)], dtype=complex)
+    ref = _exact_schedule_average(1, g, gam, dt, n, psi0)
+    Ws = model.xxx_mpo(1, 1.0, g)
+    jumps = [(0, model.SIGMA_MINUS, gam)]
+    per = np.array([mps_tjm.run_trajectory(Ws, jumps, [psi0.reshape(2, 1, 1)], dt, n, [(0, model.Z)], 11, t,
+                                           mps_tjm.Options(chi_max=2), order=1)[:, 0] for t in range(N)])
+    m, se = per.mean(0), per.std(0, ddof=1) / np.sqrt(N)
+    assert np.all(np.abs(m - ref) <= 4 * se + 1e-12)
+
+
+def test_first_order_full_rank_mps_equals_dense_per_trajectory():
+    L = 4
+    rng = np.random.default_rng(41)
+    psi = rng.normal(size=2 ** L) + 1j * rng.normal(size=2 ** L)
+    psi /= np.linalg.norm(psi)
+    m0 = mps_tjm.dense_to_mps(psi, L)
+    Ws = model.xxx_mpo(L, 1.0, 0.5)
+    H = model.xxx_dense(L, 1.0, 0.5)
+    jumps = model.relax_dephase_jumps(L, 0.3, 0.3)
+    obs = [(s, model.Z) for s in range(L)] + [(s, model.X) for s in range(L)]
+    opt = mps_tjm.Options(chi_max=16, chi_cap=16, svd_discard=-1.0)
+    n_jumps = 0
+    for traj in range(5):
+        r1, r2 = {}, {}
+        a = mps_tjm.run_trajectory(Ws, jumps, m0, 0.1, 8, obs, 13, traj, opt, r1, order=1)
+        b = dense_tjm.run_trajectory(H, jumps, psi, 0.1, 8, obs, 13, traj, r2, order=1)
+        assert r1['jumps'] == r2['jumps']
+        assert np.abs(a - b).max() < 1e-11
+        n_jumps += sum(1 for x in r1['jumps'] if x[2] >= 0)
+    assert n_jumps > 0
