@@ -458,62 +458,61 @@ TJM_DEV void rr_pair(int np, int rnd, int pr, int& a, int& b) {
 // off-diagonal |w_a^H w_b| / (|w_a| |w_b|) measured.  Ends with a barrier.
 constexpr int JAC_RPT = 8;           // rows per thread a pair keeps in registers
 
-TJM_DEVNI void jacobi_sweep(int p, int ncol, int n1, double zero2, double tol) {
-  SvdLds& SL = tjm_lds.sv;
+// The rounds of one sweep with TPP threads per pair (a group of TPP
+// neighbouring lanes, so the sums are DPP moves and shuffles within the
+// group): each thread holds rows gl + TPP t (t < JAC_RPT) of both columns,
+// which cover the p <= JAC_RPT * TPP rows in one pass.  Loads are
+// unconditional (rows beyond p read row 0 and are zeroed), so all 2 JAC_RPT
+// of a pair are in flight together.
+template <int TPP>
+TJM_DEV void jacobi_rounds(int p, int ncol, int n1, double zero2, double tol, double& offm, bool& rot) {
   zd* W = (zd*)tjm_lds.gemm;             // the columns, staged in LDS
+  constexpr int NGRP = TJM_NT / TPP;
   const int tid = tjm_tid();
+  const int g = tid / TPP, gl = tid % TPP;
   const int np = (ncol + 1) & ~1;        // players, a dummy if ncol is odd
   const int n2 = ncol - n1;
   const int mx = n1 > n2 ? n1 : n2;
   const int npair = n1 > 0 ? mx : np / 2;
   const int nrnd = n1 > 0 ? mx : np - 1;
-  // as many pairs at once as the workgroup holds, but enough threads per
-  // pair that each keeps at most JAC_RPT rows of the two columns
-  // (a group lies within one wavefront: its sums are lane shuffles)
-  int tpp = TJM_WAVE < 64 ? TJM_WAVE : 64;
-  while (tpp > 1 && tpp * npair > TJM_NT) tpp >>= 1;
-  while (tpp < 64 && tpp < TJM_WAVE && tpp < TJM_NT && tpp * JAC_RPT < p) tpp <<= 1;
-  const int span = JAC_RPT * tpp;         // rows one pass over the registers covers
-  const int ngrp = TJM_NT / tpp;
-  const int g = tid / tpp, gl = tid % tpp;
-  // this thread's largest relative off-diagonal and whether it rotated,
-  // merged into SL once at the end (not by an LDS atomic per pair and round)
-  double offm = 0.0;
-  bool rot = false;
   for (int rnd = 0; rnd < nrnd; ++rnd) {
-    for (int pr = g; pr < npair; pr += ngrp) {
+    for (int pr = g; pr < npair; pr += NGRP) {
       int a, b;
+      bool on;
       if (n1 > 0) {
         const int j = (pr + rnd) % mx;
-        if (pr >= n1 || j >= n2) continue;
         a = pr; b = n1 + j;
+        on = pr < n1 && j < n2;
       } else {
         rr_pair(np, rnd, pr, a, b);
-        if (b >= ncol) continue;
+        on = b < ncol;
       }
-      zd* wa = W + (long)a * p;
-      zd* wb = W + (long)b * p;
-      // rows r0 + gl + tpp t of both columns, in registers; one pass when
-      // p <= span, and then the rotation reuses them
+      if (!on) continue;                 // uniform over the group
+      zd* wa = W + a * p;
+      zd* wb = W + b * p;
       zd x[JAC_RPT], y[JAC_RPT];
-      double aa = 0.0, bb = 0.0, cr = 0.0, ci = 0.0;
-      for (int r0 = 0; r0 < p; r0 += span) {
 #pragma unroll
-        for (int t = 0; t < JAC_RPT; ++t) {
-          const int r = r0 + gl + tpp * t;
-          x[t] = r < p ? wa[r] : cmk(0.0, 0.0);
-          y[t] = r < p ? wb[r] : cmk(0.0, 0.0);
-        }
-#pragma unroll
-        for (int t = 0; t < JAC_RPT; ++t) {
-          aa += abs2(x[t]); bb += abs2(y[t]);
-          const zd c = cdotc(x[t], y[t]);
-          cr += c.re; ci += c.im;
-        }
+      for (int t = 0; t < JAC_RPT; ++t) {
+        const int r = gl + TPP * t;
+        const int rc = r < p ? r : 0;
+        x[t] = wa[rc];
+        y[t] = wb[rc];
       }
-      grp_sum4(aa, bb, cr, ci, tpp);
-      const double ac = hypot(cr, ci);
+      double aa = 0.0, bb = 0.0, cr = 0.0, ci = 0.0;
+#pragma unroll
+      for (int t = 0; t < JAC_RPT; ++t) {
+        const bool in = gl + TPP * t < p;
+        x[t] = csel(in, x[t], cmk(0.0, 0.0));
+        y[t] = csel(in, y[t], cmk(0.0, 0.0));
+        aa = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, aa));
+        bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
+        cr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, cr));      // conj(x) y
+        ci = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, ci));
+      }
+      aa = tjm_grp_sum<TPP>(aa); bb = tjm_grp_sum<TPP>(bb);
+      cr = tjm_grp_sum<TPP>(cr); ci = tjm_grp_sum<TPP>(ci);
       if (!(aa > zero2 && bb > zero2)) continue;
+      const double ac = hypot(cr, ci);
       const double sab = sqrt(aa) * sqrt(bb);     // no overflow for large norms
       const double rel = ac / sab;
       offm = fmax(offm, rel == rel ? rel : 1.0);
@@ -525,29 +524,46 @@ TJM_DEVNI void jacobi_sweep(int p, int ncol, int n1, double zero2, double tol) {
         if (zeta < 0.0) t = -t;
         const double cs = rsqrt(1.0 + t * t), sn = cs * t;
         const zd eph = cmk(cr * inv, -ci * inv);  // conj(c)/|c|
-        for (int r0 = 0; r0 < p; r0 += span) {
-          if (p > span) {
 #pragma unroll
-            for (int t = 0; t < JAC_RPT; ++t) {
-              const int r = r0 + gl + tpp * t;
-              x[t] = r < p ? wa[r] : cmk(0.0, 0.0);
-              y[t] = r < p ? wb[r] : cmk(0.0, 0.0);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < JAC_RPT; ++q) {
-            const int r = r0 + gl + tpp * q;
-            if (r < p) {
-              const zd yy = eph * y[q];
-              wa[r] = cs * x[q] - sn * yy;
-              wb[r] = sn * x[q] + cs * yy;
-            }
+        for (int q = 0; q < JAC_RPT; ++q) {
+          const int r = gl + TPP * q;
+          const zd yy = eph * y[q];
+          if (r < p) {
+            wa[r] = cs * x[q] - sn * yy;
+            wb[r] = sn * x[q] + cs * yy;
           }
         }
         rot = true;
       }
     }
     tjm_sync();
+  }
+}
+
+TJM_DEVNI void jacobi_sweep(int p, int ncol, int n1, double zero2, double tol) {
+  SvdLds& SL = tjm_lds.sv;
+  const int np = (ncol + 1) & ~1;
+  const int n2 = ncol - n1;
+  const int mx = n1 > n2 ? n1 : n2;
+  const int npair = n1 > 0 ? mx : np / 2;
+  // as many pairs at once as the workgroup holds, but enough threads per
+  // pair that each keeps at most JAC_RPT rows of the two columns (p <=
+  // JAC_RPT * 64); a group lies within one wavefront
+  int tpp = TJM_WAVE < 64 ? TJM_WAVE : 64;
+  while (tpp > 1 && tpp * npair > TJM_NT) tpp >>= 1;
+  while (tpp < 64 && tpp < TJM_WAVE && tpp < TJM_NT && tpp * JAC_RPT < p) tpp <<= 1;
+  // this thread's largest relative off-diagonal and whether it rotated,
+  // merged into SL once at the end (not by an LDS atomic per pair and round)
+  double offm = 0.0;
+  bool rot = false;
+  switch (tpp) {
+    case 1: jacobi_rounds<1>(p, ncol, n1, zero2, tol, offm, rot); break;
+    case 2: jacobi_rounds<2>(p, ncol, n1, zero2, tol, offm, rot); break;
+    case 4: jacobi_rounds<4>(p, ncol, n1, zero2, tol, offm, rot); break;
+    case 8: jacobi_rounds<8>(p, ncol, n1, zero2, tol, offm, rot); break;
+    case 16: jacobi_rounds<16>(p, ncol, n1, zero2, tol, offm, rot); break;
+    case 32: jacobi_rounds<32>(p, ncol, n1, zero2, tol, offm, rot); break;
+    default: jacobi_rounds<64>(p, ncol, n1, zero2, tol, offm, rot); break;
   }
   for (int s = TJM_WAVE / 2; s > 0; s >>= 1) offm = fmax(offm, tjm_shfl_xor(offm, s));
   const bool wrot = __any(rot);
