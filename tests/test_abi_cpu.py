@@ -142,7 +142,8 @@ def test_initial_mps_validation():
     (dict(n_traj=0), tjm.E_INVAL), (dict(dt=0.0), tjm.E_INVAL), (dict(T=0.25), tjm.E_INVAL),
     (dict(chi_max=0), tjm.E_INVAL), (dict(obs_site=9), tjm.E_INVAL),
     (dict(opt=dict(chi_cap=128)), tjm.E_UNSUPPORTED), (dict(opt=dict(krylov_max=40)), tjm.E_INVAL),
-    (dict(opt=dict(precision=7)), tjm.E_INVAL), (dict(opt=dict(sweep_jumps=0)), tjm.E_UNSUPPORTED)])
+    (dict(opt=dict(precision=7)), tjm.E_INVAL), (dict(opt=dict(sweep_jumps=0)), tjm.E_UNSUPPORTED),
+    (dict(opt=dict(trotter_order=3)), tjm.E_INVAL), (dict(opt=dict(trotter_order=0)), tjm.E_INVAL)])
 def test_run_rejects_bad_arguments_before_touching_the_device(kw, expect):
     m = _model()
     args = dict(n_traj=4, dt=0.1, T=0.3, chi_max=4, obs_site=0)

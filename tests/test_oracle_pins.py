@@ -460,7 +460,7 @@ def test_expm_krylov_matches_dense_expm():
 # dense linear algebra with operators built from Kronecker products
 # --------------------------------------------------------------------------
 
-def _random_mps(rng, bonds):
+def _random_mps_bonds(rng, bonds):
     L = len(bonds) - 1
     return [rng.normal(size=(2, bonds[s], bonds[s + 1])) + 1j * rng.normal(size=(2, bonds[s], bonds[s + 1]))
             for s in range(L)]
@@ -470,7 +470,7 @@ def _random_mps(rng, bonds):
 def test_mpo_expectation_matches_dense(bonds):
     rng = np.random.default_rng(sum(bonds))
     L = len(bonds) - 1
-    mps = _random_mps(rng, bonds)            # any gauge, any norm
+    mps = _random_mps_bonds(rng, bonds)      # any gauge, any norm
     psi = mps_tjm.mps_to_dense(mps)
     nrm = np.real(np.vdot(psi, psi))
 
