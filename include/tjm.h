@@ -105,6 +105,14 @@ typedef struct {
                              its steps); 0 (default): launches one step at a
                              time and waits for each.  Same kernels, same
                              results                                          */
+  int trotter_order;      /* 2 (default): the Strang-split schedule of Eq.
+                             (TimeEvolutionFunctions) with the sampling layer
+                             D[dt/2]; 1: the first-order splitting of Sec.
+                             "Higher-order Trotterization" (the paper's
+                             baseline): no F_0, every step F_k = J D[dt] U[dt]
+                             with the main draws of step k, observables
+                             measured on its result; jump_log then holds the
+                             step-k jump at 2k-1 and -1 at 0 and 2k         */
 } tjm_options;
 
 typedef struct {

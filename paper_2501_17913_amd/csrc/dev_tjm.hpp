@@ -882,7 +882,8 @@ template <typename Tc> struct Tjm {
       finish(mps, bA, o0);
     }
     if (P.n_mpo_obs) measure_mpo(mps, bA, o0);       // Psi(0), normalised
-    int m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
+    int m = -1;                                      // first-order splitting: no F_0
+    if (P.order == 2) m = jump_process(mps, bA, P.Dhalf, 0u, 0u, nullptr);
     if (tjm_tid() == 0) {
       P.jlog[(long)traj * 2 * P.n_steps] = m;
       if (m == -2) P.tflags[traj] = 1;
@@ -904,6 +905,23 @@ template <typename Tc> struct Tjm {
     load_bonds(bA, P.bonds + (long)traj * (L + 1));
     tdvp(mps, bA);
     if (P.record_bonds) store_bonds(P.blog + ((long)traj * P.n_steps + (k - 1)) * (L + 1), bA);
+    if (P.order == 1) {
+      // first-order splitting: Phi = J D[dt] U Phi, measured on its result
+      double* o1 = P.obs + ((long)traj * (P.n_steps + 1) + k) * P.n_obs;
+      const unsigned long long tj = tjm_clock();
+      const int m1 = jump_process(mps, bA, P.Dfull, (uint32_t)k, 0u, o1);
+      if (P.n_mpo_obs && m1 != -2) measure_mpo(mps, bA, o1);
+      since(TJM_ST_T_JUMP, tj);
+      if (tjm_tid() == 0) {
+        int* jl = P.jlog + (long)traj * 2 * P.n_steps;
+        jl[2 * k - 1] = m1;
+        if (k < P.n_steps) jl[2 * k] = -1;
+        if (m1 == -2) P.tflags[traj] = 1;
+      }
+      store_bonds(P.bonds + (long)traj * (L + 1), bA);
+      stats_end(traj);
+      return;
+    }
     for (int s = 0; s < L; ++s) copy(site(smps, P, s), site(mps, P, s), (long)bA[s] * d * bA[s + 1]);
     for (int b = tjm_tid(); b <= L; b += TJM_NT) bB[b] = bA[b];
     tjm_sync();

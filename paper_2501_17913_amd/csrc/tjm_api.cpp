@@ -97,6 +97,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->sweep_jumps = 1;
   o->generic_heff = 0;
   o->graph = 0;
+  o->trotter_order = 2;
 }
 
 // Validates an MPO in the layout of tjm_create (bond dimensions mpo_bond[0..L],
@@ -318,6 +319,7 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   const int chi_cap = opt.chi_cap > 0 ? opt.chi_cap : chi_max;
   if (chi_cap > 64) return fail(m, TJM_E_UNSUPPORTED, "chi_cap above 64 is not supported");
   if (opt.krylov_max < 1 || opt.krylov_max > 32) return fail(m, TJM_E_INVAL, "krylov_max must be in 1..32");
+  if (opt.trotter_order != 1 && opt.trotter_order != 2) return fail(m, TJM_E_INVAL, "trotter_order must be 1 or 2");
   if (opt.sweep_jumps != 1)
     return fail(m, TJM_E_UNSUPPORTED, "only the jump process with the printed sweeps (sweep_jumps = 1) is implemented");
   if (!std::isfinite(opt.svd_discard) || !std::isfinite(opt.deg_tol) || opt.deg_tol < 0)
@@ -344,6 +346,7 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   P.chi_max = chi_max; P.chi_cap = chi_cap; P.krylov_max = opt.krylov_max;
   P.n_jump = m->n_jump; P.n_obs = n_out; P.record_bonds = opt.record_bonds ? 1 : 0;
   P.n_site_obs = n_obs; P.n_mpo_obs = n_mobs;
+  P.order = opt.trotter_order;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;

@@ -15,6 +15,9 @@ hipError_t tjm_blocks_per_cu_float(int L, int* blocks);
 hipError_t tjm_blocks_per_cu_double(int L, int* blocks);
 hipError_t tjm_launch_step_float(const TjmParams& P, int k, int workers, hipStream_t s);
 hipError_t tjm_launch_step_double(const TjmParams& P, int k, int workers, hipStream_t s);
+// the pooled server's resident kernel (whole trajectories from a work queue)
+hipError_t tjm_launch_serve_float(const ServeDev& S, int workers, int L_max, hipStream_t s);
+hipError_t tjm_launch_serve_double(const ServeDev& S, int workers, int L_max, hipStream_t s);
 // mean / standard error over trajectories of obs[n_traj][entries], fixed order
 hipError_t tjm_launch_reduce(const double* obs, int n_traj, long entries, double* mean,
                              double* sem, hipStream_t s);

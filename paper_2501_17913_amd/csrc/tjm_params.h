@@ -21,6 +21,7 @@ struct TjmParams {
   int n_jump, n_obs;                 // n_obs: output columns (site observables, then MPO observables)
   int n_site_obs, n_mpo_obs;         // site observables are columns 0..n_site_obs-1
   int record_bonds;
+  int order;                         // 2: Strang-split schedule with sampling layer; 1: first-order splitting
   int mixed;                         // 1: complex-FP32 contractions
   int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
   double dt, krylov_tol, svd_discard, deg_tol;
@@ -122,3 +123,31 @@ enum {
   TJM_ST_T_GEMM = 15,     //   matrix-core products of the effective Hamiltonians (part of contractions)
   TJM_NSTAT = 16
 };
+
+// Work queue of the pooled server: one resident kernel per contraction
+// precision runs whole trajectories (F_0 .. F_n) of any admitted job.  The
+// host appends items to a ring in host-coherent memory and then raises
+// `tail`; workgroups take items in order through the device counter `head`
+// and mark each finished item in `done` (host-coherent).  A workgroup that
+// finds no item for `idle_spins` sleeps (about 8k cycles each), or sees
+// `stop`, exits, so the kernel always ends on its own.
+struct ServeItem {
+  int job;                           // index into params
+  int traj;                          // trajectory of that job
+};
+
+struct ServeShared {                 // host-coherent, written by the host
+  unsigned tail;                     // items appended so far
+  int stop;                          // 1: exit as soon as the queue is empty
+};
+
+struct ServeDev {
+  const TjmParams* params;           // [max_jobs] device copies of the jobs' parameters
+  const ServeItem* items;            // [cap] ring (host-coherent)
+  int* done;                         // [cap] 1 once item i % cap has finished (host-coherent)
+  ServeShared* sh;                   // host-coherent
+  unsigned* head;                    // device counter: items taken
+  int cap;
+  int idle_spins;
+};
+

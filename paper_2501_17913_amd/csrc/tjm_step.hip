@@ -48,6 +48,46 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_init_kernel(TjmParams P) {
   }
 }
 
+// The pooled server's resident kernel: whole trajectories of any admitted
+// job, taken from the work queue of ServeDev (see tjm_params.h).  Each
+// workgroup's scratch is slot blockIdx.x of the pool every job's
+// parameters point to, so only one such kernel per pool may be resident.
+template <typename T>
+__global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
+  extern __shared__ int dyn[];
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int got = -1;
+      for (int idle = 0; idle < S.idle_spins;) {
+        const unsigned h = __hip_atomic_load(S.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned t = __hip_atomic_load(&S.sh->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (h < t) {
+          if (atomicCAS(S.head, h, h + 1) == h) { got = (int)h; break; }
+          continue;                      // another workgroup took item h
+        }
+        if (__hip_atomic_load(&S.sh->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        __builtin_amdgcn_s_sleep(127);
+        ++idle;
+      }
+      tjm_lds.item = got;
+    }
+    __syncthreads();
+    const int it = tjm_lds.item;
+    __syncthreads();
+    if (it < 0) break;
+    const ServeItem w = S.items[it % S.cap];
+    const TjmParams& P = S.params[w.job];
+    Tjm<T> t(P, dyn, (int)blockIdx.x);
+    t.traj_init(w.traj);
+    for (int k = 1; k <= P.n_steps; ++k) t.traj_step(w.traj, k);
+    __syncthreads();                     // every thread's writes of the trajectory are issued
+    if (threadIdx.x == 0) {
+      __threadfence_system();
+      __hip_atomic_store(&S.done[it % S.cap], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
 #define TJM_CAT2(a, b) a##b
 #define TJM_CAT(a, b) TJM_CAT2(a, b)
 #define TJM_SUFFIX TJM_CAT(_, TJM_TC)
@@ -64,3 +104,9 @@ hipError_t TJM_CAT(tjm_launch_step, TJM_SUFFIX)(const TjmParams& P, int k, int w
     hipLaunchKernelGGL(tjm_step_kernel<Tc>, dim3(workers), dim3(TJM_NT), dyn, s, P, k);
   return hipGetLastError();
 }
+
+hipError_t TJM_CAT(tjm_launch_serve, TJM_SUFFIX)(const ServeDev& S, int workers, int L_max, hipStream_t s) {
+  hipLaunchKernelGGL(tjm_serve_kernel<Tc>, dim3(workers), dim3(TJM_NT), tjm_dyn_lds_bytes(L_max), s, S);
+  return hipGetLastError();
+}
+

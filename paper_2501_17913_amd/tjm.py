@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("krylov_max", C.c_int), ("krylov_tol", C.c_double), ("deg_tol", C.c_double),
                 ("workers", C.c_int), ("record_bonds", C.c_int), ("traj_base", C.c_uint32),
                 ("device", C.c_int), ("certify_sweeps", C.c_int), ("sweep_jumps", C.c_int),
-                ("generic_heff", C.c_int), ("graph", C.c_int)]
+                ("generic_heff", C.c_int), ("graph", C.c_int), ("trotter_order", C.c_int)]
 
 
 class Stats(C.Structure):
