@@ -185,17 +185,42 @@ def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
     return {"copy_bytes": n_bytes, "reps": reps, "avg_ms": ms, "GB/s": 2 * n_bytes / (ms * 1e-3) / 1e9}
 
 
-def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers, read_ids=0, deadline=None):
+def xxx_job(tjm, models, L):
+    """The XXX chain of the workloads (J=1, g=0.5, gamma=0.1), Neel start."""
+    mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
+    m = tjm.Model(L, mpo, s, o, r)
+    m.set_initial_product(models.neel(L))
+    return m
+
+
+def autotune(tjm, models, L, chi, N, T, prec, warm, timed, cache):
+    """tjm_autotune for the workload: (tile_mode, workers, report)."""
+    if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+    m = xxx_job(tjm, models, L)
+    t0 = time.perf_counter()
+    def progress(i, tm, w, us):
+        print("  autotune trial %d: tile_mode %d workers %d: %.1f us per trajectory-step (%.1fs)"
+              % (i, tm, w, us, time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+    tuned, rep = m.autotune(N, 0.1, T, chi, models.zx_observables(L), SEED, tjm.default_options(precision=prec),
+                            warm_steps=warm, timed_steps=timed, cache_path=cache, progress=progress)
+    m.close()
+    rep["tune_wall_s"] = time.perf_counter() - t0
+    print("  autotune: tile_mode %d workers %d (%s, %d trials, %.1fs)"
+          % (tuned.tile_mode, tuned.workers, "cached" if rep["cached"] else "tuned", rep["trials"],
+             rep["tune_wall_s"]), file=sys.stderr, flush=True)
+    return tuned.tile_mode, tuned.workers, rep
+
+
+def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers, read_ids=0, deadline=None, tile_mode=0):
     """Run one job on the GPU; time steps warmup+1 .. warmup+K.  With
     read_ids, the records of trajectories 0..read_ids-1 after the window are
     returned too.  With a deadline (perf_counter seconds), the job stops
     early once it is passed and the result says so (partial)."""
     dt = 0.1
-    n = int(round(T / dt))
-    mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
-    m = tjm.Model(L, mpo, s, o, r)
-    m.set_initial_product(models.neel(L))
-    opt = tjm.default_options(precision=prec, workers=workers)
+    m = xxx_job(tjm, models, L)
+    opt = tjm.default_options(precision=prec, workers=workers, tile_mode=tile_mode)
     name = "mixed" if prec == tjm.PREC_MIXED else "fp64"
     m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
     for k in range(warmup):
@@ -290,12 +315,14 @@ def serving(tjm, models, K, precision):
     reps.sort()
     lat = np.array([r["latency_s"] for _, r in reps])
     steps = sum(r["n_traj"] * r["n_steps"] for _, r in reps)
+    span = max(reqs[-1]["t"], 1e-9)
     flop = sum(8.0 * r["stats"]["cmac_mfma"] for _, r in reps)
     return {
         "metric": "p50/p99 latency of the serving stream (first %d requests)" % K,
         "value": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "unit": "s",
         "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "c64-mfma+f64" if prec else "f64",
-        "requests": K, "offered_rate_per_s": K / reqs[-1]["t"], "makespan_s": makespan,
+        "requests": K, "offered_rate_per_s": K / span, "makespan_s": makespan,
+        "offered_traj_steps_per_s": steps / span, "achieved_traj_steps_per_s": steps / makespan,
         "mean_queue_s": float(np.mean([r["queue_s"] for _, r in reps])),
         "mean_run_s": float(np.mean([r["run_s"] for _, r in reps])),
         "traj_steps_per_s": steps / makespan, "achieved_tflops": flop / makespan / 1e12,
@@ -325,6 +352,13 @@ def main():
                     help="only run the plain copy kernel used to calibrate the traffic counters")
     ap.add_argument("--serving", type=int, default=0, metavar="K",
                     help="instead: latency of the first K requests of the serving stream")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune tile_mode and workers for the workload first (tjm_autotune) and time with them")
+    ap.add_argument("--tune-warm", type=int, default=3, help="untimed steps of each autotuner trial")
+    ap.add_argument("--tune-steps", type=int, default=2, help="timed steps of each autotuner trial")
+    ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "paper_2501_17913_amd",
+                                                          "autotune.txt"),
+                    help="autotuner cache file ('' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -353,10 +387,14 @@ def main():
     t_start = time.perf_counter()
     nf = min(N, args.fp64_traj)
     compare_ids = nf if prec == tjm.PREC_MIXED and not args.no_fp64_compare else 0
-    head = measure(tjm, models, L, chi, N, T, prec, W, K, args.workers, read_ids=compare_ids)
+    workers, tile_mode, tune = args.workers, 0, None
+    if args.tune:
+        tile_mode, workers, tune = autotune(tjm, models, L, chi, N, T, prec, args.tune_warm, args.tune_steps,
+                                            args.tune_cache or None)
+    head = measure(tjm, models, L, chi, N, T, prec, W, K, workers, read_ids=compare_ids, tile_mode=tile_mode)
     peak = PEAK_TFLOPS[args.precision]
     out = {
-        "metric": "trajectory-steps/s at L=100 chi=64 (mixed vs FP64 path)",
+        "metric": "trajectory-steps/s at L=%d chi=%d (mixed vs FP64 path)" % (L, chi),
         "value": head["value"],
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
@@ -379,13 +417,17 @@ def main():
                      "kernel": "tjm_step_kernel<%s>" % ("float" if prec == tjm.PREC_MIXED else "double"),
                      "avg_launch_ms": head["avg_ms"], "algorithmic_flop_per_launch": head["flops_per_launch"]},
         "workers": head["workers"],
+        "tile_mode": tile_mode,
         "counts": head["counts"],
         "phase_frac": head["phase_frac"],
     }
+    if tune is not None:
+        out["autotune"] = tune
     if compare_ids:
         # leave room for the CPU baseline after it
         deadline = t_start + args.budget - (0 if args.no_cpu_baseline else args.cpu_budget + 60.0)
-        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, args.workers, read_ids=nf, deadline=deadline)
+        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, workers, read_ids=nf, deadline=deadline,
+                    tile_mode=tile_mode)
         if f["partial"]:
             out["fp64_path"] = {"value": None, "n_traj": nf, "partial": True, "steps_done": f["steps_done"],
                                 "reason": "stopped at the bench time budget (--budget %g s)" % args.budget}

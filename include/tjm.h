@@ -113,6 +113,16 @@ typedef struct {
                              with the main draws of step k, observables
                              measured on its result; jump_log then holds the
                              step-k jump at 2k-1 and -1 at 0 and 2k         */
+  int tile_mode;          /* tile choices of the contractions, 0..7 (default
+                             0); every choice gives the same results, only
+                             the speed differs (tjm_autotune picks one per
+                             workload).  Bit 0: the effective-Hamiltonian
+                             products keep the default 64 x 32 tile instead
+                             of the wide 64 x 128 / 128 x 64 (f32) or 64 x 64
+                             (f64) ones; bit 1: products below 32 x 16 run in
+                             16 x 8 wavefront blocks instead of 32 x 16;
+                             bit 2: the environment updates and generic
+                             products take the wide tiles too               */
 } tjm_options;
 
 typedef struct {
@@ -264,6 +274,57 @@ tjm_status tjm_run_read(tjm_model *m, double *per_traj_obs, int32_t *jump_log, i
 /* Kernel timings and algorithmic counters of the current or last run. */
 tjm_status tjm_get_stats(const tjm_model *m, tjm_stats *out);
 
+/*
+ * Autotuning of the launch configuration (tile_mode and resident workers)
+ * for one workload.  Every candidate gives the same results, so the tuner
+ * compares candidates on identical work: each trial is a separate run of a
+ * copy of m with the caller's arguments, seed and options (record_bonds and
+ * graph off) on min(n_traj, resident workgroups of one full launch)
+ * trajectories; it applies warm_steps untimed step functions, then times
+ * timed_steps with HIP events (step-kernel time per trajectory-step).  The
+ * candidates are the tile modes that can matter at chi_max (bits 0 and 2
+ * only change products of 48 or more rows, so below chi_max = 48 only bit 1
+ * is tried), at automatic workers; then, for the best tile mode, one
+ * workgroup per compute unit instead of the occupancy limit.
+ *
+ * Results are cached per key (device architecture and compute units,
+ * precision, chain length rounded up to a power of two, chi_max, largest MPO
+ * bond, site dimension, trial trajectories, trotter_order): in the process,
+ * and, if cache_path is not NULL, in that text file (one line per result,
+ * "key tile_mode workers us_per_traj_step"; appended after tuning).  The
+ * file's last line for the key, else this process's result for it, is
+ * returned without any trial.
+ *
+ * *tuned receives *base (NULL: defaults) with tile_mode and workers
+ * replaced.  warm_steps >= 0, timed_steps >= 1, and their sum at most the
+ * run's step count (otherwise TJM_E_INVAL).  m is not changed (its last
+ * error is set on failure); it must not have a run in progress
+ * (TJM_E_BUSY).  Unreadable cache files are ignored; an unwritable one is
+ * not an error (rep->cache_written = 0).
+ */
+typedef struct {
+  int cached;                      /* 1: from the cache, nothing timed          */
+  int trials;                      /* trial runs timed                          */
+  int trial_traj;                  /* trajectories per trial run                */
+  int tile_mode, workers;          /* the choice (as in *tuned)                 */
+  int cache_written;               /* 1: the result was appended to cache_path  */
+  double us_per_traj_step;         /* step-kernel time of the choice per
+                                      trajectory-step, microseconds            */
+  double default_us_per_traj_step; /* the same for tile_mode 0 at automatic
+                                      workers (0 when cached)                  */
+  char key[192];                   /* cache key, NUL-terminated                 */
+} tjm_tune_report;
+
+/* Called after each trial (in the caller's thread): its 0-based number, the
+ * candidate and its time per trajectory-step in microseconds. */
+typedef void (*tjm_tune_progress)(int trial, int tile_mode, int workers, double us_per_traj_step, void *ctx);
+
+tjm_status tjm_autotune(tjm_model *m, int n_traj, double dt, double T, int chi_max,
+                        int n_obs, const int *obs_site, const double *obs_op, uint64_t seed,
+                        const tjm_options *base, int warm_steps, int timed_steps,
+                        const char *cache_path, tjm_tune_progress progress, void *progress_ctx,
+                        tjm_options *tuned, tjm_tune_report *rep);
+
 /* Message of the last failing call on m (m may be NULL: last create error). */
 const char *tjm_last_error(const tjm_model *m);
 
@@ -272,15 +333,28 @@ void tjm_destroy(tjm_model *m);
 
 /*
  * Serving.  A server executes independent jobs, each one whole run as
- * tjm_run defines it (Sec. "Algorithm"), on one GPU as they are submitted.
- * Trajectories of different jobs never interact (Eq. TJMExpVal averages
- * within a job), so up to four admitted jobs run at once, each on a HIP
- * stream of its own; their results are bit-identical to tjm_run with the
- * same arguments.  Admission is first come, first served: the oldest waiting
- * job starts when an executor is free and its device-memory footprint fits
- * into the budget not held by running jobs; no younger job overtakes it.
- * The server functions are thread-safe; a model handle passed to
- * tjm_submit is only read during that call (the server keeps a copy).
+ * tjm_run defines it (Sec. "Algorithm"), on one GPU as they are submitted,
+ * with continuous batching at the level of trajectories.  Trajectories of
+ * different jobs never interact (Eq. TJMExpVal averages within a job), so
+ * each precision has one work queue served by a resident kernel whose
+ * workgroups run (job, trajectory) items whole, F_0 to F_n, in admission
+ * order: the trajectories of a job admitted while others run start as soon
+ * as workgroups free up, next to theirs.  Results are bit-identical to
+ * tjm_run with the same arguments.
+ *
+ * Device memory: each admitted job holds its own buffers (tables, MPSs,
+ * outputs); the workgroups' scratch is a pool per queue, shaped for the
+ * largest chain and bond dimension it serves.  A job larger than the
+ * current pool of its precision opens a new queue with a larger pool (the
+ * old one drains and is released).  Admission is first come, first served:
+ * the oldest waiting job is admitted once its buffers, and any new pool it
+ * needs, fit into the budget not held by admitted jobs and pools; no
+ * younger job overtakes it.  Up to 256 jobs per queue are in flight, and up
+ * to 2^20 of their trajectories.  The server functions are thread-safe; a
+ * model handle passed to tjm_submit is only read during that call (the
+ * server keeps a copy).  tjm_options.graph and workers do not apply to
+ * server jobs (the resident kernel has no per-step launches, and its
+ * workgroup count is the pool's).
  */
 typedef struct tjm_server tjm_server;
 
@@ -295,8 +369,8 @@ typedef struct {
   const double *obs_op;     /* n_obs complex d x d matrices                  */
   uint64_t seed;
   const tjm_options *opt;   /* NULL: defaults; opt->device is replaced by the
-                               server's device, opt->workers is capped so
-                               the job stays within its admitted footprint */
+                               server's device; workers and graph are not
+                               used                                          */
 } tjm_run_args;
 
 /* What tjm_wait reports about a finished job. */
@@ -308,14 +382,16 @@ typedef struct {
                                (seconds from an arbitrary origin, comparable
                                between jobs of one process)                 */
   int n_traj, n_steps;
-  size_t device_bytes;      /* footprint the job was admitted with           */
+  size_t device_bytes;      /* the job's own device buffers (tables, MPSs,
+                               outputs) it was admitted with                */
   tjm_stats stats;          /* counters and kernel timings of its run        */
+  size_t pool_bytes;        /* scratch pool of its precision while it ran    */
 } tjm_job_report;
 
 /*
  * Creates a server on HIP device `device` with a device-memory budget
  * (bytes; 0 selects 85% of the memory free at creation) and starts its
- * executor threads.  Errors: TJM_E_INVAL (NULL, device ordinal),
+ * dispatcher thread.  Errors: TJM_E_INVAL (NULL, device ordinal),
  * TJM_E_DEVICE (no GPU), TJM_E_NOMEM.
  */
 tjm_status tjm_server_create(tjm_server **out, int device, size_t hbm_budget_bytes);
@@ -323,7 +399,8 @@ tjm_status tjm_server_create(tjm_server **out, int device, size_t hbm_budget_byt
 /*
  * Queues one job and returns its id in *job without waiting for it.  The
  * arguments are validated as tjm_run validates them (TJM_E_INVAL,
- * TJM_E_UNSUPPORTED) and the job is sized; a job larger than the whole
+ * TJM_E_UNSUPPORTED; also more than 2^20 trajectories) and the job is
+ * sized; a job whose buffers and a pool of its own shape exceed the whole
  * budget is refused with TJM_E_NOMEM.  TJM_E_BUSY once the server is being
  * destroyed.
  */

@@ -36,7 +36,8 @@ def build(verbose=False):
              ("tjm_kernels.hip", "tjm_kernels", []),
              ("tjm_noalloc.hip", "tjm_noalloc", []),
              ("tjm_api.cpp", "tjm_api", ["-x", "hip"]),
-             ("tjm_server.cpp", "tjm_server", ["-x", "hip"])]
+             ("tjm_server.cpp", "tjm_server", ["-x", "hip"]),
+             ("tjm_tune.cpp", "tjm_tune", ["-x", "hip"])]
     for src, name, extra in units:
         obj = os.path.join(CSRC, name + ".o")
         cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]

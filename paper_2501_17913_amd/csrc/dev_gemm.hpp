@@ -149,9 +149,11 @@ template <typename T> struct EmbedLane {
   TJM_DEV T b(cplx<T> e) const { return fa * e.re + fb * e.im; }
 };
 
-// Small products: each wavefront owns 32 x 16 complex blocks and feeds the
-// matrix cores straight from memory (no LDS, no workgroup barriers).
-template <typename T, class OA, class OB, typename SC>
+// Small products: each wavefront owns (16 WI) x (8 WJ) complex blocks (32 x
+// 16 by default) and feeds the matrix cores straight from memory (no LDS, no
+// workgroup barriers).  Smaller blocks re-read the operands more often but
+// give the smallest products enough blocks for all four wavefronts.
+template <typename T, int WI = 2, int WJ = 2, class OA, class OB, typename SC>
 TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
                         const OA& A, const OB& B,
                         cplx<SC>* C, int ldc, long cs, bool accumulate) {
@@ -163,17 +165,20 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
   const int kp = q & 1;
   const int cpart = r16 & 1;
   const EmbedLane<T> emb(kp, cpart);
-  const int nti = (M + 31) / 32, ntj = (N + 15) / 16;
+  constexpr int RB = 16 * WI, CB = 8 * WJ;
+  const int nti = (M + RB - 1) / RB, ntj = (N + CB - 1) / CB;
   const int nout = sum_batches ? 1 : nb;
   const int nitems = nout * nti * ntj;
   for (int it = tjm_wave(); it < nitems; it += TJM_NWAVE) {
     const int ob = it / (nti * ntj);
     const int rem = it - ob * (nti * ntj);
-    const int i0 = (rem / ntj) * 32;
-    const int j0 = (rem % ntj) * 16;
-    acc_t acc[2][2];
-    acc[0][0] = Mfma<T>::zero(); acc[0][1] = Mfma<T>::zero();
-    acc[1][0] = Mfma<T>::zero(); acc[1][1] = Mfma<T>::zero();
+    const int i0 = (rem / ntj) * RB;
+    const int j0 = (rem % ntj) * CB;
+    acc_t acc[WI][WJ];
+#pragma unroll
+    for (int ti = 0; ti < WI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WJ; ++tj) acc[ti][tj] = Mfma<T>::zero();
     const int b_lo = sum_batches ? 0 : ob;
     const int b_hi = sum_batches ? nb : ob + 1;
     for (int b = b_lo; b < b_hi; ++b) {
@@ -181,29 +186,32 @@ TJM_DEV void wave_cgemm(int M, int N, int K, int nb, bool sum_batches,
       for (int k0 = 0; k0 < K; k0 += 2) {
         const int kc = k0 + kq;
         const bool kin = kc < K;
-        T av[2], bv[2];
+        T av[WI], bv[WJ];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < WI; ++t) {
           const int row = i0 + 16 * t + r16;
           const bool oka = kin && row < M;
           const cplx<T> ea = A.template get<T>(b, oka ? row : 0, oka ? kc : 0);
           av[t] = oka ? emb.a(ea) : (T)0;
+        }
+#pragma unroll
+        for (int t = 0; t < WJ; ++t) {
           const int col = j0 + 8 * t + (r16 >> 1);
           const bool okb = kin && col < N;
           const cplx<T> eb = B.template get<T>(b, okb ? kc : 0, okb ? col : 0);
           bv[t] = okb ? emb.b(eb) : (T)0;
         }
-        acc[0][0] = Mfma<T>::mma(av[0], bv[0], acc[0][0]);
-        acc[0][1] = Mfma<T>::mma(av[0], bv[1], acc[0][1]);
-        acc[1][0] = Mfma<T>::mma(av[1], bv[0], acc[1][0]);
-        acc[1][1] = Mfma<T>::mma(av[1], bv[1], acc[1][1]);
+#pragma unroll
+        for (int ti = 0; ti < WI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < WJ; ++tj) acc[ti][tj] = Mfma<T>::mma(av[ti], bv[tj], acc[ti][tj]);
       }
     }
     cplx<SC>* Cb = C + (long)ob * cs;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < WI; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
+      for (int tj = 0; tj < WJ; ++tj) {
         const int col = j0 + 8 * tj + (r16 >> 1);
         if (col >= N) continue;
 #pragma unroll
@@ -316,6 +324,15 @@ TJM_DEV void blk_cgemm(int M, int N, int K, int nb, bool sum_batches, const OA& 
   blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
 }
 
+// The same with the tile choice of a run (tile_mode of the options, chosen
+// per workload by the autotuner): bit 0 set keeps large products on the
+// default tile (no wide shapes), bit 1 set computes small products in 16 x 8
+// wavefront blocks.  Every choice sums each output's k terms in the same
+// order, so the results do not depend on it.
+template <typename T, class OA, class OB, typename SC>
+TJM_DEV void blk_cgemm_mode(int mode, int M, int N, int K, int nb, bool sum_batches, const OA& A,
+                            const OB& B, cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds);
+
 // The same with the tile shape chosen for the product's size: the wide
 // shapes where the output spans them (64 x 128 or 128 x 64 for f32
 // contractions, 64 x 64 for f64, whose accumulators take twice the
@@ -336,4 +353,18 @@ TJM_DEV void blk_cgemm_auto(int M, int N, int K, int nb, bool sum_batches, const
     else
       blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
   }
+}
+
+template <typename T, class OA, class OB, typename SC>
+TJM_DEV void blk_cgemm_mode(int mode, int M, int N, int K, int nb, bool sum_batches, const OA& A,
+                            const OB& B, cplx<SC>* C, int ldc, long cs, bool accumulate, void* lds) {
+  if (M <= 0 || N <= 0) return;
+  if ((mode & 2) && (M < 32 || N < 16 || K < 8)) {
+    wave_cgemm<T, 1, 1>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate);
+    return;
+  }
+  if (mode & 1)
+    blk_cgemm_t<T, GEMM_BM, GEMM_BN>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
+  else
+    blk_cgemm_auto<T>(M, N, K, nb, sum_batches, A, B, C, ldc, cs, accumulate, lds);
 }

@@ -67,6 +67,13 @@ template <typename Tc> struct Tjm {
     return (unsigned long long)(rp[Dout * dph] - rp[0]);
   }
 
+  // Tile choices of the contractions (tile_mode of the options; the same
+  // results under every choice): the effective-Hamiltonian products take
+  // wide tiles unless bit 0 is set, the other products only if bit 2 is set;
+  // bit 1 selects the small-block variant of the smallest products.
+  TJM_DEV int tm_heff() const { return P.tile_mode & 3; }
+  TJM_DEV int tm_other() const { return (P.tile_mode & 2) | ((P.tile_mode & 4) ? 0 : 1); }
+
   // ------------------------------------------------------------------
   // Environments (Fig. TDVP; Sec. "Hybrid strategy")
   // ------------------------------------------------------------------
@@ -79,10 +86,10 @@ template <typename Tc> struct Tjm {
     const unsigned long long t0 = tjm_clock();
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
-    blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
+    blk_cgemm_mode<Tc>(tm_other(), chl, d * chr, chl, Dl, false, cmat(Lold, chl, (long)chl * chl), cmat(A, d * chr),
                   T1, d * chr, (long)chl * d * chr, false, tjm_lds.gemm);
     tjm_sync();
-    blk_cgemm<Tc>(chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
+    blk_cgemm_mode<Tc>(tm_other(), chr, chr, chl * d, Dr, false, cmat(A, chr, 0, true, true),
                   mix_rows((const zc*)T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
                   Lnew, chr, (long)chr * chr, false, tjm_lds.gemm);
     tjm_sync();
@@ -97,10 +104,10 @@ template <typename Tc> struct Tjm {
   template <typename TE>
   TJM_DEV void env_right(const zd* B, int chl, int chr, int Dl, int Dr, const int* rp, const MixEnt* ents,
                          const cplx<TE>* Rold, cplx<TE>* Rnew, cplx<TE>* Tb) {
-    blk_cgemm<TE>(chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
+    blk_cgemm_mode<TE>(tm_other(), chl * d, chr, chr, Dr, false, cmat(B, chr), cmat(Rold, chr, (long)chr * chr),
                   Tb, chr, (long)chl * d * chr, false, tjm_lds.gemm);
     tjm_sync();
-    blk_cgemm<TE>(chl, chl, d * chr, Dl, false,
+    blk_cgemm_mode<TE>(tm_other(), chl, chl, d * chr, Dl, false,
                   mix_cols((const cplx<TE>*)Tb, rp, ents, d, chr, (long)chl * d * chr, (long)d * chr, (long)chr),
                   cmat(B, d * chr, 0, true, true), Rnew, chl, (long)chl * chl, false, tjm_lds.gemm);
     tjm_sync();
@@ -198,14 +205,14 @@ template <typename Tc> struct Tjm {
     const unsigned long long tg = tjm_clock();
     bool acc = false;
     if (nL > 0) {      // left class: (chl x chl) . (chl x dp chr), summed over channels
-      blk_cgemm_auto<Tc>(chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
+      blk_cgemm_mode<Tc>(tm_heff(), chl, dp * chr, chl, nL, true, chan_mat(Le, chl, (long)chl * chl, chanL),
                     mix_cols(q, ptrL, P.mixL, dp, chr, 0L, (long)dp * chr, (long)chr), y, dp * chr, 0, false,
                     tjm_lds.gemm);
       tjm_sync();        // the small-product path returns without a barrier
       acc = true;
     }
     if (nR > 0) {      // right class: (chl dp x chr) . (chr x chr), summed over channels
-      blk_cgemm_auto<Tc>(chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
+      blk_cgemm_mode<Tc>(tm_heff(), chl * dp, chr, chr, nR, true, mix_rows(q, ptrR, P.mixL, dp, 0L, (long)dp * chr, (long)chr),
                     chan_mat(Re, chr, (long)chr * chr, chanR), y, chr, 0, acc, tjm_lds.gemm);
       tjm_sync();
       acc = true;
@@ -235,10 +242,10 @@ template <typename Tc> struct Tjm {
         return;
       }
       const int* rp = P.mixL_ptr + (long)s * (P.Dmax * d + 1);
-      blk_cgemm<Tc>(chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
+      blk_cgemm_mode<Tc>(t->tm_other(), chl, d * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d * chr),
                     t->T1, d * chr, (long)chl * d * chr, false, tjm_lds.gemm);
       tjm_sync();
-      blk_cgemm<Tc>(chl * d, chr, chr, Dr, true,
+      blk_cgemm_mode<Tc>(t->tm_other(), chl * d, chr, chr, Dr, true,
                     mix_rows((const zc*)t->T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
                     cmat(Re, chr, (long)chr * chr), y, chr, 0, false, tjm_lds.gemm);
       tjm_sync();
@@ -264,10 +271,10 @@ template <typename Tc> struct Tjm {
         return;
       }
       const int* rp = P.mix2_ptr + (long)s * (P.Dmax * d2 + 1);
-      blk_cgemm<Tc>(chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
+      blk_cgemm_mode<Tc>(t->tm_other(), chl, d2 * chr, chl, Dl, false, cmat(Le, chl, (long)chl * chl), cmat(q, d2 * chr),
                     t->T1, d2 * chr, (long)chl * d2 * chr, false, tjm_lds.gemm);
       tjm_sync();
-      blk_cgemm<Tc>(chl * d2, chr, chr, Dr, true,
+      blk_cgemm_mode<Tc>(t->tm_other(), chl * d2, chr, chr, Dr, true,
                     mix_rows((const zc*)t->T1, rp, P.mix2, d2, (long)chl * d2 * chr, (long)d2 * chr, (long)chr),
                     cmat(Re, chr, (long)chr * chr), y, chr, 0, false, tjm_lds.gemm);
       tjm_sync();
@@ -287,16 +294,16 @@ template <typename Tc> struct Tjm {
         // y = C R[st] + L[en] C + sum_{other w} (L[w] C) R[w]
         const int st = P.env_st[b], en = P.env_en[b], nlr = P.lr_n[b];
         const int* lr = P.lr_chan + (long)b * P.Dmax;
-        blk_cgemm<Tc>(kl, kr, kr, 1, true, cmat(q, kr), cmat(Re + (long)st * kr * kr, kr), y, kr, 0, false,
+        blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kr, 1, true, cmat(q, kr), cmat(Re + (long)st * kr * kr, kr), y, kr, 0, false,
                       tjm_lds.gemm);
         tjm_sync();      // the small-product path returns without a barrier
-        blk_cgemm<Tc>(kl, kr, kl, 1, true, cmat(Le + (long)en * kl * kl, kl), cmat(q, kr), y, kr, 0, true,
+        blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kl, 1, true, cmat(Le + (long)en * kl * kl, kl), cmat(q, kr), y, kr, 0, true,
                       tjm_lds.gemm);
         if (nlr > 0) {
-          blk_cgemm<Tc>(kl, kr, kl, nlr, false, chan_mat(Le, kl, (long)kl * kl, lr), cmat(q, kr),
+          blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kl, nlr, false, chan_mat(Le, kl, (long)kl * kl, lr), cmat(q, kr),
                         t->T1, kr, (long)kl * kr, false, tjm_lds.gemm);
           tjm_sync();
-          blk_cgemm<Tc>(kl, kr, kr, nlr, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
+          blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kr, nlr, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
                         chan_mat(Re, kr, (long)kr * kr, lr), y, kr, 0, true, tjm_lds.gemm);
         }
         tjm_sync();
@@ -305,10 +312,10 @@ template <typename Tc> struct Tjm {
         t->since(TJM_ST_T_CONTRACT, t0);
         return;
       }
-      blk_cgemm<Tc>(kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
+      blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kl, D, false, cmat(Le, kl, (long)kl * kl), cmat(q, kr),
                     t->T1, kr, (long)kl * kr, false, tjm_lds.gemm);
       tjm_sync();
-      blk_cgemm<Tc>(kl, kr, kr, D, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
+      blk_cgemm_mode<Tc>(t->tm_other(), kl, kr, kr, D, true, cmat((const zc*)t->T1, kr, (long)kl * kr),
                     cmat(Re, kr, (long)kr * kr), y, kr, 0, false, tjm_lds.gemm);
       tjm_sync();
       t->count(TJM_ST_CMAC_MFMA, (unsigned long long)D * kl * kl * kr + (unsigned long long)D * kl * kr * kr);

@@ -98,6 +98,7 @@ extern "C" void tjm_default_options(tjm_options* o) {
   o->generic_heff = 0;
   o->graph = 0;
   o->trotter_order = 2;
+  o->tile_mode = 0;
 }
 
 // Validates an MPO in the layout of tjm_create (bond dimensions mpo_bond[0..L],
@@ -320,6 +321,7 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   if (chi_cap > 64) return fail(m, TJM_E_UNSUPPORTED, "chi_cap above 64 is not supported");
   if (opt.krylov_max < 1 || opt.krylov_max > 32) return fail(m, TJM_E_INVAL, "krylov_max must be in 1..32");
   if (opt.trotter_order != 1 && opt.trotter_order != 2) return fail(m, TJM_E_INVAL, "trotter_order must be 1 or 2");
+  if (opt.tile_mode < 0 || opt.tile_mode > 7) return fail(m, TJM_E_INVAL, "tile_mode must be in 0..7");
   if (opt.sweep_jumps != 1)
     return fail(m, TJM_E_UNSUPPORTED, "only the jump process with the printed sweeps (sweep_jumps = 1) is implemented");
   if (!std::isfinite(opt.svd_discard) || !std::isfinite(opt.deg_tol) || opt.deg_tol < 0)
@@ -347,6 +349,7 @@ static tjm_status plan_run(tjm_model* m, int n_traj, double dt, double T, int ch
   P.n_jump = m->n_jump; P.n_obs = n_out; P.record_bonds = opt.record_bonds ? 1 : 0;
   P.n_site_obs = n_obs; P.n_mpo_obs = n_mobs;
   P.order = opt.trotter_order;
+  P.tile_mode = opt.tile_mode;
   P.mixed = opt.precision == TJM_PREC_MIXED ? 1 : 0;
   P.certify = opt.certify_sweeps < 0 ? P.mixed : (opt.certify_sweeps ? 1 : 0);
   P.dt = dt; P.krylov_tol = tol; P.svd_discard = opt.svd_discard; P.deg_tol = opt.deg_tol;
@@ -739,30 +742,18 @@ tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int 
   return TJM_OK;
 }
 
-extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double T, int chi_max,
-                                    int n_obs, const int* obs_site, const double* obs_op,
-                                    uint64_t seed, const tjm_options* opt_in) {
-  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
-  if (m->run) return fail(m, TJM_E_BUSY, "a run is already in progress on this model");
-  tjm_options opt;
-  tjm_default_options(&opt);
-  if (opt_in) opt = *opt_in;
-  Plan pl;
-  tjm_status st0 = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt, pl);
-  if (st0 != TJM_OK) return st0;
-  if ((st0 = select_device(m, opt)) != TJM_OK) return st0;
+// Device allocations and uploads of a planned run.  With pool_scratch the
+// workers' scratch is that pool (pool_workers slots of pool_stride bytes,
+// at least the plan's stride) instead of an allocation of the run's own.
+static tjm_status alloc_run(tjm_model* m, Plan& pl, const tjm_options& opt, int n_traj, Run* r,
+                            char* pool_scratch, long pool_stride, int pool_workers) {
   const int L = m->L;
   const long n = pl.n;
-
-  Run* r = new Run();
   r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = pl.P.n_obs; r->record_bonds = pl.P.record_bonds;
   r->use_graph = opt.graph ? 1 : 0;
   r->P = pl.P;
   TjmParams& P = r->P;
-  auto bail = [&](tjm_status st, const std::string& msg) {
-    free_run(r);
-    return fail(m, st, msg);
-  };
+  auto bail = [&](tjm_status st, const std::string& msg) { return fail(m, st, msg); };
 #define RCHK(expr)                                                                              \
   do {                                                                                          \
     hipError_t e_ = (expr);                                                                     \
@@ -770,20 +761,20 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
       return bail(e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,                      \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                          \
   } while (0)
-
-
-  // ---- worker count --------------------------------------------------------
-  long workers = 1;
-  {
+  if (pool_scratch) {
+    if (pool_stride < P.scratch_stride) return bail(TJM_E_INVAL, "job does not fit the scratch pool");
+    r->workers = pool_workers;
+  } else {
+    long workers = 1;
     tjm_status stw = plan_workers(m, pl, opt, &workers);
-    if (stw != TJM_OK) { free_run(r); return stw; }
+    if (stw != TJM_OK) return stw;
+    size_t freeb = 0, totalb = 0;
+    RCHK(hipMemGetInfo(&freeb, &totalb));
+    const double avail = 0.85 * (double)freeb - pl.per_traj * n_traj;
+    if (avail < (double)P.scratch_stride) return bail(TJM_E_NOMEM, "not enough device memory for the run");
+    workers = std::min<long>(workers, (long)(avail / (double)P.scratch_stride));
+    r->workers = (int)std::max<long>(workers, 1);
   }
-  size_t freeb = 0, totalb = 0;
-  RCHK(hipMemGetInfo(&freeb, &totalb));
-  const double avail = 0.85 * (double)freeb - pl.per_traj * n_traj;
-  if (avail < (double)P.scratch_stride) return bail(TJM_E_NOMEM, "not enough device memory for the run");
-  workers = std::min<long>(workers, (long)(avail / (double)P.scratch_stride));
-  r->workers = (int)std::max<long>(workers, 1);
   // ---- uploads ---------------------------------------------------------------
   // Every copy and zero fill is ordered on the run's stream, ahead of the
   // launches, so runs on other streams of the device are not waited for.
@@ -837,12 +828,50 @@ extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double 
   }
   RCHK(dalloc(r, (size_t)n_traj * TJM_NSTAT * 8, &p)); P.tstats = (unsigned long long*)p; r->d_stats = P.tstats;
   RCHK(dalloc(r, (size_t)n_traj * 4, &p)); P.tflags = (int*)p; r->d_flags = P.tflags;
-  RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
+  if (pool_scratch) {
+    P.scratch = pool_scratch;
+    P.scratch_stride = pool_stride;
+  } else {
+    RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
+  }
   RCHK(dalloc(r, 256, &p)); P.counter = (int*)p;
 
   // the host tables of the plan must outlive their copies
   RCHK(hipStreamSynchronize(r->stream));
 
+  return TJM_OK;
+#undef RCHK
+}
+
+extern "C" tjm_status tjm_run_begin(tjm_model* m, int n_traj, double dt, double T, int chi_max,
+                                    int n_obs, const int* obs_site, const double* obs_op,
+                                    uint64_t seed, const tjm_options* opt_in) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  if (m->run) return fail(m, TJM_E_BUSY, "a run is already in progress on this model");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  Plan pl;
+  tjm_status st0 = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt, pl);
+  if (st0 != TJM_OK) return st0;
+  if ((st0 = select_device(m, opt)) != TJM_OK) return st0;
+  Run* r = new Run();
+  if ((st0 = alloc_run(m, pl, opt, n_traj, r, nullptr, 0, 0)) != TJM_OK) {
+    free_run(r);
+    return st0;
+  }
+  TjmParams& P = r->P;
+  auto bail = [&](tjm_status st, const std::string& msg) {
+    free_run(r);
+    return fail(m, st, msg);
+  };
+#define RCHK(expr)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return bail(e_ == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,                      \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
   // ---- F_0 ------------------------------------------------------------------
   RCHK(tjm_launch_reset(P.counter, r->stream));
   RCHK(hipEventRecord(r->ev0, r->stream));
@@ -1043,6 +1072,75 @@ extern "C" tjm_status tjm_run(tjm_model* m, int n_traj, double dt, double T, int
                         nullptr, nullptr, nullptr);
 }
 
+// ---- jobs of the pooled server ---------------------------------------------
+// A job runs whole trajectories in the server's resident kernel; its workers'
+// scratch is the server's pool, so it holds only its own tables, MPSs and
+// outputs.
+
+tjm_status tjm_pool_plan(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                         const int* obs_site, const double* obs_op, const tjm_options* opt_in, long* stride,
+                         size_t* bytes) {
+  if (!m) return fail(nullptr, TJM_E_INVAL, "model is NULL");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  Plan pl;
+  tjm_status st = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, 0, opt, pl);
+  if (st != TJM_OK) return st;
+  if (opt.graph) return fail(m, TJM_E_INVAL, "graph capture does not apply to server jobs");
+  double b = vec_bytes(pl.ents) + vec_bytes(pl.mixL_ptr) + vec_bytes(pl.mixR_ptr) + vec_bytes(pl.mix2_ptr) +
+             vec_bytes(pl.sptr1) + vec_bytes(pl.schan1) + vec_bytes(pl.sn1) + vec_bytes(pl.sloc1) +
+             vec_bytes(pl.sptr2) + vec_bytes(pl.schan2) + vec_bytes(pl.sn2) + vec_bytes(pl.sloc2) +
+             vec_bytes(pl.env_st) + vec_bytes(pl.env_en) + vec_bytes(pl.lr_chan) + vec_bytes(pl.lr_n) +
+             vec_bytes(pl.Dh) + vec_bytes(pl.Df) + vec_bytes(pl.jopd) + vec_bytes(m->jrate) +
+             vec_bytes(m->jsite) + vec_bytes(pl.jptr) + vec_bytes(pl.jidx) + vec_bytes(pl.optr) +
+             vec_bytes(pl.oidx) + vec_bytes(pl.obsd) + vec_bytes(pl.initd) + vec_bytes(pl.init_t) +
+             vec_bytes(m->init_bond) + vec_bytes(pl.soff) + vec_bytes(pl.bcap) + vec_bytes(m->mpoD) +
+             vec_bytes(pl.oD) + vec_bytes(pl.omix_ptr);
+  b += pl.per_traj * n_traj + 256;
+  b += 2.0 * 8 * (pl.n + 1) * std::max(pl.P.n_obs, 1);
+  b += 64.0 * 1024 * 64;
+  *stride = pl.P.scratch_stride;
+  *bytes = (size_t)b;
+  return TJM_OK;
+}
+
+tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                            const int* obs_site, const double* obs_op, uint64_t seed, const tjm_options* opt_in,
+                            char* scratch, long stride, int workers, void** job, TjmParams* Pout) {
+  if (!m || !job || !Pout || !scratch) return fail(m, TJM_E_INVAL, "NULL argument");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  Plan pl;
+  tjm_status st = plan_run(m, n_traj, dt, T, chi_max, n_obs, obs_site, obs_op, seed, opt, pl);
+  if (st != TJM_OK) return st;
+  if ((st = select_device(m, opt)) != TJM_OK) return st;
+  Run* r = new Run();
+  if ((st = alloc_run(m, pl, opt, n_traj, r, scratch, stride, workers)) != TJM_OK) {
+    free_run(r);
+    return st;
+  }
+  const hipError_t e = hipStreamSynchronize(r->stream);   // tables uploaded, outputs zeroed
+  if (e != hipSuccess) {
+    free_run(r);
+    return fail(m, TJM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  }
+  *job = r;
+  *Pout = r->P;
+  return TJM_OK;
+}
+
+tjm_status tjm_pool_finish(tjm_model* m, void* job, double* mean, double* sem, tjm_stats* stats) {
+  Run* r = (Run*)job;
+  if (!m || !r) return fail(m, TJM_E_INVAL, "NULL argument");
+  r->steps_done = r->n_steps;              // every trajectory ran all its steps in the pool kernel
+  m->run = r;
+  const tjm_status st = tjm_run_end(m, mean, sem, nullptr, nullptr, nullptr);
+  if (stats) *stats = m->last;
+  return st;
+}
+
 extern "C" const char* tjm_last_error(const tjm_model* m) {
   return m ? m->err.c_str() : g_create_err.c_str();
 }
@@ -1065,6 +1163,12 @@ tjm_model* tjm_model_copy(const tjm_model* m) {
 
 int tjm_model_d(const tjm_model* m) { return m ? m->d : 0; }
 int tjm_model_n_mpo_obs(const tjm_model* m) { return m ? (int)m->oW.size() : 0; }
+int tjm_model_L(const tjm_model* m) { return m ? m->L : 0; }
+int tjm_model_Dmax(const tjm_model* m) {
+  return m && !m->mpoD.empty() ? *std::max_element(m->mpoD.begin(), m->mpoD.end()) : 0;
+}
+tjm_status tjm_model_fail(tjm_model* m, tjm_status st, const char* msg) { return fail(m, st, msg); }
+int tjm_model_busy(const tjm_model* m) { return m && m->run ? 1 : 0; }
 
 extern "C" void tjm_destroy(tjm_model* m) {
   if (!m) return;

@@ -43,10 +43,33 @@ tjm_status tjm_fail_global(tjm_status st, const char* msg);
 // A deep copy of a model's inputs (no run state); NULL if out of memory.
 tjm_model* tjm_model_copy(const tjm_model* m);
 int tjm_model_d(const tjm_model* m);
+int tjm_model_L(const tjm_model* m);
 int tjm_model_n_mpo_obs(const tjm_model* m);   // MPO observables registered (output columns after n_obs)
+int tjm_model_Dmax(const tjm_model* m);        // largest MPO bond dimension
+// Records msg as the model's last error and returns st.
+tjm_status tjm_model_fail(tjm_model* m, tjm_status st, const char* msg);
+int tjm_model_busy(const tjm_model* m);          // 1: a run is in progress
 // Validates a run as tjm_run_begin does and returns the device memory it
 // would hold and the resident workgroups it would use (opt->workers caps
 // them).  Makes opt->device current.  Errors as tjm_run_begin, message on m.
 tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
                              const int* obs_site, const double* obs_op, const tjm_options* opt,
                              size_t* bytes, int* workers);
+
+// Jobs of the pooled server (tjm_server.cpp), whose trajectories run whole in
+// the resident work-queue kernel with the server's scratch pool.
+// tjm_pool_plan: the scratch stride a job needs and the device bytes it
+// holds besides scratch (validation as tjm_run_begin, no device call).
+tjm_status tjm_pool_plan(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                         const int* obs_site, const double* obs_op, const tjm_options* opt, long* stride,
+                         size_t* bytes);
+// tjm_pool_prepare: allocates and uploads the job (scratch: `workers` slots
+// of `stride` bytes at `scratch`), waits for the uploads, and returns the
+// job handle and its kernel parameters.
+tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
+                            const int* obs_site, const double* obs_op, uint64_t seed, const tjm_options* opt,
+                            char* scratch, long stride, int workers, void** job, TjmParams* P);
+// tjm_pool_finish: once every trajectory has finished, reduces and copies
+// mean and sem, collects the statistics and releases the job.
+tjm_status tjm_pool_finish(tjm_model* m, void* job, double* mean, double* sem, tjm_stats* stats);
+

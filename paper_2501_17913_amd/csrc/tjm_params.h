@@ -22,6 +22,8 @@ struct TjmParams {
   int n_site_obs, n_mpo_obs;         // site observables are columns 0..n_site_obs-1
   int record_bonds;
   int order;                         // 2: Strang-split schedule with sampling layer; 1: first-order splitting
+  int tile_mode;                     // contraction tile choices (bit 0: no wide tiles in H_eff products; bit 1: small
+                                     // products in 16 x 8 wavefront blocks; bit 2: wide tiles in the other products)
   int mixed;                         // 1: complex-FP32 contractions
   int certify;                       // 1: QR moves with a no-truncation certificate in post-jump sweeps
   double dt, krylov_tol, svd_discard, deg_tol;

@@ -1,13 +1,28 @@
 // Serving front end of the TJM library: independent jobs (one whole run
-// each, Sec. "Algorithm") submitted as they arrive and executed on one GPU.
+// each, Sec. "Algorithm") submitted as they arrive and executed on one GPU
+// with continuous batching at the level of trajectories.
 //
-// Trajectories of a job are independent of other jobs, so jobs share the
-// device freely: each admitted job runs on a stream of its own through the
-// same begin/advance/end path as tjm_run.  Admission is first come, first
-// served: the oldest waiting job starts as soon as an executor is free and
-// its device-memory footprint fits in what the budget has left; a younger
-// job never overtakes it.  A job larger than the whole budget is refused at
-// submission.  See include/tjm.h for the contract.
+// Trajectories are independent of each other and of other jobs (Eq.
+// TJMExpVal averages within a job), so the server keeps one resident work
+// queue per contraction precision: a persistent kernel (tjm_serve_kernel)
+// whose workgroups take (job, trajectory) items in arrival order and run
+// each trajectory whole, F_0 to F_n.  Jobs of any chain length, bond
+// dimension and model share that queue: the trajectories of a job admitted
+// while others run are taken as soon as workgroups free up, next to the
+// rest.  Each workgroup's scratch is a slot of its queue's pool.  A job too
+// large for the current pool of its precision opens a new queue with a pool
+// for the larger shape (its own resident kernel); the older queue drains
+// and is released once idle.
+//
+// A dispatcher thread admits jobs first come, first served (the oldest
+// waiting job is admitted once its buffers, and any new pool it needs, fit
+// in what the budget has left; a younger job never overtakes it), appends
+// their items, (re)launches the resident kernel whenever items are pending
+// and it has exited (it exits by itself when idle), and finishes a job
+// (reduction, copies, release) once all of its items are marked done.
+// Results are bit-identical to tjm_run with the same arguments: each
+// trajectory runs the same device code on the same data.  See include/tjm.h
+// for the contract.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,9 +45,15 @@ namespace {
 
 typedef std::chrono::steady_clock Clock;
 
-// executors: concurrent jobs, one HIP stream each (the hardware queues a
-// process gets by default)
-constexpr int kExecutors = 4;
+constexpr int kMaxJobs = 256;          // parameter slots per pool (jobs in flight)
+constexpr int kCap = 1 << 20;          // ring of work items per pool
+// sleeps (about 3.4 us each) an idle workgroup waits for new items before it
+// exits: long enough that the workgroups of a resident kernel stay for the
+// next request of a stream, short enough that an idle kernel soon frees
+// the device
+constexpr int kIdleSpins = 150000;
+
+struct Pool;
 
 struct Job {
   uint64_t id = 0;
@@ -44,7 +65,9 @@ struct Job {
   std::vector<int> obs_site;
   std::vector<double> obs_op;
   tjm_options opt{};
-  size_t bytes = 0;
+  size_t bytes = 0;                    // the job's own device buffers (scratch is the pool's)
+  long stride = 0;                     // scratch one of its workgroups needs
+  int L = 0;
   int n_steps = 0;
   int done = 0;
   int waited = 0;                      // a tjm_wait call has claimed the job
@@ -53,6 +76,33 @@ struct Job {
   std::vector<double> mean, sem;
   tjm_stats stats{};
   Clock::time_point t_submit, t_start, t_done;
+  // while admitted
+  Pool* pool = nullptr;
+  void* run = nullptr;
+  int slot = -1;
+  unsigned first = 0;                  // its items are first .. first + n_traj - 1
+  int seen = 0;                        // items known done
+  size_t pool_bytes = 0;
+};
+
+// The resident queue of one contraction precision.
+struct Pool {
+  int mixed = 0;
+  char* scratch = nullptr;
+  long stride = 0;
+  int workers = 0;
+  int L_max = 0;
+  size_t bytes = 0;                    // scratch bytes held
+  hipStream_t stream = nullptr;
+  TjmParams* d_params = nullptr;       // [kMaxJobs]
+  unsigned* d_head = nullptr;
+  ServeShared* sh = nullptr;           // host-coherent
+  ServeItem* items = nullptr;          // host-coherent [kCap]
+  int* done = nullptr;                 // host-coherent [kCap]
+  unsigned pushed = 0;
+  int active = 0;                      // admitted jobs not yet finished
+  bool retired = false;                // takes no new job; released once drained
+  std::vector<int> free_slots;
 };
 
 thread_local std::string t_err;
@@ -67,47 +117,294 @@ tjm_status sfail(tjm_status st, const std::string& msg) {
 struct tjm_server {
   int device = 0;
   size_t budget = 0;
+  int n_cu = 0;
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv;          // job state changes (waiters)
+  std::condition_variable wake;        // new work for the dispatcher
   std::deque<Job*> queue;              // waiting, oldest first
+  std::vector<Job*> active;            // admitted, not finished
   std::map<uint64_t, Job*> jobs;       // every job not yet collected by tjm_wait
-  size_t active_bytes = 0;
+  size_t active_bytes = 0;             // admitted jobs' buffers plus the pools
   uint64_t next_id = 1;
   bool stop = false;
-  std::vector<std::thread> exec;
+  std::vector<Pool*> pools[2];         // FP64, mixed: queues, the newest last
+  std::thread dispatcher;
 };
 
-static void run_job(Job* j) {
+static hipError_t pool_init(Pool& p, int mixed) {
+  p.mixed = mixed;
+  hipError_t e = hipStreamCreateWithFlags(&p.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_params, sizeof(TjmParams) * kMaxJobs);
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_head, 256);
+  if (e == hipSuccess) e = hipMemset(p.d_head, 0, 256);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p.sh, sizeof(ServeShared), hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p.items, sizeof(ServeItem) * (size_t)kCap, hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p.done, sizeof(int) * (size_t)kCap, hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  std::memset(p.sh, 0, sizeof(ServeShared));
+  std::memset(p.done, 0, sizeof(int) * (size_t)kCap);
+  for (int i = kMaxJobs - 1; i >= 0; --i) p.free_slots.push_back(i);
+  return hipSuccess;
+}
+
+static void pool_free(Pool& p) {
+  if (p.stream) (void)hipStreamSynchronize(p.stream);
+  if (p.scratch) (void)hipFree(p.scratch);
+  if (p.d_params) (void)hipFree(p.d_params);
+  if (p.d_head) (void)hipFree(p.d_head);
+  if (p.sh) (void)hipHostFree(p.sh);
+  if (p.items) (void)hipHostFree(p.items);
+  if (p.done) (void)hipHostFree(p.done);
+  if (p.stream) (void)hipStreamDestroy(p.stream);
+  p = Pool();
+}
+
+static bool pool_running(Pool& p) { return hipStreamQuery(p.stream) == hipErrorNotReady; }
+
+// workgroups of the resident kernel for chains up to L
+static int pool_workers(tjm_server* s, int mixed, int L) {
+  int bpc = 1;
+  if (tjm_blocks_per_cu(mixed, L, &bpc) != hipSuccess || bpc < 1) bpc = 1;
+  return bpc * s->n_cu;
+}
+
+// The shape of a pool that serves the current pool's jobs and j.
+static void pool_shape(const Pool* cur, const Job* j, long* stride, int* L) {
+  *stride = cur ? std::max(cur->stride, j->stride) : j->stride;
+  *L = cur ? std::max(cur->L_max, j->L) : j->L;
+}
+
+static size_t pool_bytes_for(tjm_server* s, int mixed, long stride, int L) {
+  return (size_t)pool_workers(s, mixed, L) * (size_t)stride;
+}
+
+// A new queue with a scratch pool of the given shape; the caller holds the
+// lock and has checked the budget.
+static hipError_t pool_open(tjm_server* s, int mixed, long stride, int L, Pool** out) {
+  Pool* p = new (std::nothrow) Pool();
+  if (!p) return hipErrorOutOfMemory;
+  hipError_t e = pool_init(*p, mixed);
+  const int w = pool_workers(s, mixed, L);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->scratch, (size_t)w * (size_t)stride);
+  if (e != hipSuccess) {
+    pool_free(*p);
+    delete p;
+    return e;
+  }
+  p->stride = stride;
+  p->L_max = L;
+  p->workers = w;
+  p->bytes = (size_t)w * (size_t)stride;
+  s->active_bytes += p->bytes;
+  for (Pool* o : s->pools[mixed]) o->retired = true;
+  s->pools[mixed].push_back(p);
+  *out = p;
+  return hipSuccess;
+}
+
+// the queue new jobs of a precision go to, or null
+static Pool* current_pool(tjm_server* s, int q) {
+  if (s->pools[q].empty() || s->pools[q].back()->retired) return nullptr;
+  return s->pools[q].back();
+}
+
+static void release_slot(tjm_server* s, Job* j) {
+  j->pool->free_slots.push_back(j->slot);
+  j->pool->active--;
+  s->active_bytes -= j->bytes;
+}
+
+static void mark_done(tjm_server* s, Job* j) {
+  j->t_done = Clock::now();
+  j->done = 1;
+  s->cv.notify_all();
+}
+
+static void finish_job(tjm_server* s, Job* j, std::unique_lock<std::mutex>& lk) {
   const long entries = (long)(j->n_steps + 1) * j->n_out;
   j->mean.assign(std::max<long>(entries, 1), 0.0);
   j->sem.assign(std::max<long>(entries, 1), 0.0);
-  j->status = tjm_run(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
-                      j->obs_site.empty() ? nullptr : j->obs_site.data(),
-                      j->obs_op.empty() ? nullptr : j->obs_op.data(), j->seed, &j->opt,
-                      j->mean.data(), j->sem.data());
-  if (j->status != TJM_OK) j->err = tjm_last_error(j->model);
-  tjm_get_stats(j->model, &j->stats);
+  void* run = j->run;
+  lk.unlock();
+  const tjm_status st = tjm_pool_finish(j->model, run, j->mean.data(), j->sem.data(), &j->stats);
+  lk.lock();
+  j->status = st;
+  if (st != TJM_OK) j->err = tjm_last_error(j->model);
+  j->run = nullptr;
+  release_slot(s, j);
+  mark_done(s, j);
 }
 
-static void executor(tjm_server* s) {
+// Whether n more items fit in the pool's ring: the new indices must not
+// reach the oldest item whose completion has not been observed yet.
+static bool ring_has_room(tjm_server* s, const Pool& p, int n) {
+  unsigned in_flight = 0;              // items from the oldest unobserved one on (wrap-safe differences)
+  for (const Job* j : s->active)
+    if (j->pool == &p) in_flight = std::max(in_flight, p.pushed - (j->first + (unsigned)j->seen));
+  return (unsigned long long)in_flight + (unsigned)n <= (unsigned long long)kCap;
+}
+
+// Admits the oldest waiting job if it fits; returns false if it must wait.
+static bool admit_front(tjm_server* s, std::unique_lock<std::mutex>& lk) {
+  Job* j = s->queue.front();
+  const int q = j->opt.precision == TJM_PREC_MIXED ? 1 : 0;
+  Pool* cur = current_pool(s, q);
+  const bool fits = cur && j->stride <= cur->stride && j->L <= cur->L_max && !cur->free_slots.empty();
+  if (fits && !ring_has_room(s, *cur, j->n_traj)) return false;   // waits for earlier items to finish
+  long stride = 0;
+  int Lp = 0;
+  pool_shape(cur, j, &stride, &Lp);
+  const size_t extra = fits ? 0 : pool_bytes_for(s, q, stride, Lp);
+  if (s->active_bytes + j->bytes + extra > s->budget) {
+    // no room: idle queues of either precision give up their pools (they are
+    // released once their kernels have exited), and the job waits
+    if (!fits)
+      for (int r = 0; r < 2; ++r)
+        for (Pool* o : s->pools[r])
+          if (o->active == 0) o->retired = true;
+    return false;
+  }
+  s->queue.pop_front();
+  j->t_start = Clock::now();
+  if (!fits) {
+    const hipError_t e = pool_open(s, q, stride, Lp, &cur);
+    if (e != hipSuccess) {
+      j->status = e == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE;
+      j->err = std::string("scratch pool: ") + hipGetErrorString(e);
+      mark_done(s, j);
+      return true;
+    }
+  }
+  Pool& p = *cur;
+  j->pool = &p;
+  j->slot = p.free_slots.back();
+  p.free_slots.pop_back();
+  p.active++;
+  s->active_bytes += j->bytes;
+  j->pool_bytes = p.bytes;
+  char* scratch = p.scratch;
+  const long pstride = p.stride;
+  const int workers = p.workers;
+  lk.unlock();
+  void* run = nullptr;
+  TjmParams P;
+  std::string err;
+  tjm_status st = tjm_pool_prepare(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
+                                   j->obs_site.empty() ? nullptr : j->obs_site.data(),
+                                   j->obs_op.empty() ? nullptr : j->obs_op.data(), j->seed, &j->opt, scratch,
+                                   pstride, workers, &run, &P);
+  if (st != TJM_OK) {
+    err = tjm_last_error(j->model);
+  } else {
+    const hipError_t e = hipMemcpy(p.d_params + j->slot, &P, sizeof(P), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      st = TJM_E_DEVICE;
+      err = std::string("parameter upload: ") + hipGetErrorString(e);
+      (void)tjm_pool_finish(j->model, run, nullptr, nullptr, nullptr);   // releases the job's buffers
+      run = nullptr;
+    }
+  }
+  lk.lock();
+  if (st != TJM_OK) {
+    j->status = st;
+    j->err = err;
+    release_slot(s, j);
+    mark_done(s, j);
+    return true;
+  }
+  j->run = run;
+  // append the job's trajectories to the ring, then publish them
+  j->first = p.pushed;
+  for (int t = 0; t < j->n_traj; ++t) {
+    const unsigned idx = p.pushed + (unsigned)t;
+    p.done[idx % kCap] = 0;
+    p.items[idx % kCap] = ServeItem{j->slot, t};
+  }
+  p.pushed += (unsigned)j->n_traj;
+  __atomic_store_n(&p.sh->tail, p.pushed, __ATOMIC_RELEASE);
+  s->active.push_back(j);
+  return true;
+}
+
+// Launches the resident kernel of a pool whose admitted jobs have items
+// left and whose previous kernel has exited; on a launch error every job
+// of the pool fails.
+static void keep_resident(tjm_server* s, Pool& p, std::unique_lock<std::mutex>& lk) {
+  if (!p.stream || p.active == 0 || pool_running(p)) return;
+  bool pending = false;
+  for (Job* j : s->active)
+    if (j->pool == &p && j->seen < j->n_traj) { pending = true; break; }
+  if (!pending) return;
+  ServeDev S;
+  S.params = p.d_params; S.items = p.items; S.done = p.done; S.sh = p.sh; S.head = p.d_head;
+  S.cap = kCap; S.idle_spins = kIdleSpins;
+  const hipError_t e = p.mixed ? tjm_launch_serve_float(S, p.workers, p.L_max, p.stream)
+                               : tjm_launch_serve_double(S, p.workers, p.L_max, p.stream);
+  if (e == hipSuccess) return;
+  for (size_t i = 0; i < s->active.size();) {
+    Job* j = s->active[i];
+    if (j->pool != &p) { ++i; continue; }
+    s->active.erase(s->active.begin() + (long)i);
+    void* run = j->run;
+    j->run = nullptr;
+    lk.unlock();
+    (void)tjm_pool_finish(j->model, run, nullptr, nullptr, nullptr);
+    lk.lock();
+    j->status = TJM_E_DEVICE;
+    j->err = std::string("serve kernel launch: ") + hipGetErrorString(e);
+    release_slot(s, j);
+    mark_done(s, j);
+  }
+}
+
+static void dispatcher(tjm_server* s) {
+  (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    s->cv.wait(lk, [s] {
-      return s->stop || (!s->queue.empty() && s->active_bytes + s->queue.front()->bytes <= s->budget);
-    });
-    if (s->stop) return;
-    Job* j = s->queue.front();
-    s->queue.pop_front();
-    s->active_bytes += j->bytes;
-    j->t_start = Clock::now();
-    lk.unlock();
-    run_job(j);
-    lk.lock();
-    j->t_done = Clock::now();
-    j->done = 1;
-    s->active_bytes -= j->bytes;
-    s->cv.notify_all();
+    // admission, first come first served
+    while (!s->queue.empty() && !s->stop)
+      if (!admit_front(s, lk)) break;
+    // finished jobs: every item of the job marked done by the kernel
+    for (size_t i = 0; i < s->active.size();) {
+      Job* j = s->active[i];
+      const Pool& p = *j->pool;
+      while (j->seen < j->n_traj &&
+             __atomic_load_n(&p.done[(j->first + (unsigned)j->seen) % kCap], __ATOMIC_ACQUIRE))
+        ++j->seen;
+      if (j->seen == j->n_traj) {
+        s->active.erase(s->active.begin() + (long)i);
+        finish_job(s, j, lk);
+      } else {
+        ++i;
+      }
+    }
+    // a resident kernel wherever items are pending (it exits when idle);
+    // retired queues are released once drained and their kernel has exited
+    for (int q = 0; q < 2; ++q)
+      for (size_t i = 0; i < s->pools[q].size();) {
+        Pool* p = s->pools[q][i];
+        keep_resident(s, *p, lk);
+        if (p->retired && p->active == 0) {
+          __atomic_store_n(&p->sh->stop, 1, __ATOMIC_RELEASE);
+          if (!pool_running(*p)) {
+            s->active_bytes -= p->bytes;
+            pool_free(*p);
+            delete p;
+            s->pools[q].erase(s->pools[q].begin() + (long)i);
+            continue;
+          }
+        }
+        ++i;
+      }
+    if (s->stop && s->active.empty()) break;
+    s->wake.wait_for(lk, std::chrono::microseconds(500));
   }
+  lk.unlock();
+  for (int q = 0; q < 2; ++q)
+    for (Pool* p : s->pools[q]) {
+      __atomic_store_n(&p->sh->stop, 1, __ATOMIC_RELEASE);
+      (void)hipStreamSynchronize(p->stream);
+    }
 }
 
 extern "C" tjm_status tjm_server_create(tjm_server** out, int device, size_t hbm_budget_bytes) {
@@ -119,25 +416,29 @@ extern "C" tjm_status tjm_server_create(tjm_server** out, int device, size_t hbm
   int prev = 0;
   (void)hipGetDevice(&prev);
   size_t freeb = 0, totalb = 0;
+  hipDeviceProp_t prop;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMemGetInfo(&freeb, &totalb);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+  tjm_server* s = nullptr;
+  if (e == hipSuccess) {
+    s = new (std::nothrow) tjm_server();
+    if (!s) e = hipErrorOutOfMemory;
+  }
   (void)hipSetDevice(prev);
-  if (e != hipSuccess) return sfail(TJM_E_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
-  tjm_server* s = new (std::nothrow) tjm_server();
-  if (!s) return sfail(TJM_E_NOMEM, "host allocation failed");
+  if (e != hipSuccess) {
+    delete s;
+    return sfail(e == hipErrorOutOfMemory ? TJM_E_NOMEM : TJM_E_DEVICE,
+                 std::string("server set-up: ") + hipGetErrorString(e));
+  }
   s->device = device;
+  s->n_cu = prop.multiProcessorCount;
   s->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (size_t)(0.85 * (double)freeb);
   try {
-    for (int i = 0; i < kExecutors; ++i) s->exec.emplace_back(executor, s);
+    s->dispatcher = std::thread(dispatcher, s);
   } catch (...) {
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      s->stop = true;
-    }
-    s->cv.notify_all();
-    for (auto& t : s->exec) t.join();
     delete s;
-    return sfail(TJM_E_NOMEM, "could not start executor threads");
+    return sfail(TJM_E_NOMEM, "could not start the dispatcher thread");
   }
   *out = s;
   return TJM_OK;
@@ -158,6 +459,7 @@ extern "C" tjm_status tjm_submit(tjm_server* s, const tjm_model* m, const tjm_ru
   const int d = tjm_model_d(m);
   j->n_traj = a->n_traj; j->dt = a->dt; j->T = a->T; j->chi_max = a->chi_max; j->n_obs = a->n_obs;
   j->n_out = a->n_obs + tjm_model_n_mpo_obs(j->model);
+  j->L = tjm_model_L(j->model);
   j->seed = a->seed;
   try {
     if (a->n_obs > 0) {
@@ -172,30 +474,32 @@ extern "C" tjm_status tjm_submit(tjm_server* s, const tjm_model* m, const tjm_ru
   tjm_default_options(&j->opt);
   if (a->opt) j->opt = *a->opt;
   j->opt.device = s->device;
-  // size the job with the checks of a run; the caller's current device is kept
-  int prev = 0;
-  (void)hipGetDevice(&prev);
-  int workers = 1;
-  tjm_status st = tjm_run_footprint(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
-                                    j->obs_site.empty() ? nullptr : j->obs_site.data(),
-                                    j->obs_op.empty() ? nullptr : j->obs_op.data(), &j->opt, &j->bytes,
-                                    &workers);
-  (void)hipSetDevice(prev);
+  j->opt.workers = 0;
+  // validate and size the job with the checks of a run (no device call)
+  tjm_status st = tjm_pool_plan(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
+                                j->obs_site.empty() ? nullptr : j->obs_site.data(),
+                                j->obs_op.empty() ? nullptr : j->obs_op.data(), &j->opt, &j->stride, &j->bytes);
   if (st != TJM_OK) {
     std::string msg = tjm_last_error(j->model);
     tjm_destroy(j->model);
     delete j;
     return sfail(st, msg);
   }
-  if (j->bytes > s->budget) {
+  j->n_steps = (int)std::lround(j->T / j->dt);
+  if (j->n_traj > kCap) {
     tjm_destroy(j->model);
     delete j;
-    return sfail(TJM_E_NOMEM, "job needs more device memory than the server's budget");
+    return sfail(TJM_E_UNSUPPORTED, "more trajectories than the server's work ring holds (1048576)");
   }
-  j->opt.workers = workers;      // the footprint above assumed at most this many
-  j->n_steps = (int)std::lround(j->T / j->dt);
   {
     std::lock_guard<std::mutex> g(s->mu);
+    // a job that could not run even alone next to the other precision's pool
+    const int q = j->opt.precision == TJM_PREC_MIXED ? 1 : 0;
+    if (j->bytes + pool_bytes_for(s, q, j->stride, j->L) > s->budget) {
+      tjm_destroy(j->model);
+      delete j;
+      return sfail(TJM_E_NOMEM, "job needs more device memory than the server's budget");
+    }
     if (s->stop) {
       tjm_destroy(j->model);
       delete j;
@@ -207,7 +511,7 @@ extern "C" tjm_status tjm_submit(tjm_server* s, const tjm_model* m, const tjm_ru
     s->queue.push_back(j);
     *job = j->id;
   }
-  s->cv.notify_all();
+  s->wake.notify_all();
   return TJM_OK;
 }
 
@@ -249,6 +553,7 @@ extern "C" tjm_status tjm_wait(tjm_server* s, uint64_t job, double* mean, double
     rep->n_traj = j->n_traj;
     rep->n_steps = j->n_steps;
     rep->device_bytes = j->bytes;
+    rep->pool_bytes = j->pool_bytes;
     rep->stats = j->stats;
   }
   const tjm_status st = j->status;
@@ -265,9 +570,19 @@ extern "C" void tjm_server_destroy(tjm_server* s) {
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
+    s->queue.clear();                  // never admitted: released with the server below
   }
-  s->cv.notify_all();
-  for (auto& t : s->exec) t.join();
+  s->wake.notify_all();
+  if (s->dispatcher.joinable()) s->dispatcher.join();   // admitted jobs finish first
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(s->device);
+  for (int q = 0; q < 2; ++q)
+    for (Pool* p : s->pools[q]) {
+      pool_free(*p);
+      delete p;
+    }
+  (void)hipSetDevice(prev);
   for (auto& kv : s->jobs) {
     tjm_destroy(kv.second->model);
     delete kv.second;

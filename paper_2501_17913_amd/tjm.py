@@ -23,7 +23,8 @@ EXPORTED = [
     "tjm_default_options", "tjm_create", "tjm_set_initial_product", "tjm_set_initial_mps",
     "tjm_add_mpo_observable", "tjm_clear_mpo_observables", "tjm_run",
     "tjm_run_traces",
-    "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_run_read", "tjm_get_stats", "tjm_last_error",
+    "tjm_run_begin", "tjm_run_advance", "tjm_run_end", "tjm_run_read", "tjm_get_stats", "tjm_autotune",
+    "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd", "tjm_svd_noalloc",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
     "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_wait", "tjm_server_last_error",
@@ -36,7 +37,8 @@ class Options(C.Structure):
                 ("krylov_max", C.c_int), ("krylov_tol", C.c_double), ("deg_tol", C.c_double),
                 ("workers", C.c_int), ("record_bonds", C.c_int), ("traj_base", C.c_uint32),
                 ("device", C.c_int), ("certify_sweeps", C.c_int), ("sweep_jumps", C.c_int),
-                ("generic_heff", C.c_int), ("graph", C.c_int), ("trotter_order", C.c_int)]
+                ("generic_heff", C.c_int), ("graph", C.c_int), ("trotter_order", C.c_int),
+                ("tile_mode", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -58,6 +60,17 @@ class Stats(C.Structure):
         return d
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("cached", C.c_int), ("trials", C.c_int), ("trial_traj", C.c_int), ("tile_mode", C.c_int),
+                ("workers", C.c_int), ("cache_written", C.c_int), ("us_per_traj_step", C.c_double),
+                ("default_us_per_traj_step", C.c_double), ("key", C.c_char * 192)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["key"] = self.key.decode()
+        return d
+
+
 class RunArgs(C.Structure):
     _fields_ = [("n_traj", C.c_int), ("dt", C.c_double), ("T", C.c_double), ("chi_max", C.c_int),
                 ("n_obs", C.c_int), ("obs_site", C.POINTER(C.c_int)), ("obs_op", C.POINTER(C.c_double)),
@@ -67,7 +80,7 @@ class RunArgs(C.Structure):
 class JobReport(C.Structure):
     _fields_ = [("latency_s", C.c_double), ("queue_s", C.c_double), ("run_s", C.c_double),
                 ("start_s", C.c_double), ("end_s", C.c_double), ("n_traj", C.c_int), ("n_steps", C.c_int), ("device_bytes", C.c_size_t),
-                ("stats", Stats)]
+                ("stats", Stats), ("pool_bytes", C.c_size_t)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stats"}
@@ -108,6 +121,11 @@ lib.tjm_run_read.argtypes = [_vp, _dp, _ip, _ip]
 lib.tjm_run_read.restype = C.c_int
 lib.tjm_get_stats.argtypes = [_vp, C.POINTER(Stats)]
 lib.tjm_get_stats.restype = C.c_int
+TuneProgress = C.CFUNCTYPE(None, C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p)
+lib.tjm_autotune.argtypes = [_vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, C.c_uint64,
+                             C.POINTER(Options), C.c_int, C.c_int, C.c_char_p, TuneProgress, C.c_void_p,
+                             C.POINTER(Options), C.POINTER(TuneReport)]
+lib.tjm_autotune.restype = C.c_int
 lib.tjm_last_error.argtypes = [_vp]
 lib.tjm_last_error.restype = C.c_char_p
 lib.tjm_destroy.argtypes = [_vp]
@@ -305,6 +323,22 @@ class Model:
         bl = np.zeros((nt, n, self.L + 1), dtype=np.int32) if self._rec else None
         self._check(lib.tjm_run_read(self.h, _dptr(per), _iptr(jl), _iptr(bl)))
         return {"per_traj": per, "jumps": jl, "bonds": bl}
+
+    def autotune(self, n_traj, dt, T, chi_max, observables, seed, options=None, warm_steps=3, timed_steps=2,
+                 cache_path=None, progress=None):
+        """tjm_autotune: (tuned Options, report dict) for this run.  progress,
+        if given, is called as progress(trial, tile_mode, workers, us) after
+        each trial."""
+        sites, ops = self._obs(observables)
+        tuned = Options()
+        rep = TuneReport()
+        base = C.byref(options) if options is not None else None
+        cp = cache_path.encode() if cache_path else None
+        cb = TuneProgress((lambda i, tm, w, us, _ctx: progress(i, tm, w, us)) if progress else 0)
+        self._check(lib.tjm_autotune(self.h, n_traj, dt, T, chi_max, len(observables), _iptr(sites), _dptr(ops),
+                                     seed, base, int(warm_steps), int(timed_steps), cp, cb, None,
+                                     C.byref(tuned), C.byref(rep)))
+        return tuned, rep.as_dict()
 
     def stats(self):
         s = Stats()

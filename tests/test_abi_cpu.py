@@ -143,7 +143,8 @@ def test_initial_mps_validation():
     (dict(chi_max=0), tjm.E_INVAL), (dict(obs_site=9), tjm.E_INVAL),
     (dict(opt=dict(chi_cap=128)), tjm.E_UNSUPPORTED), (dict(opt=dict(krylov_max=40)), tjm.E_INVAL),
     (dict(opt=dict(precision=7)), tjm.E_INVAL), (dict(opt=dict(sweep_jumps=0)), tjm.E_UNSUPPORTED),
-    (dict(opt=dict(trotter_order=3)), tjm.E_INVAL), (dict(opt=dict(trotter_order=0)), tjm.E_INVAL)])
+    (dict(opt=dict(trotter_order=3)), tjm.E_INVAL), (dict(opt=dict(trotter_order=0)), tjm.E_INVAL),
+    (dict(opt=dict(tile_mode=8)), tjm.E_INVAL), (dict(opt=dict(tile_mode=-1)), tjm.E_INVAL)])
 def test_run_rejects_bad_arguments_before_touching_the_device(kw, expect):
     m = _model()
     args = dict(n_traj=4, dt=0.1, T=0.3, chi_max=4, obs_site=0)
@@ -153,6 +154,20 @@ def test_run_rejects_bad_arguments_before_touching_the_device(kw, expect):
     with pytest.raises(tjm.TjmError) as e:
         m.run(args["n_traj"], args["dt"], args["T"], args["chi_max"], obs, 1, opt)
     assert e.value.status == expect
+
+
+@pytest.mark.parametrize("kw", [dict(warm_steps=2, timed_steps=2), dict(warm_steps=-1), dict(timed_steps=0),
+                                dict(n_traj=0), dict(chi_max=0), dict(opt=dict(tile_mode=9))])
+def test_autotune_rejects_bad_arguments_before_touching_the_device(kw):
+    # a 3-step run (T = 0.3): warm_steps + timed_steps must stay within it
+    m = _model()
+    args = dict(n_traj=4, chi_max=4, warm_steps=1, timed_steps=1)
+    args.update({k: v for k, v in kw.items() if k != "opt"})
+    opt = tjm.default_options(**kw.get("opt", {}))
+    with pytest.raises(tjm.TjmError) as e:
+        m.autotune(args["n_traj"], 0.1, 0.3, args["chi_max"], [(0, models.PAULI_Z)], 1, opt,
+                   warm_steps=args["warm_steps"], timed_steps=args["timed_steps"])
+    assert e.value.status == tjm.E_INVAL
 
 
 def test_session_calls_out_of_order_are_busy():

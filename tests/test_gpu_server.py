@@ -99,12 +99,15 @@ def test_server_small_fp64_job_matches_oracle():
 
 def test_server_budget_admits_one_job_at_a_time():
     jobs = JOBS[:3]
-    sizes = []
+    sizes, pools = [], {}
     srv = tjm.Server(0)
-    for job in jobs:       # learn each job's footprint from a first pass
-        sizes.append(srv.wait(_submit_all(srv, [job])[0])["report"]["device_bytes"])
+    for job in jobs:       # learn each job's buffers and its precision's pool from a first pass
+        rep = srv.wait(_submit_all(srv, [job])[0])["report"]
+        sizes.append(rep["device_bytes"])
+        pools[job[6]] = max(pools.get(job[6], 0), rep["pool_bytes"])
     srv.close()
-    budget = max(sizes) + min(sizes) // 2      # never room for two jobs at once
+    # the pools, plus never room for the buffers of two jobs at once
+    budget = sum(pools.values()) + max(sizes) + min(sizes) // 2
     srv = tjm.Server(0, budget)
     ids = _submit_all(srv, jobs)
     reps = [srv.wait(j) for j in ids]
@@ -132,6 +135,9 @@ def test_server_rejects_bad_jobs_and_reports_failures():
     with pytest.raises(tjm.TjmError) as e:
         srv.submit(m, 4, 0.1, 0.2, 8, models.zx_observables(6), 1, tjm.default_options(chi_cap=128))
     assert e.value.status == tjm.E_UNSUPPORTED
+    with pytest.raises(tjm.TjmError) as e:     # more trajectories than the work ring holds
+        srv.submit(m, (1 << 20) + 1, 0.1, 0.2, 8, models.zx_observables(6), 1)
+    assert e.value.status == tjm.E_UNSUPPORTED
     with pytest.raises(tjm.TjmError) as e:
         srv.wait(12345)
     assert e.value.status == tjm.E_INVAL
@@ -144,3 +150,28 @@ def test_server_rejects_bad_jobs_and_reports_failures():
         srv.submit(m, 64, 0.1, 0.3, 8, models.zx_observables(6), 2)
     srv.close()
     m.close()
+
+
+def test_server_admits_trajectories_of_new_jobs_while_others_run():
+    # continuous batching: a long job fills the resident work queue; jobs of
+    # other chain lengths and bond dimensions that arrive while it runs start
+    # before it ends and share its kernel; each equals its own direct run
+    long_job = (24, 32, 1500, 6, 0.5, 0.1, tjm.PREC_MIXED, inputs.SEED + 91)
+    short_jobs = [(7, 8, 48, 4, 0.4, 0.1, tjm.PREC_MIXED, inputs.SEED + 92),
+                  (16, 16, 96, 3, 0.6, 0.05, tjm.PREC_MIXED, inputs.SEED + 93)]
+    srv = tjm.Server(0)
+    first = _submit_all(srv, [long_job])[0]
+    while srv.poll(first):
+        pass
+    import time
+    time.sleep(0.2)
+    later = _submit_all(srv, short_jobs)
+    reps = [srv.wait(j) for j in later]
+    lrep = srv.wait(first)
+    srv.close()
+    for job, r in zip(short_jobs, reps):
+        log("short job", job[:4], "start %.3f end %.3f (long job ends %.3f)"
+            % (r["report"]["start_s"], r["report"]["end_s"], lrep["report"]["end_s"]))
+        assert r["report"]["start_s"] < lrep["report"]["end_s"]
+        assert np.array_equal(r["mean"], _direct(job)["mean"])
+    assert np.array_equal(lrep["mean"], _direct(long_job)["mean"])
