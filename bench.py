@@ -37,9 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "C2": dict(L=40, chi_max=32, n_traj=1024, T=5.0),
-    "C3": dict(L=100, chi_max=64, n_traj=4096, T=5.0),
-    "C4": dict(L=1000, chi_max=16, n_traj=512, T=2.0),
+    "C2": dict(L=40, chi_max=32, n_traj=1024, T=5.0, init="neel"),
+    "C3": dict(L=100, chi_max=64, n_traj=4096, T=5.0, init="neel"),
+    "C4": dict(L=1000, chi_max=16, n_traj=512, T=2.0, init="zero"),
 }
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
 SEED = 0x250117913
@@ -185,19 +185,20 @@ def copy_calibration(tjm, n_bytes=1 << 30, reps=5):
     return {"copy_bytes": n_bytes, "reps": reps, "avg_ms": ms, "GB/s": 2 * n_bytes / (ms * 1e-3) / 1e9}
 
 
-def xxx_job(tjm, models, L):
-    """The XXX chain of the workloads (J=1, g=0.5, gamma=0.1), Neel start."""
+def xxx_job(tjm, models, L, init):
+    """The XXX chain of the workloads (J=1, g=0.5, gamma=0.1) from the Neel
+    state or |0...0>."""
     mpo, s, o, r = models.xxx_model(L, 1.0, 0.5, 0.1)
     m = tjm.Model(L, mpo, s, o, r)
-    m.set_initial_product(models.neel(L))
+    m.set_initial_product(models.neel(L) if init == "neel" else models.product_state([0] * L))
     return m
 
 
-def autotune(tjm, models, L, chi, N, T, prec, warm, timed, cache):
+def autotune(tjm, models, L, init, chi, N, T, prec, warm, timed, cache):
     """tjm_autotune for the workload: (tile_mode, workers, report)."""
     if cache:
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
-    m = xxx_job(tjm, models, L)
+    m = xxx_job(tjm, models, L, init)
     t0 = time.perf_counter()
     def progress(i, tm, w, us):
         print("  autotune trial %d: tile_mode %d workers %d: %.1f us per trajectory-step (%.1fs)"
@@ -213,19 +214,22 @@ def autotune(tjm, models, L, chi, N, T, prec, warm, timed, cache):
     return tuned.tile_mode, tuned.workers, rep
 
 
-def measure(tjm, models, L, chi, N, T, prec, warmup, K, workers, read_ids=0, deadline=None, tile_mode=0):
+def measure(tjm, models, L, init, chi, N, T, prec, warmup, K, workers, read_ids=0, deadline=None, tile_mode=0):
     """Run one job on the GPU; time steps warmup+1 .. warmup+K.  With
     read_ids, the records of trajectories 0..read_ids-1 after the window are
     returned too.  With a deadline (perf_counter seconds), the job stops
     early once it is passed and the result says so (partial)."""
     dt = 0.1
-    m = xxx_job(tjm, models, L)
+    m = xxx_job(tjm, models, L, init)
     opt = tjm.default_options(precision=prec, workers=workers, tile_mode=tile_mode)
     name = "mixed" if prec == tjm.PREC_MIXED else "fp64"
+    tb = time.perf_counter()
     m.begin(N, dt, T, chi, models.zx_observables(L), SEED, opt)
+    print("  %s F_0 done at %.1fs" % (name, time.perf_counter() - tb), file=sys.stderr, flush=True)
     for k in range(warmup):
         m.advance(1)
-        print("  %s warmup step %d of %d done" % (name, k + 1, warmup), file=sys.stderr, flush=True)
+        print("  %s warmup step %d of %d done at %.1fs" % (name, k + 1, warmup, time.perf_counter() - tb),
+              file=sys.stderr, flush=True)
         if deadline and time.perf_counter() > deadline:
             m.close()
             return {"partial": True, "steps_done": k + 1}
@@ -377,7 +381,7 @@ def main():
     w = dict(WORKLOADS[args.workload])
     if args.n_traj:
         w["n_traj"] = args.n_traj
-    L, chi, N, T = w["L"], w["chi_max"], w["n_traj"], w["T"]
+    L, chi, N, T, init = w["L"], w["chi_max"], w["n_traj"], w["T"], w["init"]
     n = int(round(T / 0.1))
     K, W = args.steps, args.warmup
     if W + K > n or K < 1:
@@ -389,9 +393,9 @@ def main():
     compare_ids = nf if prec == tjm.PREC_MIXED and not args.no_fp64_compare else 0
     workers, tile_mode, tune = args.workers, 0, None
     if args.tune:
-        tile_mode, workers, tune = autotune(tjm, models, L, chi, N, T, prec, args.tune_warm, args.tune_steps,
+        tile_mode, workers, tune = autotune(tjm, models, L, init, chi, N, T, prec, args.tune_warm, args.tune_steps,
                                             args.tune_cache or None)
-    head = measure(tjm, models, L, chi, N, T, prec, W, K, workers, read_ids=compare_ids, tile_mode=tile_mode)
+    head = measure(tjm, models, L, init, chi, N, T, prec, W, K, workers, read_ids=compare_ids, tile_mode=tile_mode)
     peak = PEAK_TFLOPS[args.precision]
     out = {
         "metric": "trajectory-steps/s at L=%d chi=%d (mixed vs FP64 path)" % (L, chi),
@@ -407,10 +411,12 @@ def main():
         "dtype": "c64-mfma+f64" if prec == tjm.PREC_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": "XXX chain L=%d J=1 g=0.5 (X field), sigma- and Z jumps gamma=0.1 on every "
-                               "site, Neel initial state, chi_max=%d, dt=0.1, T=%g, %d trajectories, %s; "
+                               "site, %s initial state, chi_max=%d, dt=0.1, T=%g, %d trajectories, %s; "
                                "timed steps %d..%d of the %d-step job"
-                               % (L, chi, T, N, args.precision, W + 1, W + K, n),
-                   "L": L, "chi_max": chi, "n_traj": N, "dt": 0.1, "T": T, "precision": args.precision},
+                               % (L, "Neel" if init == "neel" else "|0...0>", chi, T, N, args.precision, W + 1,
+                                  W + K, n),
+                   "L": L, "chi_max": chi, "n_traj": N, "dt": 0.1, "T": T, "init": init,
+                   "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": head["achieved_tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": head["achieved_tflops"] / peak,
                      "traffic": traffic_per_launch(args.workload, args.precision, W, K),
@@ -426,7 +432,7 @@ def main():
     if compare_ids:
         # leave room for the CPU baseline after it
         deadline = t_start + args.budget - (0 if args.no_cpu_baseline else args.cpu_budget + 60.0)
-        f = measure(tjm, models, L, chi, nf, T, tjm.PREC_FP64, W, K, workers, read_ids=nf, deadline=deadline,
+        f = measure(tjm, models, L, init, chi, nf, T, tjm.PREC_FP64, W, K, workers, read_ids=nf, deadline=deadline,
                     tile_mode=tile_mode)
         if f["partial"]:
             out["fp64_path"] = {"value": None, "n_traj": nf, "partial": True, "steps_done": f["steps_done"],
