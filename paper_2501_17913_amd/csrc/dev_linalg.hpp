@@ -947,11 +947,33 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
   int used = 0;
   for (int j = 0; j < m_max; ++j) {
     op.apply(basis(j), w);                           // w = H B_j = (H q_j) / s_j
-    // one classical Gram-Schmidt pass against q_0..q_j (alpha_j = Re h_j,
-    // the three-term part included): h_i = s_i s_j B_i^H w, with w read once
-    // per block of up to eight basis vectors
     const int nq = j + 1;
     const double sj = Lz.scale[j];
+    // alpha_j = Re q_j^H H q_j = s_j^2 Re B_j^H w, then the three-term part
+    // is removed before the orthogonalisation: w <- w1 = H q_j - alpha_j q_j
+    // - beta_{j-1} q_{j-1}, in place (each thread rewrites the entries the
+    // projections below read on the same thread).  Orthogonalising the raw
+    // product instead would multiply the basis' orthogonality error by
+    // |H q_j| / beta_j per iteration (the energy over the residual), which
+    // loses orthogonality within a few iterations on long chains.
+    const zd* Bj = basis(j);
+    const zd* Bp = basis(j > 0 ? j - 1 : 0);
+    double ar = 0.0;
+#pragma unroll 2
+    for (int e = tid; e < n; e += TJM_NT) {
+      const zd b = gload(Bj, e), x = gload(w, e);
+      ar = fma(b.re, x.re, fma(b.im, x.im, ar));
+    }
+    const double aj = blk_sum(ar, S) * sj * sj;
+    const double cj_ = -aj * sj;                     // coefficient of B_j in w1
+    const double cp_ = j > 0 ? -Lz.beta[j - 1] * Lz.scale[j - 1] : 0.0;   // of B_{j-1}
+#pragma unroll 2
+    for (int e = tid; e < n; e += TJM_NT) {
+      const zd b = gload(Bj, e), p = gload(Bp, e), x = gload(w, e);
+      gstore(w, e, cmk(fma(cp_, p.re, fma(cj_, b.re, sj * x.re)), fma(cp_, p.im, fma(cj_, b.im, sj * x.im))));
+    }
+    // one classical Gram-Schmidt pass of w1 against q_0..q_j: h_i = s_i
+    // B_i^H w1, with w1 read once per block of up to eight basis vectors
     for (int i0 = 0; i0 < nq; i0 += 8) {
       const int nu = nq - i0 < 8 ? nq - i0 : 8;
       const zd* bp[8];
@@ -972,17 +994,17 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
     for (int i = tid; i < nq; i += TJM_NT) {
       double hr = 0.0, hi = 0.0;
       for (int wv = 0; wv < TJM_NWAVE; ++wv) { hr += Lz.red[wv][2 * i]; hi += Lz.red[wv][2 * i + 1]; }
-      const double f = Lz.scale[i] * sj;
+      const double f = Lz.scale[i];
       hr *= f; hi *= f;
       Lz.hre[i] = hr; Lz.him[i] = hi;
       Lz.hsre[i] = -hr * Lz.scale[i]; Lz.hsim[i] = -hi * Lz.scale[i];   // -h_i s_i
-      if (i == j) Lz.alpha[j] = hr;
+      if (i == j) Lz.alpha[j] = aj;
     }
     tjm_sync();
-    // w' = H q_j - sum_i h_i q_i = s_j w - sum_i (h_i s_i) B_i, into B_{j+1}
-    // (w itself where the basis is full: w' is then only needed for beta)
+    // w' = w1 - sum_i h_i q_i = w1 - sum_i (h_i s_i) B_i, into B_{j+1} (w
+    // itself where the basis is full: w' is then only needed for beta)
     zd* nb = j + 1 < m_max ? basis(j + 1) : w;
-    double bn = lz_axpy(basis, nq, Lz.hsre, Lz.hsim, w, sj, nb, n);
+    double bn = lz_axpy(basis, nq, Lz.hsre, Lz.hsim, w, 1.0, nb, n);
     bn = sqrt(blk_sum(bn, S));
     tridiag_exp_e0(j + 1, t, Lz);
     tjm_sync();
