@@ -82,9 +82,15 @@ def _oracle_sample(args):
     from oracle import model as om, mps_tjm
     rng = np.random.default_rng(seed)
     bonds = [min(2 ** b, 2 ** (L - b), chi) for b in range(L + 1)]
-    psi = [rng.normal(size=(2, bonds[l], bonds[l + 1])) + 1j * rng.normal(size=(2, bonds[l], bonds[l + 1]))
-           for l in range(L)]
-    mps_tjm.canonicalize(psi)
+    # every site a random isometry (rows orthonormal over (s, b)): a
+    # right-canonical state of norm 1 however long the chain, where a product
+    # of unnormalised random tensors would overflow
+    psi = []
+    for l in range(L):
+        a, b = bonds[l], bonds[l + 1]
+        g = rng.normal(size=(2 * b, a)) + 1j * rng.normal(size=(2 * b, a))
+        q, _ = np.linalg.qr(g)                       # 2b x a, orthonormal columns
+        psi.append(q.conj().T.reshape(a, 2, b).transpose(1, 0, 2).copy())
     Ws = om.xxx_mpo(L, 1.0, 0.5)
     jumps = om.relax_dephase_jumps(L, 0.1, 0.1)
     obs = [(q, om.Z) for q in range(L)] + [(q, om.X) for q in range(L)]
@@ -304,13 +310,25 @@ def serving(tjm, models, K, precision):
                               q["seed"], tjm.default_options(precision=prec)))
     reps = []
     pending = set(range(len(ids)))
-    while pending:                        # progress as jobs finish, in any order
+    total = sum(q["n_traj"] for q in reqs)
+    finished = {i: 0 for i in pending}
+    reported, t_rep = 0, time.perf_counter()
+    while pending:                        # progress as trajectories and jobs finish, in any order
         for i in sorted(pending):
             if srv.poll(ids[i]):
+                finished[i] = reqs[i]["n_traj"]
                 reps.append((i, srv.wait(ids[i])["report"]))
                 pending.discard(i)
                 print("  request %d done (%d of %d) at %.1fs" % (i, len(reps), len(ids), time.perf_counter() - t0),
                       file=sys.stderr, flush=True)
+            else:
+                finished[i] = srv.progress(ids[i])
+        done = sum(finished.values())
+        # every 5% of all trajectories, or any that finished after 20 s without a line
+        if done >= reported + total // 20 or (done > reported and time.perf_counter() - t_rep > 20.0):
+            reported, t_rep = done, time.perf_counter()
+            print("  %d of %d trajectories finished at %.1fs" % (done, total, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
         time.sleep(0.01)
     makespan = time.perf_counter() - t0
     srv.close()

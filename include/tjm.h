@@ -410,6 +410,11 @@ tjm_status tjm_submit(tjm_server *s, const tjm_model *m, const tjm_run_args *arg
  * TJM_E_INVAL for an unknown or already collected job. */
 tjm_status tjm_poll(tjm_server *s, uint64_t job, int *done);
 
+/* *traj_done = the job's trajectories finished so far (all of them once the
+ * job has finished, 0 while it waits for admission).  TJM_E_INVAL for an
+ * unknown or already collected job. */
+tjm_status tjm_job_progress(tjm_server *s, uint64_t job, int *traj_done);
+
 /*
  * Blocks until the job has finished, then writes its outputs into
  * caller-allocated buffers (each may be NULL): mean and sem as in tjm_run,

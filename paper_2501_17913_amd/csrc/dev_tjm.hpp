@@ -81,6 +81,31 @@ template <typename Tc> struct Tjm {
     if (tjm_tid() == 0) e[0] = cmk((Tc)1, (Tc)0);
   }
 
+  // Mixed path: the channel of a new complex-FP32 environment that carries
+  // the energy of its half chain (L[en] on the left, R[st] on the right,
+  // with en / st the identity channels of the other side) is re-centred on
+  // zero, its diagonal mean removed.  FP32 then holds the spread of the
+  // Schmidt states' energies instead of an energy of order L, and every
+  // effective Hamiltonian built from such environments is H^eff - c I,
+  // which multiplies the evolved centre tensor, and so the whole state, by
+  // the phase exp(i tau c): observables, norms, Schmidt values and jump
+  // probabilities are unchanged.  The shift is exact: the energy channel
+  // meets the MPO only through identity blocks that end in the other side's
+  // identity channel, so c I in it is c times the identity operator.
+  // Skipped at the chain ends, where the single channel is both, and for
+  // MPOs without identity channels.
+  TJM_DEV void env_center(zc* E, int chi, int chan, int other) {
+    if constexpr (sizeof(Tc) == 4) {
+      if (chan < 0 || other < 0 || chan == other) return;
+      zc* M = E + (long)chan * chi * chi;
+      double sum = 0.0;
+      for (int a = tjm_tid(); a < chi; a += TJM_NT) sum += (double)M[(long)a * chi + a].re;
+      const double mean = blk_sum(sum, tjm_lds.S) / chi;
+      for (int a = tjm_tid(); a < chi; a += TJM_NT) M[(long)a * chi + a].re = (Tc)((double)M[(long)a * chi + a].re - mean);
+      tjm_sync();
+    }
+  }
+
   // L_{s+1}[w'][b'][b] = sum L_s[w][a'][a] conj(A[a'][s'][b']) W[w][w'][s'][s] A[a][s][b]
   TJM_DEVNI void lupdate(int s, const zd* A, int chl, int chr, const zc* Lold, zc* Lnew) {
     const unsigned long long t0 = tjm_clock();
@@ -93,6 +118,7 @@ template <typename Tc> struct Tjm {
                   mix_rows((const zc*)T1, rp, P.mixL, d, (long)chl * d * chr, (long)d * chr, (long)chr),
                   Lnew, chr, (long)chr * chr, false, tjm_lds.gemm);
     tjm_sync();
+    env_center(Lnew, chr, P.env_en[s + 1], P.env_st[s + 1]);
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dl * chl * chl * d * chr + (unsigned long long)Dr * chr * chr * chl * d);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dr, d, rp) * chl * chr);
     since(TJM_ST_T_CONTRACT, t0);
@@ -118,6 +144,7 @@ template <typename Tc> struct Tjm {
     const int Dl = P.mpoD[s], Dr = P.mpoD[s + 1];
     const int* rp = P.mixR_ptr + (long)s * (P.Dmax * d + 1);
     env_right<Tc>(B, chl, chr, Dl, Dr, rp, P.mixR, Rold, Rnew, T1);
+    env_center(Rnew, chl, P.env_st[s], P.env_en[s]);
     count(TJM_ST_CMAC_MFMA, (unsigned long long)Dr * chl * d * chr * chr + (unsigned long long)Dl * chl * chl * d * chr);
     count(TJM_ST_CMAC_MIX, mix_nnz(Dl, d, rp) * chl * chr);
     since(TJM_ST_T_CONTRACT, t0);

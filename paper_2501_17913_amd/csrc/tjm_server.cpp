@@ -524,6 +524,16 @@ extern "C" tjm_status tjm_poll(tjm_server* s, uint64_t job, int* done) {
   return TJM_OK;
 }
 
+extern "C" tjm_status tjm_job_progress(tjm_server* s, uint64_t job, int* traj_done) {
+  if (!s || !traj_done) return sfail(TJM_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->jobs.find(job);
+  if (it == s->jobs.end()) return sfail(TJM_E_INVAL, "unknown job");
+  const Job* j = it->second;
+  *traj_done = j->done ? j->n_traj : j->seen;
+  return TJM_OK;
+}
+
 extern "C" tjm_status tjm_wait(tjm_server* s, uint64_t job, double* mean, double* sem, tjm_job_report* rep) {
   if (!s) return sfail(TJM_E_INVAL, "server is NULL");
   Job* j = nullptr;

@@ -27,7 +27,7 @@ EXPORTED = [
     "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd", "tjm_svd_noalloc",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
-    "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_wait", "tjm_server_last_error",
+    "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_job_progress", "tjm_wait", "tjm_server_last_error",
     "tjm_server_destroy",
 ]
 
@@ -155,6 +155,8 @@ lib.tjm_submit.argtypes = [_vp, _vp, C.POINTER(RunArgs), C.POINTER(C.c_uint64)]
 lib.tjm_submit.restype = C.c_int
 lib.tjm_poll.argtypes = [_vp, C.c_uint64, _ip]
 lib.tjm_poll.restype = C.c_int
+lib.tjm_job_progress.argtypes = [_vp, C.c_uint64, _ip]
+lib.tjm_job_progress.restype = C.c_int
 lib.tjm_wait.argtypes = [_vp, C.c_uint64, _dp, _dp, C.POINTER(JobReport)]
 lib.tjm_wait.restype = C.c_int
 lib.tjm_server_last_error.argtypes = []
@@ -377,6 +379,12 @@ class Server:
         done = C.c_int()
         self._sc(lib.tjm_poll(self.h, C.c_uint64(job), C.byref(done)))
         return bool(done.value)
+
+    def progress(self, job):
+        """Trajectories of the job finished so far (tjm_job_progress)."""
+        n = C.c_int()
+        self._sc(lib.tjm_job_progress(self.h, C.c_uint64(job), C.byref(n)))
+        return n.value
 
     def wait(self, job):
         """Blocks until the job ends; returns dict with mean, sem and report."""

@@ -161,13 +161,21 @@ def test_server_admits_trajectories_of_new_jobs_while_others_run():
                   (16, 16, 96, 3, 0.6, 0.05, tjm.PREC_MIXED, inputs.SEED + 93)]
     srv = tjm.Server(0)
     first = _submit_all(srv, [long_job])[0]
-    while srv.poll(first):
-        pass
     import time
     time.sleep(0.2)
     later = _submit_all(srv, short_jobs)
+    # per-job progress: trajectories finished so far, never decreasing,
+    # all of them once the job is done
+    seen = []
+    while not srv.poll(first):
+        seen.append(srv.progress(first))
+        time.sleep(0.05)
+    assert all(0 <= a <= b <= long_job[2] for a, b in zip(seen, seen[1:]))
+    assert srv.progress(first) == long_job[2]
     reps = [srv.wait(j) for j in later]
     lrep = srv.wait(first)
+    with pytest.raises(tjm.TjmError):
+        srv.progress(first)                # collected
     srv.close()
     for job, r in zip(short_jobs, reps):
         log("short job", job[:4], "start %.3f end %.3f (long job ends %.3f)"
