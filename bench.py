@@ -310,24 +310,24 @@ def serving(tjm, models, K, precision):
                               q["seed"], tjm.default_options(precision=prec)))
     reps = []
     pending = set(range(len(ids)))
-    total = sum(q["n_traj"] for q in reqs)
+    total = sum(q["n_traj"] * q["n_steps"] for q in reqs)
     finished = {i: 0 for i in pending}
     reported, t_rep = 0, time.perf_counter()
-    while pending:                        # progress as trajectories and jobs finish, in any order
+    while pending:                        # progress as step functions and jobs finish, in any order
         for i in sorted(pending):
             if srv.poll(ids[i]):
-                finished[i] = reqs[i]["n_traj"]
+                finished[i] = reqs[i]["n_traj"] * reqs[i]["n_steps"]
                 reps.append((i, srv.wait(ids[i])["report"]))
                 pending.discard(i)
                 print("  request %d done (%d of %d) at %.1fs" % (i, len(reps), len(ids), time.perf_counter() - t0),
                       file=sys.stderr, flush=True)
             else:
-                finished[i] = srv.progress(ids[i])
+                finished[i] = srv.progress(ids[i])[1]
         done = sum(finished.values())
-        # every 5% of all trajectories, or any that finished after 20 s without a line
+        # every 5% of all trajectory-steps, or any finished after 20 s without a line
         if done >= reported + total // 20 or (done > reported and time.perf_counter() - t_rep > 20.0):
             reported, t_rep = done, time.perf_counter()
-            print("  %d of %d trajectories finished at %.1fs" % (done, total, time.perf_counter() - t0),
+            print("  %d of %d trajectory-steps finished at %.1fs" % (done, total, time.perf_counter() - t0),
                   file=sys.stderr, flush=True)
         time.sleep(0.01)
     makespan = time.perf_counter() - t0

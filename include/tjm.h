@@ -410,10 +410,12 @@ tjm_status tjm_submit(tjm_server *s, const tjm_model *m, const tjm_run_args *arg
  * TJM_E_INVAL for an unknown or already collected job. */
 tjm_status tjm_poll(tjm_server *s, uint64_t job, int *done);
 
-/* *traj_done = the job's trajectories finished so far (all of them once the
- * job has finished, 0 while it waits for admission).  TJM_E_INVAL for an
- * unknown or already collected job. */
-tjm_status tjm_job_progress(tjm_server *s, uint64_t job, int *traj_done);
+/* Progress of a job: *traj_done = its trajectories finished so far and
+ * *steps_done = its step functions F_k (k >= 1) finished so far over all of
+ * its trajectories (n_traj and n_traj * n once it has finished
+ * successfully; 0 while it waits for admission).  TJM_E_INVAL for NULL, an
+ * unknown or an already collected job. */
+tjm_status tjm_job_progress(tjm_server *s, uint64_t job, int *traj_done, unsigned long long *steps_done);
 
 /*
  * Blocks until the job has finished, then writes its outputs into

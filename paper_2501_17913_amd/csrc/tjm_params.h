@@ -147,6 +147,7 @@ struct ServeDev {
   const TjmParams* params;           // [max_jobs] device copies of the jobs' parameters
   const ServeItem* items;            // [cap] ring (host-coherent)
   int* done;                         // [cap] 1 once item i % cap has finished (host-coherent)
+  unsigned long long* steps;         // [max_jobs] step functions finished per job slot (host-coherent)
   ServeShared* sh;                   // host-coherent
   unsigned* head;                    // device counter: items taken
   int cap;

@@ -99,6 +99,7 @@ struct Pool {
   ServeShared* sh = nullptr;           // host-coherent
   ServeItem* items = nullptr;          // host-coherent [kCap]
   int* done = nullptr;                 // host-coherent [kCap]
+  unsigned long long* steps = nullptr; // host-coherent [kMaxJobs]: step functions finished per slot
   unsigned pushed = 0;
   int active = 0;                      // admitted jobs not yet finished
   bool retired = false;                // takes no new job; released once drained
@@ -140,7 +141,10 @@ static hipError_t pool_init(Pool& p, int mixed) {
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.sh, sizeof(ServeShared), hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.items, sizeof(ServeItem) * (size_t)kCap, hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.done, sizeof(int) * (size_t)kCap, hipHostMallocCoherent);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&p.steps, sizeof(unsigned long long) * kMaxJobs, hipHostMallocCoherent);
   if (e != hipSuccess) return e;
+  std::memset(p.steps, 0, sizeof(unsigned long long) * kMaxJobs);
   std::memset(p.sh, 0, sizeof(ServeShared));
   std::memset(p.done, 0, sizeof(int) * (size_t)kCap);
   for (int i = kMaxJobs - 1; i >= 0; --i) p.free_slots.push_back(i);
@@ -155,6 +159,7 @@ static void pool_free(Pool& p) {
   if (p.sh) (void)hipHostFree(p.sh);
   if (p.items) (void)hipHostFree(p.items);
   if (p.done) (void)hipHostFree(p.done);
+  if (p.steps) (void)hipHostFree(p.steps);
   if (p.stream) (void)hipStreamDestroy(p.stream);
   p = Pool();
 }
@@ -313,6 +318,7 @@ static bool admit_front(tjm_server* s, std::unique_lock<std::mutex>& lk) {
     return true;
   }
   j->run = run;
+  __atomic_store_n(&p.steps[j->slot], 0ull, __ATOMIC_RELAXED);
   // append the job's trajectories to the ring, then publish them
   j->first = p.pushed;
   for (int t = 0; t < j->n_traj; ++t) {
@@ -336,7 +342,7 @@ static void keep_resident(tjm_server* s, Pool& p, std::unique_lock<std::mutex>& 
     if (j->pool == &p && j->seen < j->n_traj) { pending = true; break; }
   if (!pending) return;
   ServeDev S;
-  S.params = p.d_params; S.items = p.items; S.done = p.done; S.sh = p.sh; S.head = p.d_head;
+  S.params = p.d_params; S.items = p.items; S.done = p.done; S.steps = p.steps; S.sh = p.sh; S.head = p.d_head;
   S.cap = kCap; S.idle_spins = kIdleSpins;
   const hipError_t e = p.mixed ? tjm_launch_serve_float(S, p.workers, p.L_max, p.stream)
                                : tjm_launch_serve_double(S, p.workers, p.L_max, p.stream);
@@ -524,13 +530,16 @@ extern "C" tjm_status tjm_poll(tjm_server* s, uint64_t job, int* done) {
   return TJM_OK;
 }
 
-extern "C" tjm_status tjm_job_progress(tjm_server* s, uint64_t job, int* traj_done) {
-  if (!s || !traj_done) return sfail(TJM_E_INVAL, "NULL argument");
+extern "C" tjm_status tjm_job_progress(tjm_server* s, uint64_t job, int* traj_done, unsigned long long* steps_done) {
+  if (!s || !traj_done || !steps_done) return sfail(TJM_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->jobs.find(job);
   if (it == s->jobs.end()) return sfail(TJM_E_INVAL, "unknown job");
   const Job* j = it->second;
   *traj_done = j->done ? j->n_traj : j->seen;
+  if (j->done) *steps_done = j->status == TJM_OK ? (unsigned long long)j->n_traj * j->n_steps : 0ull;
+  else if (j->pool) *steps_done = __atomic_load_n(&j->pool->steps[j->slot], __ATOMIC_RELAXED);
+  else *steps_done = 0ull;
   return TJM_OK;
 }
 

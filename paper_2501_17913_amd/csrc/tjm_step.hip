@@ -79,7 +79,11 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
     const TjmParams& P = S.params[w.job];
     Tjm<T> t(P, dyn, (int)blockIdx.x);
     t.traj_init(w.traj);
-    for (int k = 1; k <= P.n_steps; ++k) t.traj_step(w.traj, k);
+    for (int k = 1; k <= P.n_steps; ++k) {
+      t.traj_step(w.traj, k);
+      if (threadIdx.x == 0)                // progress of the job, read by the host
+        __hip_atomic_fetch_add(&S.steps[w.job], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     __syncthreads();                     // every thread's writes of the trajectory are issued
     if (threadIdx.x == 0) {
       __threadfence_system();

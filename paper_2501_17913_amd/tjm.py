@@ -155,7 +155,7 @@ lib.tjm_submit.argtypes = [_vp, _vp, C.POINTER(RunArgs), C.POINTER(C.c_uint64)]
 lib.tjm_submit.restype = C.c_int
 lib.tjm_poll.argtypes = [_vp, C.c_uint64, _ip]
 lib.tjm_poll.restype = C.c_int
-lib.tjm_job_progress.argtypes = [_vp, C.c_uint64, _ip]
+lib.tjm_job_progress.argtypes = [_vp, C.c_uint64, _ip, C.POINTER(C.c_ulonglong)]
 lib.tjm_job_progress.restype = C.c_int
 lib.tjm_wait.argtypes = [_vp, C.c_uint64, _dp, _dp, C.POINTER(JobReport)]
 lib.tjm_wait.restype = C.c_int
@@ -381,10 +381,11 @@ class Server:
         return bool(done.value)
 
     def progress(self, job):
-        """Trajectories of the job finished so far (tjm_job_progress)."""
+        """(trajectories, step functions) of the job finished so far (tjm_job_progress)."""
         n = C.c_int()
-        self._sc(lib.tjm_job_progress(self.h, C.c_uint64(job), C.byref(n)))
-        return n.value
+        k = C.c_ulonglong()
+        self._sc(lib.tjm_job_progress(self.h, C.c_uint64(job), C.byref(n), C.byref(k)))
+        return n.value, k.value
 
     def wait(self, job):
         """Blocks until the job ends; returns dict with mean, sem and report."""

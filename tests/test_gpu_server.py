@@ -164,14 +164,17 @@ def test_server_admits_trajectories_of_new_jobs_while_others_run():
     import time
     time.sleep(0.2)
     later = _submit_all(srv, short_jobs)
-    # per-job progress: trajectories finished so far, never decreasing,
-    # all of them once the job is done
+    # per-job progress: trajectories and step functions finished so far,
+    # never decreasing, all of them once the job is done
     seen = []
     while not srv.poll(first):
         seen.append(srv.progress(first))
         time.sleep(0.05)
-    assert all(0 <= a <= b <= long_job[2] for a, b in zip(seen, seen[1:]))
-    assert srv.progress(first) == long_job[2]
+    n_steps = long_job[3]
+    assert all(0 <= a[0] <= b[0] <= long_job[2] and 0 <= a[1] <= b[1] <= long_job[2] * n_steps
+               and a[0] * n_steps <= a[1] for a, b in zip(seen, seen[1:]))
+    assert any(0 < s[1] < long_job[2] * n_steps for s in seen)
+    assert srv.progress(first) == (long_job[2], long_job[2] * n_steps)
     reps = [srv.wait(j) for j in later]
     lrep = srv.wait(first)
     with pytest.raises(tjm.TjmError):
