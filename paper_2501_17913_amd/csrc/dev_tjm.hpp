@@ -450,9 +450,38 @@ template <typename Tc> struct Tjm {
 
   // True if every singular value of the upper-triangular leading n x n block
   // of R (row-major, ld) provably exceeds sqrt(2 thr): sigma_min(R) >=
-  // 1 / ||R^{-1}||_F, with R^{-1} by back substitution (thread c builds
-  // column c in Y).  For a wide R [R1 R2], sigma_min >= sigma_min(R1).
+  // 1 / ||R^{-1}||_F, with R^{-1} by back substitution.  For a wide R
+  // [R1 R2], sigma_min >= sigma_min(R1).  Up to 64 columns (every bond of
+  // the supported chi_cap) lane c of wavefront 0 builds column c of R^{-1}
+  // in LDS, the rows from the bottom in step across the lanes: row i is
+  // x_ic = (delta_ic - sum_{j>i} R_ij x_jc) / R_ii for every c at once (x_jc
+  // = 0 for j > c comes out of the same formula), so R_ij is one broadcast
+  // value per step and x_jc an LDS read of the lane's own column; the sums
+  // and the result are those of a per-column substitution.
   TJM_DEVNI bool sv_floor_certified(const zd* R, int n, int ld, double thr) {
+    if (n <= 64) {
+      zd* X = (zd*)tjm_lds.gemm;                 // X[j][c] = (R^{-1})_{jc}, 64 x 64 complex
+      double acc = 0.0;
+      int bad = 0;
+      if (tjm_wave() == 0) {
+        const int c = tjm_lane();
+        const bool on = c < n;
+        for (int i = n - 1; i >= 0; --i) {
+          zd sum = cmk(i == c ? 1.0 : 0.0, 0.0);
+          const zd* Ri = R + (long)i * ld;
+          for (int j = i + 1; j < n; ++j) sum = sum - Ri[j] * X[j * 64 + c];
+          const zd rii = Ri[i];
+          const double d2 = abs2(rii);
+          if (!(d2 > 0.0)) { bad = 1; break; }   // uniform: every lane reads the same R_ii
+          const zd xi = cmk((sum.re * rii.re + sum.im * rii.im) / d2, (sum.im * rii.re - sum.re * rii.im) / d2);
+          X[i * 64 + c] = xi;
+          if (on) acc += abs2(xi);
+        }
+      }
+      double b2 = (double)bad;
+      blk_sum2(acc, b2, tjm_lds.S);
+      return b2 == 0.0 && acc * 2.0 * thr < 1.0;
+    }
     double acc = 0.0;
     int bad = 0;
     for (int c = tjm_tid(); c < n; c += TJM_NT) {
