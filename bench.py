@@ -347,6 +347,9 @@ def serving(tjm, models, K, precision):
         "offered_traj_steps_per_s": steps / span, "achieved_traj_steps_per_s": steps / makespan,
         "mean_queue_s": float(np.mean([r["queue_s"] for _, r in reps])),
         "mean_run_s": float(np.mean([r["run_s"] for _, r in reps])),
+        "per_request": {"latency_s": [round(r["latency_s"], 3) for _, r in reps],
+                        "queue_s": [round(r["queue_s"], 3) for _, r in reps],
+                        "run_s": [round(r["run_s"], 3) for _, r in reps]},
         "traj_steps_per_s": steps / makespan, "achieved_tflops": flop / makespan / 1e12,
         "config": {"workload": "serving stream: Poisson arrivals (mean 0.05 s), XXX chains L~U{20..200}, "
                                "chi_max in {16,32,64}, gamma~U[0.01,0.2], g~U[0,1], N~U{64..512}, "
@@ -367,7 +370,7 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=8.0, help="seconds of sampled oracle updates per process")
-    ap.add_argument("--budget", type=float, default=500.0,
+    ap.add_argument("--budget", type=float, default=520.0,
                     help="seconds after which the FP64 comparison is cut short (reported as partial)")
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
