@@ -870,6 +870,42 @@ TJM_DEV void lz_project(const zd* const* bp, const zd* w, int n, int i0, Lanczos
   }
 }
 
+// The projections of one Lanczos iteration in one pass: for the block of
+// basis vectors bp[0..NB) (indices i0 + u), d_u = B_u^H w, e_u = B_u^H B_j
+// and f_u = B_u^H B_{j-1}, this wavefront's parts written to red[(wave *
+// TJM_KMAX + i0 + u) * 6 + (d re, d im, e re, e im, f re, f im)].
+template <int NB>
+TJM_DEV void lz_project3(const zd* const* bp, const zd* w, const zd* Bj, const zd* Bp, int n, int i0,
+                         double* red) {
+  double a[NB][6];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[u][k] = 0.0;
+  for (int e = tjm_tid(); e < n; e += TJM_NT) {
+    const zd x = gload(w, e), y = gload(Bj, e), z = gload(Bp, e);
+    zd b[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) b[u] = gload(bp[u], e);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      a[u][0] = fma(b[u].re, x.re, fma(b[u].im, x.im, a[u][0]));
+      a[u][1] = fma(b[u].re, x.im, fma(-b[u].im, x.re, a[u][1]));
+      a[u][2] = fma(b[u].re, y.re, fma(b[u].im, y.im, a[u][2]));
+      a[u][3] = fma(b[u].re, y.im, fma(-b[u].im, y.re, a[u][3]));
+      a[u][4] = fma(b[u].re, z.re, fma(b[u].im, z.im, a[u][4]));
+      a[u][5] = fma(b[u].re, z.im, fma(-b[u].im, z.re, a[u][5]));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double s = tjm_grp_sum<TJM_WAVE>(a[u][k]);
+      if (tjm_lane() == 0) red[((long)tjm_wave() * TJM_KMAX + i0 + u) * 6 + k] = s;
+    }
+}
+
 // x_k + sum_u c_u B_u[e_k] for two entries e_0, e_1 and the coefficients
 // c_u = (cr[u], ci[u]) (LDS)
 template <int NB>
@@ -949,62 +985,63 @@ TJM_DEVNI int blk_expm(Op& op, zd* v, int n, double t, int m_max, double tol, zd
     op.apply(basis(j), w);                           // w = H B_j = (H q_j) / s_j
     const int nq = j + 1;
     const double sj = Lz.scale[j];
-    // alpha_j = Re q_j^H H q_j = s_j^2 Re B_j^H w, then the three-term part
-    // is removed before the orthogonalisation: w <- w1 = H q_j - alpha_j q_j
-    // - beta_{j-1} q_{j-1}, in place (each thread rewrites the entries the
-    // projections below read on the same thread).  Orthogonalising the raw
-    // product instead would multiply the basis' orthogonality error by
-    // |H q_j| / beta_j per iteration (the energy over the residual), which
-    // loses orthogonality within a few iterations on long chains.
+    // The iteration in the oracle's order: alpha_j = Re q_j^H H q_j, then
+    // w1 = H q_j - alpha_j q_j - beta_{j-1} q_{j-1}, then one classical
+    // Gram-Schmidt pass of w1 against q_0..q_j.  w1 is never stored: one
+    // pass over the basis gives d_i = B_i^H w, e_i = B_i^H B_j and f_i =
+    // B_i^H B_{j-1} (with w = H B_j, alpha_j = s_j^2 Re d_j), so that
+    // q_i^H w1 = s_i (s_j d_i + c_j e_i + c_p f_i) with c_j = -alpha_j s_j and
+    // c_p = -beta_{j-1} s_{j-1}.  The overlaps e_i and f_i of the stored
+    // vectors carry their orthogonality error into the projections, which is
+    // what removing the three-term part first achieves: orthogonalising the
+    // raw product would multiply that error by |H q_j| / beta_j (the energy
+    // over the residual) per iteration and lose orthogonality within a few
+    // iterations on long chains.
     const zd* Bj = basis(j);
     const zd* Bp = basis(j > 0 ? j - 1 : 0);
-    double ar = 0.0;
-#pragma unroll 2
-    for (int e = tid; e < n; e += TJM_NT) {
-      const zd b = gload(Bj, e), x = gload(w, e);
-      ar = fma(b.re, x.re, fma(b.im, x.im, ar));
-    }
-    const double aj = blk_sum(ar, S) * sj * sj;
-    const double cj_ = -aj * sj;                     // coefficient of B_j in w1
-    const double cp_ = j > 0 ? -Lz.beta[j - 1] * Lz.scale[j - 1] : 0.0;   // of B_{j-1}
-#pragma unroll 2
-    for (int e = tid; e < n; e += TJM_NT) {
-      const zd b = gload(Bj, e), p = gload(Bp, e), x = gload(w, e);
-      gstore(w, e, cmk(fma(cp_, p.re, fma(cj_, b.re, sj * x.re)), fma(cp_, p.im, fma(cj_, b.im, sj * x.im))));
-    }
-    // one classical Gram-Schmidt pass of w1 against q_0..q_j: h_i = s_i
-    // B_i^H w1, with w1 read once per block of up to eight basis vectors
+    double* red = (double*)tjm_lds.gemm;            // free between products
     for (int i0 = 0; i0 < nq; i0 += 8) {
       const int nu = nq - i0 < 8 ? nq - i0 : 8;
       const zd* bp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) bp[u] = basis(i0 + (u < nu ? u : 0));
       switch (nu) {
-        case 1: lz_project<1>(bp, w, n, i0, Lz); break;
-        case 2: lz_project<2>(bp, w, n, i0, Lz); break;
-        case 3: lz_project<3>(bp, w, n, i0, Lz); break;
-        case 4: lz_project<4>(bp, w, n, i0, Lz); break;
-        case 5: lz_project<5>(bp, w, n, i0, Lz); break;
-        case 6: lz_project<6>(bp, w, n, i0, Lz); break;
-        case 7: lz_project<7>(bp, w, n, i0, Lz); break;
-        default: lz_project<8>(bp, w, n, i0, Lz); break;
+        case 1: lz_project3<1>(bp, w, Bj, Bp, n, i0, red); break;
+        case 2: lz_project3<2>(bp, w, Bj, Bp, n, i0, red); break;
+        case 3: lz_project3<3>(bp, w, Bj, Bp, n, i0, red); break;
+        case 4: lz_project3<4>(bp, w, Bj, Bp, n, i0, red); break;
+        case 5: lz_project3<5>(bp, w, Bj, Bp, n, i0, red); break;
+        case 6: lz_project3<6>(bp, w, Bj, Bp, n, i0, red); break;
+        case 7: lz_project3<7>(bp, w, Bj, Bp, n, i0, red); break;
+        default: lz_project3<8>(bp, w, Bj, Bp, n, i0, red); break;
       }
     }
     tjm_sync();
-    for (int i = tid; i < nq; i += TJM_NT) {
-      double hr = 0.0, hi = 0.0;
-      for (int wv = 0; wv < TJM_NWAVE; ++wv) { hr += Lz.red[wv][2 * i]; hi += Lz.red[wv][2 * i + 1]; }
-      const double f = Lz.scale[i];
-      hr *= f; hi *= f;
-      Lz.hre[i] = hr; Lz.him[i] = hi;
-      Lz.hsre[i] = -hr * Lz.scale[i]; Lz.hsim[i] = -hi * Lz.scale[i];   // -h_i s_i
-      if (i == j) Lz.alpha[j] = aj;
+    {
+      double dj = 0.0;
+      for (int wv = 0; wv < TJM_NWAVE; ++wv) dj += red[((long)wv * TJM_KMAX + j) * 6];
+      const double aj = dj * sj * sj;
+      const double cj = -aj * sj;
+      const double cp = j > 0 ? -Lz.beta[j - 1] * Lz.scale[j - 1] : 0.0;
+      for (int i = tid; i < nq; i += TJM_NT) {
+        double v6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int wv = 0; wv < TJM_NWAVE; ++wv)
+          for (int k = 0; k < 6; ++k) v6[k] += red[((long)wv * TJM_KMAX + i) * 6 + k];
+        const double si = Lz.scale[i];
+        const double hr = si * (sj * v6[0] + cj * v6[2] + cp * v6[4]);
+        const double hi = si * (sj * v6[1] + cj * v6[3] + cp * v6[5]);
+        Lz.hre[i] = hr; Lz.him[i] = hi;
+        // coefficient of B_i in w' = s_j w + c_j B_j + c_p B_{j-1} - sum_i h_i s_i B_i
+        Lz.hsre[i] = -hr * si + (i == j ? cj : 0.0) + (j > 0 && i == j - 1 ? cp : 0.0);
+        Lz.hsim[i] = -hi * si;
+        if (i == j) Lz.alpha[j] = aj;
+      }
     }
     tjm_sync();
-    // w' = w1 - sum_i h_i q_i = w1 - sum_i (h_i s_i) B_i, into B_{j+1} (w
-    // itself where the basis is full: w' is then only needed for beta)
+    // w' = w1 - sum_i h_i q_i, into B_{j+1} (w itself where the basis is
+    // full: w' is then only needed for beta)
     zd* nb = j + 1 < m_max ? basis(j + 1) : w;
-    double bn = lz_axpy(basis, nq, Lz.hsre, Lz.hsim, w, 1.0, nb, n);
+    double bn = lz_axpy(basis, nq, Lz.hsre, Lz.hsim, w, sj, nb, n);
     bn = sqrt(blk_sum(bn, S));
     tridiag_exp_e0(j + 1, t, Lz);
     tjm_sync();
