@@ -345,8 +345,9 @@ void tjm_destroy(tjm_model *m);
  * Device memory: each admitted job holds its own buffers (tables, MPSs,
  * outputs); the workgroups' scratch is a pool per queue, shaped for the
  * largest chain and bond dimension it serves.  A job larger than the
- * current pool of its precision opens a new queue with a larger pool (the
- * old one drains and is released).  Admission is first come, first served:
+ * current pool of its precision waits until that queue has drained; a new
+ * queue then opens with a pool shaped for every waiting job of that
+ * precision that fits the budget.  Admission is first come, first served:
  * the oldest waiting job is admitted once its buffers, and any new pool it
  * needs, fit into the budget not held by admitted jobs and pools; no
  * younger job overtakes it.  Up to 256 jobs per queue are in flight, and up

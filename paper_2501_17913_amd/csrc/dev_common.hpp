@@ -167,3 +167,19 @@ TJM_DEV void tjm_draws(uint64_t seed, uint32_t traj, uint32_t step, uint32_t bra
   eps = u53(c[0], c[1]);
   r = u53(c[2], c[3]);
 }
+
+// Mean and standard error over trajectories of entry e of obs[n_traj][entries]
+// (Eq. TJMExpVal), the trajectories summed in index order: the same
+// arithmetic wherever a job's outputs are reduced.
+TJM_DEV void tjm_reduce_entry(const double* obs, int n_traj, long entries, long e, double* mean, double* sem) {
+  double s = 0.0;
+  for (int t = 0; t < n_traj; ++t) s += obs[(long)t * entries + e];
+  const double mu = s / n_traj;
+  double q = 0.0;
+  for (int t = 0; t < n_traj; ++t) {
+    const double x = obs[(long)t * entries + e] - mu;
+    q += x * x;
+  }
+  mean[e] = mu;
+  sem[e] = n_traj > 1 ? sqrt(q / ((double)(n_traj - 1) * n_traj)) : 0.0;
+}

@@ -35,9 +35,23 @@ struct Run {
   unsigned long long* d_stats = nullptr;
   int* d_flags = nullptr;
   int record_bonds = 0;
+
+  // server jobs: no fill kernels (the serve kernel clears what it needs) and
+  // uploads from pinned staging buffers, which the runtime copies with the
+  // DMA engines; a staged copy from pageable memory runs as a kernel on the
+  // stream's hardware queue, which may be the one a resident kernel holds
+  bool no_fill = false;
+  bool own_stream = true;                    // false: the server's upload stream, borrowed
+  std::vector<void*> host_allocs;            // pinned staging, freed with the run
+  // server jobs: the host-coherent buffers the serve kernel reduces the job into
+  double* h_mean = nullptr;
+  double* h_sem = nullptr;
+  unsigned long long* h_stats = nullptr;     // [TJM_NSTAT + 1]: statistics, failed trajectories
 };
 
 std::string g_create_err;
+
+
 
 }  // namespace
 
@@ -248,9 +262,13 @@ static void dissipator2(const cd G[4], double tau, cd out[4]) {
 static void free_run(Run* r) {
   if (!r) return;
   for (void* p : r->allocs) (void)hipFree(p);
+  for (void* h : r->host_allocs) (void)hipHostFree(h);
+  if (r->h_mean) (void)hipHostFree(r->h_mean);
+  if (r->h_sem) (void)hipHostFree(r->h_sem);
+  if (r->h_stats) (void)hipHostFree(r->h_stats);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
   if (r->ev1) (void)hipEventDestroy(r->ev1);
-  if (r->stream) (void)hipStreamDestroy(r->stream);
+  if (r->stream && r->own_stream) (void)hipStreamDestroy(r->stream);
   delete r;
 }
 
@@ -262,7 +280,18 @@ static hipError_t upload(Run* r, const std::vector<T>& h, T** dptr) {
   if (e != hipSuccess) return e;
   r->allocs.push_back(p);
   r->bytes += n;
-  if (!h.empty()) e = hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, r->stream);
+  if (!h.empty()) {
+    const void* src = h.data();
+    if (r->no_fill) {
+      void* pin = nullptr;
+      e = hipHostMalloc(&pin, h.size() * sizeof(T), hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      r->host_allocs.push_back(pin);
+      std::memcpy(pin, h.data(), h.size() * sizeof(T));
+      src = pin;
+    }
+    e = hipMemcpyAsync(p, src, h.size() * sizeof(T), hipMemcpyHostToDevice, r->stream);
+  }
   *dptr = (T*)p;
   return e;
 }
@@ -273,7 +302,7 @@ static hipError_t dalloc(Run* r, size_t n, void** dptr) {
   if (e != hipSuccess) return e;
   r->allocs.push_back(p);
   r->bytes += n;
-  e = hipMemsetAsync(p, 0, std::max<size_t>(n, 16), r->stream);
+  if (!r->no_fill) e = hipMemsetAsync(p, 0, std::max<size_t>(n, 16), r->stream);
   *dptr = p;
   return e;
 }
@@ -746,7 +775,8 @@ tjm_status tjm_run_footprint(tjm_model* m, int n_traj, double dt, double T, int 
 // workers' scratch is that pool (pool_workers slots of pool_stride bytes,
 // at least the plan's stride) instead of an allocation of the run's own.
 static tjm_status alloc_run(tjm_model* m, Plan& pl, const tjm_options& opt, int n_traj, Run* r,
-                            char* pool_scratch, long pool_stride, int pool_workers) {
+                            char* pool_scratch, long pool_stride, int pool_workers,
+                            hipStream_t pool_stream = nullptr) {
   const int L = m->L;
   const long n = pl.n;
   r->n_traj = n_traj; r->n_steps = (int)n; r->n_obs = pl.P.n_obs; r->record_bonds = pl.P.record_bonds;
@@ -778,7 +808,13 @@ static tjm_status alloc_run(tjm_model* m, Plan& pl, const tjm_options& opt, int 
   // ---- uploads ---------------------------------------------------------------
   // Every copy and zero fill is ordered on the run's stream, ahead of the
   // launches, so runs on other streams of the device are not waited for.
-  RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+  if (pool_scratch) {
+    r->no_fill = true;
+    r->stream = pool_stream;
+    r->own_stream = false;
+  } else {
+    RCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+  }
   RCHK(hipEventCreate(&r->ev0));
   RCHK(hipEventCreate(&r->ev1));
   RCHK(upload(r, m->mpoD, (int**)&P.mpoD));
@@ -835,6 +871,15 @@ static tjm_status alloc_run(tjm_model* m, Plan& pl, const tjm_options& opt, int 
     RCHK(dalloc(r, (size_t)r->workers * P.scratch_stride, &p)); P.scratch = (char*)p;
   }
   RCHK(dalloc(r, 256, &p)); P.counter = (int*)p;
+  if (pool_scratch) {
+    const size_t entries = (size_t)(n + 1) * std::max(P.n_obs, 1);
+    RCHK(hipHostMalloc((void**)&r->h_mean, entries * 8, hipHostMallocCoherent));
+    RCHK(hipHostMalloc((void**)&r->h_sem, entries * 8, hipHostMallocCoherent));
+    RCHK(hipHostMalloc((void**)&r->h_stats, (TJM_NSTAT + 1) * 8, hipHostMallocCoherent));
+    P.serve_mean = r->h_mean;
+    P.serve_sem = r->h_sem;
+    P.serve_stats = r->h_stats;
+  }
 
   // the host tables of the plan must outlive their copies
   RCHK(hipStreamSynchronize(r->stream));
@@ -1107,8 +1152,9 @@ tjm_status tjm_pool_plan(tjm_model* m, int n_traj, double dt, double T, int chi_
 
 tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
                             const int* obs_site, const double* obs_op, uint64_t seed, const tjm_options* opt_in,
-                            char* scratch, long stride, int workers, void** job, TjmParams* Pout) {
-  if (!m || !job || !Pout || !scratch) return fail(m, TJM_E_INVAL, "NULL argument");
+                            char* scratch, long stride, int workers, TjmParams* d_slot, hipStream_t stream,
+                            void** job, TjmParams* Pout) {
+  if (!m || !job || !Pout || !scratch || !d_slot || !stream) return fail(m, TJM_E_INVAL, "NULL argument");
   tjm_options opt;
   tjm_default_options(&opt);
   if (opt_in) opt = *opt_in;
@@ -1117,14 +1163,22 @@ tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int c
   if (st != TJM_OK) return st;
   if ((st = select_device(m, opt)) != TJM_OK) return st;
   Run* r = new Run();
-  if ((st = alloc_run(m, pl, opt, n_traj, r, scratch, stride, workers)) != TJM_OK) {
+  if ((st = alloc_run(m, pl, opt, n_traj, r, scratch, stride, workers, stream)) != TJM_OK) {
     free_run(r);
     return st;
   }
-  const hipError_t e = hipStreamSynchronize(r->stream);   // tables uploaded, outputs zeroed
+  // the kernel parameters into the server's slot, on the same stream
+  void* pin = nullptr;
+  hipError_t e = hipHostMalloc(&pin, sizeof(TjmParams), hipHostMallocDefault);
+  if (e == hipSuccess) {
+    r->host_allocs.push_back(pin);
+    std::memcpy(pin, &r->P, sizeof(TjmParams));
+    e = hipMemcpyAsync(d_slot, pin, sizeof(TjmParams), hipMemcpyHostToDevice, r->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);   // tables uploaded
   if (e != hipSuccess) {
     free_run(r);
-    return fail(m, TJM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return fail(m, TJM_E_DEVICE, std::string("job upload: ") + hipGetErrorString(e));
   }
   *job = r;
   *Pout = r->P;
@@ -1134,12 +1188,28 @@ tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int c
 tjm_status tjm_pool_finish(tjm_model* m, void* job, double* mean, double* sem, tjm_stats* stats) {
   Run* r = (Run*)job;
   if (!m || !r) return fail(m, TJM_E_INVAL, "NULL argument");
-  r->steps_done = r->n_steps;              // every trajectory ran all its steps in the pool kernel
-  m->run = r;
-  const tjm_status st = tjm_run_end(m, mean, sem, nullptr, nullptr, nullptr);
-  if (stats) *stats = m->last;
-  return st;
+  // the serve kernel has reduced the job into r's host-coherent buffers; no
+  // device work here (the resident kernel may still be running)
+  tjm_stats& s = m->last;
+  std::memset(&s, 0, sizeof(s));
+  s.n_traj = r->n_traj; s.n_steps = r->n_steps; s.steps_done = r->n_steps; s.workers = r->workers;
+  s.device_bytes = r->bytes;
+  const unsigned long long* q = r->h_stats;
+  for (int i = 0; i < 8; ++i) s.phase_s[i] = 1e-8 * (double)q[TJM_ST_T_TOTAL + i];
+  s.cmac_mfma = q[TJM_ST_CMAC_MFMA]; s.cmac_mix = q[TJM_ST_CMAC_MIX];
+  s.krylov_iters = q[TJM_ST_KRYLOV]; s.expm_calls = q[TJM_ST_EXPM];
+  s.one_site = q[TJM_ST_ONE_SITE]; s.two_site = q[TJM_ST_TWO_SITE];
+  s.factorizations = q[TJM_ST_FACT]; s.jumps = q[TJM_ST_JUMPS];
+  s.failed_traj = (int)q[TJM_NSTAT];
+  if (stats) *stats = s;
+  if (s.failed_traj) return fail(m, TJM_E_NUMERIC, std::to_string(s.failed_traj) + " trajectories with a non-finite norm");
+  const size_t entries = (size_t)(r->n_steps + 1) * r->n_obs;
+  if (mean && entries) std::memcpy(mean, r->h_mean, entries * 8);
+  if (sem && entries) std::memcpy(sem, r->h_sem, entries * 8);
+  return TJM_OK;
 }
+
+void tjm_pool_release(void* job) { free_run((Run*)job); }
 
 extern "C" const char* tjm_last_error(const tjm_model* m) {
   return m ? m->err.c_str() : g_create_err.c_str();

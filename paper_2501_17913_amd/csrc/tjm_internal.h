@@ -64,12 +64,18 @@ tjm_status tjm_pool_plan(tjm_model* m, int n_traj, double dt, double T, int chi_
                          const int* obs_site, const double* obs_op, const tjm_options* opt, long* stride,
                          size_t* bytes);
 // tjm_pool_prepare: allocates and uploads the job (scratch: `workers` slots
-// of `stride` bytes at `scratch`), waits for the uploads, and returns the
-// job handle and its kernel parameters.
+// of `stride` bytes at `scratch`) and its kernel parameters into d_slot,
+// all on `stream` (the server's, which the job borrows and never destroys),
+// waits for that stream, and returns the job handle and its parameters.
 tjm_status tjm_pool_prepare(tjm_model* m, int n_traj, double dt, double T, int chi_max, int n_obs,
                             const int* obs_site, const double* obs_op, uint64_t seed, const tjm_options* opt,
-                            char* scratch, long stride, int workers, void** job, TjmParams* P);
-// tjm_pool_finish: once every trajectory has finished, reduces and copies
-// mean and sem, collects the statistics and releases the job.
+                            char* scratch, long stride, int workers, TjmParams* d_slot, hipStream_t stream,
+                            void** job, TjmParams* P);
+// tjm_pool_finish: once every trajectory has finished, copies the mean, sem
+// and statistics the serve kernel reduced the job into (no device work).
 tjm_status tjm_pool_finish(tjm_model* m, void* job, double* mean, double* sem, tjm_stats* stats);
+// tjm_pool_release: frees the job's device and host buffers; the server
+// calls it while none of its resident kernels runs (freeing device memory
+// waits for the whole device).
+void tjm_pool_release(void* job);
 

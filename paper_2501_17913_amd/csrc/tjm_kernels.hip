@@ -12,16 +12,7 @@ __global__ void tjm_reduce_kernel(const double* obs, int n_traj, long entries, d
                                   double* sem) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= entries) return;
-  double s = 0.0;
-  for (int t = 0; t < n_traj; ++t) s += obs[(long)t * entries + e];
-  const double mu = s / n_traj;
-  double q = 0.0;
-  for (int t = 0; t < n_traj; ++t) {
-    double x = obs[(long)t * entries + e] - mu;
-    q += x * x;
-  }
-  mean[e] = mu;
-  sem[e] = n_traj > 1 ? sqrt(q / ((double)(n_traj - 1) * n_traj)) : 0.0;
+  tjm_reduce_entry(obs, n_traj, entries, e, mean, sem);
 }
 
 size_t tjm_dyn_lds_bytes(int L) { return sizeof(int) * (size_t)(3 * L + 4); }

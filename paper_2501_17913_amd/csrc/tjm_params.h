@@ -102,6 +102,13 @@ struct TjmParams {
   long off_ot, ot_cap;               //   and their FP64 stage buffer of ot_cap complex
 
   int* counter;                      // work queue head
+  // server jobs only (null otherwise): where the workgroup that finishes the
+  // job's last trajectory writes its mean and standard error
+  // [n_steps+1][n_obs] and its summed statistics [TJM_NSTAT] plus the count
+  // of failed trajectories (host-coherent memory)
+  double* serve_mean;
+  double* serve_sem;
+  unsigned long long* serve_stats;
 };
 
 // indices of the per-trajectory statistics
@@ -148,6 +155,8 @@ struct ServeDev {
   const ServeItem* items;            // [cap] ring (host-coherent)
   int* done;                         // [cap] 1 once item i % cap has finished (host-coherent)
   unsigned long long* steps;         // [max_jobs] step functions finished per job slot (host-coherent)
+  int* count;                        // [max_jobs] trajectories finished per job slot (device; zero
+                                     // between jobs: the workgroup that finishes a job resets it)
   ServeShared* sh;                   // host-coherent
   unsigned* head;                    // device counter: items taken
   int cap;

@@ -10,9 +10,11 @@
 // dimension and model share that queue: the trajectories of a job admitted
 // while others run are taken as soon as workgroups free up, next to the
 // rest.  Each workgroup's scratch is a slot of its queue's pool.  A job too
-// large for the current pool of its precision opens a new queue with a pool
-// for the larger shape (its own resident kernel); the older queue drains
-// and is released once idle.
+// large for the current pool of its precision waits until that queue has
+// drained; the idle queue is released and a new one opens with a pool
+// shaped for every waiting job of the precision that the budget allows, so
+// that a stream of mixed shapes reshapes the pool rarely and never runs two
+// resident kernels of one precision against each other.
 //
 // A dispatcher thread admits jobs first come, first served (the oldest
 // waiting job is admitted once its buffers, and any new pool it needs, fit
@@ -100,6 +102,7 @@ struct Pool {
   ServeItem* items = nullptr;          // host-coherent [kCap]
   int* done = nullptr;                 // host-coherent [kCap]
   unsigned long long* steps = nullptr; // host-coherent [kMaxJobs]: step functions finished per slot
+  int* d_count = nullptr;              // [kMaxJobs] trajectories finished per slot (device)
   unsigned pushed = 0;
   int active = 0;                      // admitted jobs not yet finished
   bool retired = false;                // takes no new job; released once drained
@@ -129,15 +132,57 @@ struct tjm_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::vector<Pool*> pools[2];         // FP64, mixed: queues, the newest last
+  // finished jobs whose buffers await release: freeing device memory waits
+  // for the whole device, so it happens only while no resident kernel runs
+  // (the bytes stay counted in active_bytes until then)
+  std::vector<std::pair<void*, size_t>> graveyard;
+  // streams of the server's lifetime, each put to use once at creation,
+  // before any resident kernel runs: the resident kernels' (one per
+  // precision; a queue's successor opens only after it has been released)
+  // and the one that carries every job's uploads
+  hipStream_t kstream[2] = {nullptr, nullptr};
+  hipStream_t up_stream = nullptr;
   std::thread dispatcher;
 };
 
-static hipError_t pool_init(Pool& p, int mixed) {
+// A resident kernel's stream carries only that kernel, which occupies the
+// stream's hardware queue until it exits.  Ordinary streams share the
+// process's few hardware queues, so a job's uploads on a stream that landed
+// on the same queue would wait for the kernel; a stream created with a CU
+// mask (here all compute units) gets a hardware queue of its own.  The
+// server issues nothing on the null stream, which would wait for this one.
+static hipError_t stream_create(hipStream_t* st, int n_cu, bool own_queue) {
+  hipError_t e = hipErrorUnknown;
+  if (own_queue) {
+    std::vector<uint32_t> mask((size_t)(n_cu + 31) / 32, 0xffffffffu);
+    e = hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
+    if (e != hipSuccess) (void)hipGetLastError();
+  }
+  if (e != hipSuccess) e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  // first use: a small copy, so that whatever the runtime sets up for the
+  // stream happens now, not behind a running resident kernel
+  char* d = nullptr;
+  static const char zero[64] = {};
+  e = hipMalloc((void**)&d, sizeof zero);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, zero, sizeof zero, hipMemcpyHostToDevice, *st);
+  if (e == hipSuccess) e = hipStreamSynchronize(*st);
+  if (d) (void)hipFree(d);
+  return e;
+}
+
+static hipError_t pool_init(Pool& p, int mixed, hipStream_t stream) {
   p.mixed = mixed;
-  hipError_t e = hipStreamCreateWithFlags(&p.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc((void**)&p.d_params, sizeof(TjmParams) * kMaxJobs);
+  p.stream = stream;                   // the server's, for this precision
+  hipError_t e = hipMalloc((void**)&p.d_params, sizeof(TjmParams) * kMaxJobs);
   if (e == hipSuccess) e = hipMalloc((void**)&p.d_head, 256);
-  if (e == hipSuccess) e = hipMemset(p.d_head, 0, 256);
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_count, sizeof(int) * kMaxJobs);
+  // zeroed by copies (no fill kernel: another queue's resident kernel may
+  // hold every compute unit)
+  std::vector<char> zero(std::max<size_t>(256, sizeof(int) * kMaxJobs), 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(p.d_head, zero.data(), 256, hipMemcpyHostToDevice, p.stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p.d_count, zero.data(), sizeof(int) * kMaxJobs, hipMemcpyHostToDevice, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.sh, sizeof(ServeShared), hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.items, sizeof(ServeItem) * (size_t)kCap, hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostMalloc((void**)&p.done, sizeof(int) * (size_t)kCap, hipHostMallocCoherent);
@@ -156,21 +201,25 @@ static void pool_free(Pool& p) {
   if (p.scratch) (void)hipFree(p.scratch);
   if (p.d_params) (void)hipFree(p.d_params);
   if (p.d_head) (void)hipFree(p.d_head);
+  if (p.d_count) (void)hipFree(p.d_count);
   if (p.sh) (void)hipHostFree(p.sh);
   if (p.items) (void)hipHostFree(p.items);
   if (p.done) (void)hipHostFree(p.done);
   if (p.steps) (void)hipHostFree(p.steps);
-  if (p.stream) (void)hipStreamDestroy(p.stream);
   p = Pool();
 }
 
 static bool pool_running(Pool& p) { return hipStreamQuery(p.stream) == hipErrorNotReady; }
 
-// workgroups of the resident kernel for chains up to L
+// Workgroups of the resident kernel for chains up to L: what the compute
+// units hold, less one per 32 compute units (one per XCD on MI355X), so
+// that copies the runtime runs as small kernels (from pageable memory, for
+// one: the zeroed counters of a queue that opens while the other
+// precision's kernel runs) find room instead of waiting for it to exit.
 static int pool_workers(tjm_server* s, int mixed, int L) {
   int bpc = 1;
   if (tjm_blocks_per_cu(mixed, L, &bpc) != hipSuccess || bpc < 1) bpc = 1;
-  return bpc * s->n_cu;
+  return std::max(1, bpc * s->n_cu - std::max(1, s->n_cu / 32));
 }
 
 // The shape of a pool that serves the current pool's jobs and j.
@@ -188,7 +237,7 @@ static size_t pool_bytes_for(tjm_server* s, int mixed, long stride, int L) {
 static hipError_t pool_open(tjm_server* s, int mixed, long stride, int L, Pool** out) {
   Pool* p = new (std::nothrow) Pool();
   if (!p) return hipErrorOutOfMemory;
-  hipError_t e = pool_init(*p, mixed);
+  hipError_t e = pool_init(*p, mixed, s->kstream[mixed]);
   const int w = pool_workers(s, mixed, L);
   if (e == hipSuccess) e = hipMalloc((void**)&p->scratch, (size_t)w * (size_t)stride);
   if (e != hipSuccess) {
@@ -213,10 +262,19 @@ static Pool* current_pool(tjm_server* s, int q) {
   return s->pools[q].back();
 }
 
-static void release_slot(tjm_server* s, Job* j) {
+// the job's slot is free again; its buffers go to the graveyard
+static void release_slot(tjm_server* s, Job* j, void* run) {
   j->pool->free_slots.push_back(j->slot);
   j->pool->active--;
-  s->active_bytes -= j->bytes;
+  if (run) s->graveyard.emplace_back(run, j->bytes);
+  else s->active_bytes -= j->bytes;
+}
+
+static bool any_running(tjm_server* s) {
+  for (int q = 0; q < 2; ++q)
+    for (Pool* p : s->pools[q])
+      if (pool_running(*p)) return true;
+  return false;
 }
 
 static void mark_done(tjm_server* s, Job* j) {
@@ -236,7 +294,7 @@ static void finish_job(tjm_server* s, Job* j, std::unique_lock<std::mutex>& lk) 
   j->status = st;
   if (st != TJM_OK) j->err = tjm_last_error(j->model);
   j->run = nullptr;
-  release_slot(s, j);
+  release_slot(s, j, run);
   mark_done(s, j);
 }
 
@@ -254,11 +312,33 @@ static bool admit_front(tjm_server* s, std::unique_lock<std::mutex>& lk) {
   Job* j = s->queue.front();
   const int q = j->opt.precision == TJM_PREC_MIXED ? 1 : 0;
   Pool* cur = current_pool(s, q);
-  const bool fits = cur && j->stride <= cur->stride && j->L <= cur->L_max && !cur->free_slots.empty();
-  if (fits && !ring_has_room(s, *cur, j->n_traj)) return false;   // waits for earlier items to finish
+  // One resident queue per precision at a time (two persistent kernels that
+  // each fill the device would take compute units from each other in no
+  // useful order).  A job larger than the current pool waits until that
+  // queue has drained; the idle queue is then released, and the next pool
+  // is shaped for every waiting job of the precision that the budget allows.
+  const bool fits = cur && j->stride <= cur->stride && j->L <= cur->L_max;
+  if (cur && !fits) {
+    if (cur->active == 0) cur->retired = true;
+    return false;
+  }
+  if (!cur)
+    for (Pool* o : s->pools[q])
+      if (o->retired) return false;                             // still being released
+  if (fits && (cur->free_slots.empty() || !ring_has_room(s, *cur, j->n_traj))) return false;
   long stride = 0;
   int Lp = 0;
-  pool_shape(cur, j, &stride, &Lp);
+  if (!fits) {
+    pool_shape(nullptr, j, &stride, &Lp);
+    for (const Job* w : s->queue) {                             // the front job first
+      if ((w->opt.precision == TJM_PREC_MIXED ? 1 : 0) != q) continue;
+      const long ws = std::max(stride, w->stride);
+      const int wl = std::max(Lp, w->L);
+      if (s->active_bytes + j->bytes + pool_bytes_for(s, q, ws, wl) > s->budget) break;
+      stride = ws;
+      Lp = wl;
+    }
+  }
   const size_t extra = fits ? 0 : pool_bytes_for(s, q, stride, Lp);
   if (s->active_bytes + j->bytes + extra > s->budget) {
     // no room: idle queues of either precision give up their pools (they are
@@ -297,23 +377,13 @@ static bool admit_front(tjm_server* s, std::unique_lock<std::mutex>& lk) {
   tjm_status st = tjm_pool_prepare(j->model, j->n_traj, j->dt, j->T, j->chi_max, j->n_obs,
                                    j->obs_site.empty() ? nullptr : j->obs_site.data(),
                                    j->obs_op.empty() ? nullptr : j->obs_op.data(), j->seed, &j->opt, scratch,
-                                   pstride, workers, &run, &P);
-  if (st != TJM_OK) {
-    err = tjm_last_error(j->model);
-  } else {
-    const hipError_t e = hipMemcpy(p.d_params + j->slot, &P, sizeof(P), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      st = TJM_E_DEVICE;
-      err = std::string("parameter upload: ") + hipGetErrorString(e);
-      (void)tjm_pool_finish(j->model, run, nullptr, nullptr, nullptr);   // releases the job's buffers
-      run = nullptr;
-    }
-  }
+                                   pstride, workers, p.d_params + j->slot, s->up_stream, &run, &P);
+  if (st != TJM_OK) err = tjm_last_error(j->model);
   lk.lock();
   if (st != TJM_OK) {
     j->status = st;
     j->err = err;
-    release_slot(s, j);
+    release_slot(s, j, run);             // run is null if nothing was allocated
     mark_done(s, j);
     return true;
   }
@@ -342,7 +412,7 @@ static void keep_resident(tjm_server* s, Pool& p, std::unique_lock<std::mutex>& 
     if (j->pool == &p && j->seen < j->n_traj) { pending = true; break; }
   if (!pending) return;
   ServeDev S;
-  S.params = p.d_params; S.items = p.items; S.done = p.done; S.steps = p.steps; S.sh = p.sh; S.head = p.d_head;
+  S.params = p.d_params; S.items = p.items; S.done = p.done; S.steps = p.steps; S.count = p.d_count; S.sh = p.sh; S.head = p.d_head;
   S.cap = kCap; S.idle_spins = kIdleSpins;
   const hipError_t e = p.mixed ? tjm_launch_serve_float(S, p.workers, p.L_max, p.stream)
                                : tjm_launch_serve_double(S, p.workers, p.L_max, p.stream);
@@ -353,12 +423,9 @@ static void keep_resident(tjm_server* s, Pool& p, std::unique_lock<std::mutex>& 
     s->active.erase(s->active.begin() + (long)i);
     void* run = j->run;
     j->run = nullptr;
-    lk.unlock();
-    (void)tjm_pool_finish(j->model, run, nullptr, nullptr, nullptr);
-    lk.lock();
     j->status = TJM_E_DEVICE;
     j->err = std::string("serve kernel launch: ") + hipGetErrorString(e);
-    release_slot(s, j);
+    release_slot(s, j, run);
     mark_done(s, j);
   }
 }
@@ -385,23 +452,33 @@ static void dispatcher(tjm_server* s) {
       }
     }
     // a resident kernel wherever items are pending (it exits when idle);
-    // retired queues are released once drained and their kernel has exited
+    // retired queues are stopped once drained
     for (int q = 0; q < 2; ++q)
-      for (size_t i = 0; i < s->pools[q].size();) {
-        Pool* p = s->pools[q][i];
+      for (Pool* p : s->pools[q]) {
         keep_resident(s, *p, lk);
-        if (p->retired && p->active == 0) {
-          __atomic_store_n(&p->sh->stop, 1, __ATOMIC_RELEASE);
-          if (!pool_running(*p)) {
+        if (p->retired && p->active == 0) __atomic_store_n(&p->sh->stop, 1, __ATOMIC_RELEASE);
+      }
+    // releases that wait for the whole device: only while no resident
+    // kernel runs (finished jobs' buffers, drained retired queues)
+    if (!any_running(s)) {
+      for (auto& g : s->graveyard) {
+        tjm_pool_release(g.first);
+        s->active_bytes -= g.second;
+      }
+      s->graveyard.clear();
+      for (int q = 0; q < 2; ++q)
+        for (size_t i = 0; i < s->pools[q].size();) {
+          Pool* p = s->pools[q][i];
+          if (p->retired && p->active == 0) {
             s->active_bytes -= p->bytes;
             pool_free(*p);
             delete p;
             s->pools[q].erase(s->pools[q].begin() + (long)i);
             continue;
           }
+          ++i;
         }
-        ++i;
-      }
+    }
     if (s->stop && s->active.empty()) break;
     s->wake.wait_for(lk, std::chrono::microseconds(500));
   }
@@ -410,6 +487,17 @@ static void dispatcher(tjm_server* s) {
     for (Pool* p : s->pools[q]) {
       __atomic_store_n(&p->sh->stop, 1, __ATOMIC_RELEASE);
       (void)hipStreamSynchronize(p->stream);
+    }
+  for (auto& g : s->graveyard) tjm_pool_release(g.first);
+  s->graveyard.clear();
+}
+
+static void server_streams_destroy(tjm_server* s) {
+  for (hipStream_t* st : {&s->kstream[0], &s->kstream[1], &s->up_stream})
+    if (*st) {
+      (void)hipStreamSynchronize(*st);
+      (void)hipStreamDestroy(*st);
+      *st = nullptr;
     }
 }
 
@@ -439,6 +527,16 @@ extern "C" tjm_status tjm_server_create(tjm_server** out, int device, size_t hbm
   }
   s->device = device;
   s->n_cu = prop.multiProcessorCount;
+  if ((e = hipSetDevice(device)) == hipSuccess) {
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = stream_create(&s->kstream[q], s->n_cu, true);
+    if (e == hipSuccess) e = stream_create(&s->up_stream, s->n_cu, false);
+    (void)hipSetDevice(prev);
+  }
+  if (e != hipSuccess) {
+    server_streams_destroy(s);
+    delete s;
+    return sfail(TJM_E_DEVICE, std::string("server streams: ") + hipGetErrorString(e));
+  }
   s->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (size_t)(0.85 * (double)freeb);
   try {
     s->dispatcher = std::thread(dispatcher, s);
@@ -601,6 +699,7 @@ extern "C" void tjm_server_destroy(tjm_server* s) {
       pool_free(*p);
       delete p;
     }
+  server_streams_destroy(s);
   (void)hipSetDevice(prev);
   for (auto& kv : s->jobs) {
     tjm_destroy(kv.second->model);

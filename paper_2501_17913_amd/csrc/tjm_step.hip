@@ -78,6 +78,16 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
     const ServeItem w = S.items[it % S.cap];
     const TjmParams& P = S.params[w.job];
     Tjm<T> t(P, dyn, (int)blockIdx.x);
+    // the job's buffers come uninitialised (admission launches no kernel:
+    // the resident one holds every compute unit): clear what this
+    // trajectory accumulates into or may leave unwritten
+    {
+      double* o = P.obs + (long)w.traj * (P.n_steps + 1) * P.n_obs;
+      for (long e = threadIdx.x; e < (long)(P.n_steps + 1) * P.n_obs; e += TJM_NT) o[e] = 0.0;
+      for (int i = threadIdx.x; i < TJM_NSTAT; i += TJM_NT) P.tstats[(long)w.traj * TJM_NSTAT + i] = 0ull;
+      if (threadIdx.x == 0) P.tflags[w.traj] = 0;
+      __syncthreads();
+    }
     t.traj_init(w.traj);
     for (int k = 1; k <= P.n_steps; ++k) {
       t.traj_step(w.traj, k);
@@ -85,6 +95,30 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
         __hip_atomic_fetch_add(&S.steps[w.job], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();                     // every thread's writes of the trajectory are issued
+    // the workgroup that finishes a job's last trajectory reduces the job
+    // (mean, standard error, statistics) into the host's buffers, so that
+    // finishing a job needs no further device work
+    if (threadIdx.x == 0) {
+      __threadfence();
+      tjm_lds.pick = atomicAdd(&S.count[w.job], 1);
+    }
+    __syncthreads();
+    if (tjm_lds.pick == P.n_traj - 1) {
+      __threadfence();
+      if (threadIdx.x == 0) S.count[w.job] = 0;      // every other trajectory of the job has counted
+      const long entries = (long)(P.n_steps + 1) * P.n_obs;
+      for (long e = threadIdx.x; e < entries; e += TJM_NT)
+        tjm_reduce_entry(P.obs, P.n_traj, entries, e, P.serve_mean, P.serve_sem);
+      for (int i = threadIdx.x; i <= TJM_NSTAT; i += TJM_NT) {
+        unsigned long long s = 0;
+        if (i < TJM_NSTAT)
+          for (int q = 0; q < P.n_traj; ++q) s += P.tstats[(long)q * TJM_NSTAT + i];
+        else
+          for (int q = 0; q < P.n_traj; ++q) s += P.tflags[q] != 0;
+        P.serve_stats[i] = s;
+      }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence_system();
       __hip_atomic_store(&S.done[it % S.cap], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

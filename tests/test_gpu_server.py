@@ -98,7 +98,12 @@ def test_server_small_fp64_job_matches_oracle():
 
 
 def test_server_budget_admits_one_job_at_a_time():
-    jobs = JOBS[:3]
+    # one chain shape and precision, so that every job uses the same scratch
+    # pool whatever the server reshapes (a smaller pool would leave room for
+    # more buffers than the first pass measured)
+    jobs = [(8, 8, 40, 6, 0.5, 0.1, tjm.PREC_FP64, inputs.SEED + 86),
+            (8, 8, 120, 4, 0.3, 0.05, tjm.PREC_FP64, inputs.SEED + 87),
+            (8, 8, 16, 8, 0.6, 0.1, tjm.PREC_FP64, inputs.SEED + 88)]
     sizes, pools = [], {}
     srv = tjm.Server(0)
     for job in jobs:       # learn each job's buffers and its precision's pool from a first pass
@@ -184,5 +189,8 @@ def test_server_admits_trajectories_of_new_jobs_while_others_run():
         log("short job", job[:4], "start %.3f end %.3f (long job ends %.3f)"
             % (r["report"]["start_s"], r["report"]["end_s"], lrep["report"]["end_s"]))
         assert r["report"]["start_s"] < lrep["report"]["end_s"]
+        # and is finished and released while the long job still runs (its
+        # release does not wait for the resident kernel)
+        assert r["report"]["end_s"] < lrep["report"]["end_s"]
         assert np.array_equal(r["mean"], _direct(job)["mean"])
     assert np.array_equal(lrep["mean"], _direct(long_job)["mean"])
