@@ -14,7 +14,9 @@ trajectories x K / wall seconds.  The default window (W=5, K=20: steps
 path is timed on the same steps for trajectory ids 0..511 (fp64_path), and
 the observables of those ids on both paths are compared step by step
 (error_vs_fp64: largest difference over trajectories whose jump logs agree,
-and the number whose jump logs differ).
+the number whose jump logs differ, how many exceed 2e-4 and through which
+step all stay within it, and the largest difference of the ensemble means,
+also in FP64 standard errors).
 
 roofline.traffic (HBM bytes per launch of the step kernel) comes from the
 FETCH_SIZE / WRITE_SIZE counter summary in profiles/, scaled by the same
@@ -275,16 +277,35 @@ def measure(tjm, models, L, init, chi, N, T, prec, warmup, K, workers, read_ids=
     }
 
 
-def compare(a, b):
-    """Mixed against FP64 records of the same trajectory ids: trajectories
-    whose jump logs differ are counted (a decision within the FP32 error of
-    its threshold sends the trajectory elsewhere); over the rest, the
-    largest and mean absolute difference of the observables."""
+def compare(a, b, tol=2e-4):
+    """Mixed (a) against FP64 (b) records of the same trajectory ids.
+
+    Per trajectory: those whose jump logs differ are counted (a decision
+    within the FP32 error of its threshold sends the trajectory elsewhere);
+    over the rest, the largest and mean absolute difference of the
+    observables, how many exceed tol at some step, and the last step through
+    which every one of them stays within tol (in the truncated regime the
+    dynamics amplify any difference, FP32 rounding included, step by step).
+    Ensemble: the largest difference of the trajectory means over all ids,
+    absolute and in units of the FP64 standard error of the mean."""
     same = np.all(a["jumps"] == b["jumps"], axis=1)
-    d = np.abs(a["per_traj"] - b["per_traj"])[same]
-    return {"trajectories": int(len(same)), "flipped": int((~same).sum()),
-            "max_abs": float(d.max()) if d.size else None, "mean_abs": float(d.mean()) if d.size else None,
-            "steps": int(a["per_traj"].shape[1] - 1)}
+    d = np.abs(a["per_traj"] - b["per_traj"])[same]            # traj x step x obs
+    out = {"trajectories": int(len(same)), "flipped": int((~same).sum()),
+           "max_abs": float(d.max()) if d.size else None, "mean_abs": float(d.mean()) if d.size else None,
+           "steps": int(a["per_traj"].shape[1] - 1), "tol": tol}
+    if d.size:
+        per_step = d.max(axis=(0, 2))
+        bad = np.nonzero(per_step > tol)[0]
+        out["over_tol"] = int((d.max(axis=(1, 2)) > tol).sum())
+        out["within_tol_through_step"] = int(bad[0] - 1) if bad.size else out["steps"]
+    n = a["per_traj"].shape[0]
+    if n > 1:
+        dm = np.abs(a["per_traj"].mean(axis=0) - b["per_traj"].mean(axis=0))
+        sem = b["per_traj"].std(axis=0, ddof=1) / np.sqrt(n)
+        pos = sem > 0
+        out["ensemble_max_abs"] = float(dm.max())
+        out["ensemble_max_over_sem"] = float((dm[pos] / sem[pos]).max()) if pos.any() else None
+    return out
 
 
 def serving(tjm, models, K, precision):

@@ -142,6 +142,7 @@ struct tjm_server {
   // and the one that carries every job's uploads
   hipStream_t kstream[2] = {nullptr, nullptr};
   hipStream_t up_stream = nullptr;
+  char* d_touch = nullptr;             // target of those first copies (freed with the server)
   std::thread dispatcher;
 };
 
@@ -151,7 +152,7 @@ struct tjm_server {
 // on the same queue would wait for the kernel; a stream created with a CU
 // mask (here all compute units) gets a hardware queue of its own.  The
 // server issues nothing on the null stream, which would wait for this one.
-static hipError_t stream_create(hipStream_t* st, int n_cu, bool own_queue) {
+static hipError_t stream_create(hipStream_t* st, int n_cu, bool own_queue, char* d_touch) {
   hipError_t e = hipErrorUnknown;
   if (own_queue) {
     std::vector<uint32_t> mask((size_t)(n_cu + 31) / 32, 0xffffffffu);
@@ -162,12 +163,9 @@ static hipError_t stream_create(hipStream_t* st, int n_cu, bool own_queue) {
   if (e != hipSuccess) return e;
   // first use: a small copy, so that whatever the runtime sets up for the
   // stream happens now, not behind a running resident kernel
-  char* d = nullptr;
   static const char zero[64] = {};
-  e = hipMalloc((void**)&d, sizeof zero);
-  if (e == hipSuccess) e = hipMemcpyAsync(d, zero, sizeof zero, hipMemcpyHostToDevice, *st);
+  e = hipMemcpyAsync(d_touch, zero, sizeof zero, hipMemcpyHostToDevice, *st);
   if (e == hipSuccess) e = hipStreamSynchronize(*st);
-  if (d) (void)hipFree(d);
   return e;
 }
 
@@ -499,6 +497,8 @@ static void server_streams_destroy(tjm_server* s) {
       (void)hipStreamDestroy(*st);
       *st = nullptr;
     }
+  if (s->d_touch) (void)hipFree(s->d_touch);
+  s->d_touch = nullptr;
 }
 
 extern "C" tjm_status tjm_server_create(tjm_server** out, int device, size_t hbm_budget_bytes) {
@@ -528,8 +528,9 @@ extern "C" tjm_status tjm_server_create(tjm_server** out, int device, size_t hbm
   s->device = device;
   s->n_cu = prop.multiProcessorCount;
   if ((e = hipSetDevice(device)) == hipSuccess) {
-    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = stream_create(&s->kstream[q], s->n_cu, true);
-    if (e == hipSuccess) e = stream_create(&s->up_stream, s->n_cu, false);
+    e = hipMalloc((void**)&s->d_touch, 64);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = stream_create(&s->kstream[q], s->n_cu, true, s->d_touch);
+    if (e == hipSuccess) e = stream_create(&s->up_stream, s->n_cu, false, s->d_touch);
     (void)hipSetDevice(prev);
   }
   if (e != hipSuccess) {
