@@ -308,9 +308,11 @@ def compare(a, b, tol=2e-4):
     return out
 
 
-def serving(tjm, models, K, precision):
+def serving(tjm, models, K, precision, reserve=True):
     """The first K requests of the serving stream, submitted at their arrival
-    times to one tjm_server; latency = submission to completion."""
+    times to one tjm_server; latency = submission to completion.  With
+    reserve, the server's pools are shaped for the largest request shape
+    among them (tjm_server_reserve) before the first arrival."""
     from tests import inputs
     reqs = inputs.serving_stream(K)
     prec = tjm.PREC_MIXED if precision == "mixed" else tjm.PREC_FP64
@@ -321,6 +323,13 @@ def serving(tjm, models, K, precision):
         m.set_initial_product(models.neel(q["L"]))
         built.append(m)
     srv = tjm.Server(0)
+    Lr = max(q["L"] for q in reqs)
+    chir = max(q["chi_max"] for q in reqs)
+    if reserve:                          # the largest request shape of the K requests
+        mpo, s, o, r = models.xxx_model(Lr, 1.0, 0.5, 0.1)
+        hint = tjm.Model(Lr, mpo, s, o, r)
+        srv.reserve(hint, 64, 0.1, 0.1, chir, models.zx_observables(Lr), tjm.default_options(precision=prec))
+        hint.close()
     t0 = time.perf_counter()
     ids = []
     for q, m in zip(reqs, built):
@@ -364,7 +373,8 @@ def serving(tjm, models, K, precision):
         "metric": "p50/p99 latency of the serving stream (first %d requests)" % K,
         "value": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "unit": "s",
         "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "c64-mfma+f64" if prec else "f64",
-        "requests": K, "offered_rate_per_s": K / span, "makespan_s": makespan,
+        "requests": K, "reserved_shape": {"L": Lr, "chi_max": chir} if reserve else None,
+        "offered_rate_per_s": K / span, "makespan_s": makespan,
         "offered_traj_steps_per_s": steps / span, "achieved_traj_steps_per_s": steps / makespan,
         "mean_queue_s": float(np.mean([r["queue_s"] for _, r in reps])),
         "mean_run_s": float(np.mean([r["run_s"] for _, r in reps])),
@@ -396,6 +406,8 @@ def main():
     ap.add_argument("--fp64-traj", type=int, default=512, help="trajectory ids of the FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy kernel used to calibrate the traffic counters")
+    ap.add_argument("--no-reserve", action="store_true",
+                    help="serving: no pool shape reserved for the stream's largest request")
     ap.add_argument("--serving", type=int, default=0, metavar="K",
                     help="instead: latency of the first K requests of the serving stream")
     ap.add_argument("--tune", action="store_true",
@@ -417,7 +429,7 @@ def main():
         return
 
     if args.serving > 0:
-        print(json.dumps(serving(tjm, models, args.serving, args.precision)), flush=True)
+        print(json.dumps(serving(tjm, models, args.serving, args.precision, not args.no_reserve)), flush=True)
         return
 
     w = dict(WORKLOADS[args.workload])

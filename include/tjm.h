@@ -344,7 +344,8 @@ void tjm_destroy(tjm_model *m);
  *
  * Device memory: each admitted job holds its own buffers (tables, MPSs,
  * outputs); the workgroups' scratch is a pool per queue, shaped for the
- * largest chain and bond dimension it serves.  A job larger than the
+ * largest chain and bond dimension it serves (and at least the shape
+ * given to tjm_server_reserve, budget permitting).  A job larger than the
  * current pool of its precision waits until that queue has drained; a new
  * queue then opens with a pool shaped for every waiting job of that
  * precision that fits the budget.  Admission is first come, first served:
@@ -406,6 +407,23 @@ tjm_status tjm_server_create(tjm_server **out, int device, size_t hbm_budget_byt
  * destroyed.
  */
 tjm_status tjm_submit(tjm_server *s, const tjm_model *m, const tjm_run_args *args, uint64_t *job);
+
+/*
+ * Shape hint for the scratch pools: every pool of args->opt's precision
+ * that opens from now on is shaped to serve at least a job of this model
+ * and these arguments (its chain length and its per-workgroup scratch),
+ * where the budget allows it at the time the pool opens; otherwise the pool
+ * is shaped as if no hint had been given.  Serving a stream whose largest
+ * request shape is known, this spares the drain and reshape that a larger
+ * request arriving after a smaller one would otherwise cost.  Several calls
+ * combine (the largest of each).  Nothing is allocated or queued.  The
+ * resident kernel's LDS grows with the pool's chain length, so a reserved
+ * chain longer than the jobs need can lower the workgroups resident per
+ * compute unit (on gfx950: two up to 198 sites, one beyond).  Errors:
+ * those of tjm_submit's validation, and TJM_E_NOMEM if the shape alone (a
+ * job's buffers and its pool) exceeds the budget.
+ */
+tjm_status tjm_server_reserve(tjm_server *s, const tjm_model *m, const tjm_run_args *args);
 
 /* *done = 1 if the job has finished (successfully or not), else 0.
  * TJM_E_INVAL for an unknown or already collected job. */

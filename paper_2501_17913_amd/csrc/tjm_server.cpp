@@ -132,6 +132,8 @@ struct tjm_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::vector<Pool*> pools[2];         // FP64, mixed: queues, the newest last
+  long floor_stride[2] = {0, 0};       // tjm_server_reserve: least pool shape per precision
+  int floor_L[2] = {0, 0};
   // finished jobs whose buffers await release: freeing device memory waits
   // for the whole device, so it happens only while no resident kernel runs
   // (the bytes stay counted in active_bytes until then)
@@ -335,6 +337,13 @@ static bool admit_front(tjm_server* s, std::unique_lock<std::mutex>& lk) {
       if (s->active_bytes + j->bytes + pool_bytes_for(s, q, ws, wl) > s->budget) break;
       stride = ws;
       Lp = wl;
+    }
+    // the reserved shape too, where the budget allows it
+    const long fs = std::max(stride, s->floor_stride[q]);
+    const int fl = std::max(Lp, s->floor_L[q]);
+    if (s->active_bytes + j->bytes + pool_bytes_for(s, q, fs, fl) <= s->budget) {
+      stride = fs;
+      Lp = fl;
     }
   }
   const size_t extra = fits ? 0 : pool_bytes_for(s, q, stride, Lp);
@@ -617,6 +626,36 @@ extern "C" tjm_status tjm_submit(tjm_server* s, const tjm_model* m, const tjm_ru
     *job = j->id;
   }
   s->wake.notify_all();
+  return TJM_OK;
+}
+
+extern "C" tjm_status tjm_server_reserve(tjm_server* s, const tjm_model* m, const tjm_run_args* a) {
+  if (!s || !m || !a) return sfail(TJM_E_INVAL, "NULL argument");
+  if (a->n_obs < 0 || (a->n_obs > 0 && (!a->obs_site || !a->obs_op)))
+    return sfail(TJM_E_INVAL, "bad observables");
+  tjm_model* c = tjm_model_copy(m);
+  if (!c) return sfail(TJM_E_NOMEM, "host allocation failed");
+  tjm_options opt;
+  tjm_default_options(&opt);
+  if (a->opt) opt = *a->opt;
+  opt.device = s->device;
+  opt.workers = 0;
+  long stride = 0;
+  size_t bytes = 0;
+  const tjm_status st = tjm_pool_plan(c, a->n_traj, a->dt, a->T, a->chi_max, a->n_obs, a->obs_site, a->obs_op,
+                                      &opt, &stride, &bytes);
+  const int L = tjm_model_L(c);
+  std::string msg = st != TJM_OK ? tjm_last_error(c) : "";
+  tjm_destroy(c);
+  if (st != TJM_OK) return sfail(st, msg);
+  const int q = opt.precision == TJM_PREC_MIXED ? 1 : 0;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (bytes + pool_bytes_for(s, q, std::max(stride, s->floor_stride[q]), std::max(L, s->floor_L[q])) > s->budget)
+      return sfail(TJM_E_NOMEM, "the reserved shape needs more device memory than the server's budget");
+    s->floor_stride[q] = std::max(stride, s->floor_stride[q]);
+    s->floor_L[q] = std::max(L, s->floor_L[q]);
+  }
   return TJM_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTED = [
     "tjm_last_error",
     "tjm_destroy", "tjm_selftest_cgemm", "tjm_selftest_qr", "tjm_selftest_svd", "tjm_svd_noalloc",
     "tjm_selftest_expm", "tjm_selftest_philox", "tjm_selftest_copy",
-    "tjm_server_create", "tjm_submit", "tjm_poll", "tjm_job_progress", "tjm_wait", "tjm_server_last_error",
+    "tjm_server_create", "tjm_submit", "tjm_server_reserve", "tjm_poll", "tjm_job_progress", "tjm_wait", "tjm_server_last_error",
     "tjm_server_destroy",
 ]
 
@@ -153,6 +153,8 @@ lib.tjm_server_create.argtypes = [C.POINTER(_vp), C.c_int, C.c_size_t]
 lib.tjm_server_create.restype = C.c_int
 lib.tjm_submit.argtypes = [_vp, _vp, C.POINTER(RunArgs), C.POINTER(C.c_uint64)]
 lib.tjm_submit.restype = C.c_int
+lib.tjm_server_reserve.argtypes = [_vp, _vp, C.POINTER(RunArgs)]
+lib.tjm_server_reserve.restype = C.c_int
 lib.tjm_poll.argtypes = [_vp, C.c_uint64, _ip]
 lib.tjm_poll.restype = C.c_int
 lib.tjm_job_progress.argtypes = [_vp, C.c_uint64, _ip, C.POINTER(C.c_ulonglong)]
@@ -362,18 +364,31 @@ class Server:
         if st != OK:
             raise TjmError(st, lib.tjm_server_last_error().decode())
 
-    def submit(self, model, n_traj, dt, T, chi_max, observables, seed, options=None):
-        """Queues one run of `model`; returns the job id."""
+    @staticmethod
+    def _args(n_traj, dt, T, chi_max, observables, seed, options):
         sites, ops = Model._obs(observables)
         opsd = ops.view(np.float64)
         a = RunArgs(n_traj=n_traj, dt=dt, T=T, chi_max=chi_max, n_obs=len(observables),
                     obs_site=_iptr(sites), obs_op=opsd.ctypes.data_as(_dp), seed=seed,
                     opt=C.pointer(options) if options is not None else None)
+        return a, (sites, opsd)          # the arrays must outlive the call
+
+    def submit(self, model, n_traj, dt, T, chi_max, observables, seed, options=None):
+        """Queues one run of `model`; returns the job id."""
+        a, keep = self._args(n_traj, dt, T, chi_max, observables, seed, options)
         job = C.c_uint64()
         self._sc(lib.tjm_submit(self.h, model.h, C.byref(a), C.byref(job)))
+        del keep
         n = max(int(round(T / dt)), 0) if dt > 0 and T > 0 else 0
         self._jobs[job.value] = (n, len(observables) + model.n_mpo_obs)
         return job.value
+
+    def reserve(self, model, n_traj, dt, T, chi_max, observables, options=None):
+        """tjm_server_reserve: pools of the options' precision that open from
+        now on serve at least a job of this shape, budget permitting."""
+        a, keep = self._args(n_traj, dt, T, chi_max, observables, 0, options)
+        self._sc(lib.tjm_server_reserve(self.h, model.h, C.byref(a)))
+        del keep
 
     def poll(self, job):
         done = C.c_int()

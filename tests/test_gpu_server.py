@@ -194,3 +194,40 @@ def test_server_admits_trajectories_of_new_jobs_while_others_run():
         assert r["report"]["end_s"] < lrep["report"]["end_s"]
         assert np.array_equal(r["mean"], _direct(job)["mean"])
     assert np.array_equal(lrep["mean"], _direct(long_job)["mean"])
+
+
+def test_server_reserve_shapes_the_first_pool():
+    # a larger job arriving while a smaller one runs would wait for the
+    # smaller one's queue to drain; with the larger shape reserved, the first
+    # pool already serves it and it starts at once, in the same kernel
+    first = (24, 32, 1500, 6, 0.5, 0.1, tjm.PREC_MIXED, inputs.SEED + 94)
+    larger = (40, 32, 32, 2, 0.6, 0.05, tjm.PREC_MIXED, inputs.SEED + 95)
+    opt = tjm.default_options(precision=tjm.PREC_MIXED)
+    srv = tjm.Server(0)
+    hint = _model(40, 0.6, 0.05)
+    with pytest.raises(tjm.TjmError) as e:      # validated as a submission is
+        srv.reserve(hint, 32, 0.1, 0.25, 32, models.zx_observables(40), opt)
+    assert e.value.status == tjm.E_INVAL
+    srv.reserve(hint, 32, 0.1, 0.2, 32, models.zx_observables(40), opt)
+    hint.close()
+    a = _submit_all(srv, [first])[0]
+    import time
+    time.sleep(0.2)
+    b = _submit_all(srv, [larger])[0]
+    rb = srv.wait(b)
+    ra = srv.wait(a)
+    srv.close()
+    log("reserved: first start %.3f end %.3f, larger start %.3f end %.3f" % (
+        ra["report"]["start_s"], ra["report"]["end_s"], rb["report"]["start_s"], rb["report"]["end_s"]))
+    assert rb["report"]["pool_bytes"] == ra["report"]["pool_bytes"]
+    assert rb["report"]["start_s"] < ra["report"]["end_s"]
+    assert rb["report"]["queue_s"] < 1.0
+    assert np.array_equal(rb["mean"], _direct(larger)["mean"])
+    # a reserved shape beyond the whole budget is refused
+    srv = tjm.Server(0, 1 << 20)
+    m = _model(40, 0.6, 0.05)
+    with pytest.raises(tjm.TjmError) as e:
+        srv.reserve(m, 32, 0.1, 0.2, 32, models.zx_observables(40), opt)
+    assert e.value.status == tjm.E_NOMEM
+    m.close()
+    srv.close()
