@@ -94,14 +94,15 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
       if (threadIdx.x == 0)                // progress of the job, read by the host
         __hip_atomic_fetch_add(&S.steps[w.job], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    __syncthreads();                     // every thread's writes of the trajectory are issued
+    // every thread's writes of the trajectory reach device scope before the
+    // count: a fence orders only its own wavefront's stores, and the barrier
+    // alone keeps them within the workgroup
+    __threadfence();
+    __syncthreads();
     // the workgroup that finishes a job's last trajectory reduces the job
     // (mean, standard error, statistics) into the host's buffers, so that
     // finishing a job needs no further device work
-    if (threadIdx.x == 0) {
-      __threadfence();
-      tjm_lds.pick = atomicAdd(&S.count[w.job], 1);
-    }
+    if (threadIdx.x == 0) tjm_lds.pick = atomicAdd(&S.count[w.job], 1);
     __syncthreads();
     if (tjm_lds.pick == P.n_traj - 1) {
       __threadfence();
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(TJM_NT, 2) void tjm_serve_kernel(ServeDev S) {
           for (int q = 0; q < P.n_traj; ++q) s += P.tflags[q] != 0;
         P.serve_stats[i] = s;
       }
+      __threadfence_system();            // each thread's results, before the done flag
     }
     __syncthreads();
     if (threadIdx.x == 0) {
