@@ -36,10 +36,9 @@ struct Run {
   int* d_flags = nullptr;
   int record_bonds = 0;
 
-  // server jobs: no fill kernels (the serve kernel clears what it needs) and
-  // uploads from pinned staging buffers, which the runtime copies with the
-  // DMA engines; a staged copy from pageable memory runs as a kernel on the
-  // stream's hardware queue, which may be the one a resident kernel holds
+  // server jobs: no fill kernels (the serve kernel clears what it needs),
+  // and uploads from pinned staging buffers on the server's upload stream,
+  // which the job borrows; both leave the device to the resident kernel
   bool no_fill = false;
   bool own_stream = true;                    // false: the server's upload stream, borrowed
   std::vector<void*> host_allocs;            // pinned staging, freed with the run
