@@ -215,6 +215,9 @@ def test_server_calls_reject_null_arguments():
     done = C.c_int()
     assert tjm.lib.tjm_poll(None, 1, C.byref(done)) == tjm.E_INVAL
     assert tjm.lib.tjm_wait(None, 1, None, None, None) == tjm.E_INVAL
+    assert tjm.lib.tjm_server_reserve(None, None, None) == tjm.E_INVAL
+    traj, steps = C.c_int(), C.c_ulonglong()
+    assert tjm.lib.tjm_job_progress(None, 1, C.byref(traj), C.byref(steps)) == tjm.E_INVAL
     tjm.lib.tjm_server_destroy(None)
     h = C.c_void_p()
     assert tjm.lib.tjm_server_create(C.byref(h), -1, 0) in (tjm.E_INVAL, tjm.E_DEVICE)
