@@ -39,7 +39,7 @@ def _one_domain_wall(args):
 
 
 def workers(n_tasks, cap=16):
-    """Worker count: at most `cap` (the CPU share of one GPU machine) and the host's cores."""
+    """Worker count: at most `cap` (the host cores one GPU is given) and the host's cores."""
     return max(1, min(n_tasks, cap, os.cpu_count() or 1))
 
 
