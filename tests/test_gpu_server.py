@@ -158,10 +158,12 @@ def test_server_rejects_bad_jobs_and_reports_failures():
 
 
 def test_server_admits_trajectories_of_new_jobs_while_others_run():
-    # continuous batching: a long job fills the resident work queue; jobs of
-    # other chain lengths and bond dimensions that arrive while it runs start
-    # before it ends and share its kernel; each equals its own direct run
-    long_job = (24, 32, 1500, 6, 0.5, 0.1, tjm.PREC_MIXED, inputs.SEED + 91)
+    # continuous batching: a long job runs in the resident kernel (fewer
+    # trajectories than its workgroups, many steps each); jobs of other chain
+    # lengths and bond dimensions that arrive while it runs take the idle
+    # workgroups of the same kernel and finish long before it; each equals
+    # its own direct run
+    long_job = (24, 32, 300, 24, 0.5, 0.1, tjm.PREC_MIXED, inputs.SEED + 91)
     short_jobs = [(7, 8, 48, 4, 0.4, 0.1, tjm.PREC_MIXED, inputs.SEED + 92),
                   (16, 16, 96, 3, 0.6, 0.05, tjm.PREC_MIXED, inputs.SEED + 93)]
     srv = tjm.Server(0)
